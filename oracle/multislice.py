@@ -1,0 +1,299 @@
+"""FP64 CPU oracle for the multislice forward model, its loss and its gradient.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+module; only tests, the smoke check and the benchmark's CPU-baseline leg do.
+It shares no code with the HIP path (the two only share the seeded input
+generator, which holds none of this arithmetic).
+
+Everything is plain NumPy in float64 / complex128, with a loop over scan
+positions and arrays over probe modes, written in the order of the paper's
+equations:
+
+* forward model, Eq. (1)-(4) of Sec. "Physical model": sub-pixel Fourier shift
+  of each probe mode, integer crop of the object patch, transmission through
+  every slice with the tilted Fresnel propagator of Eq. (4) between slices,
+  far-field intensity summed incoherently over modes (Eq. 2);
+* the Gaussian and Poisson losses of Eq. (5)-(6), Sec. "Optimizers and loss
+  functions";
+* the gradient of the loss with respect to the six optimisable parameters of
+  Sec. "AD-optimizable parameters" (object amplitude, object phase, probe,
+  position, local tilt, slice spacing), obtained by the chain rule through the
+  same steps in reverse.  Complex gradients follow the convention
+  dL/dRe + i dL/dIm.
+
+Conventions (readings where the paper is silent):
+* F is the orthonormal 2-D DFT with the e^{-2 pi i} sign; F^-1 uses e^{+2 pi i}.
+* q = fftfreq(N) in cycles/pixel, k = q/dx in 1/angstrom; axis 0 is y, axis 1
+  is x; positions and tilts are given as (y, x) pairs.
+* the patch for position rho has top-left corner round_half_even(rho) - N/2;
+  the probe is shifted by dr = rho - round(rho) with the ramp
+  exp(-2 pi i (q_y dr_y + q_x dr_x)).
+* S slices use S-1 propagations; the far field is F of the last transmitted
+  wave; intensities are returned fftshifted (zero frequency at (N/2, N/2)).
+* loss averages run over all B*N*N values of the batch; singular points
+  (I = 0 with p < 1, zero Gaussian residual) give a zero gradient.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+POISSON_EPS = 1e-6   # epsilon inside the Poisson log, Eq. (6)
+
+
+# ---------------------------------------------------------------- transforms
+def fft2(x):
+    """Orthonormal forward 2-D DFT over the last two axes."""
+    return np.fft.fft2(x, norm="ortho")
+
+
+def ifft2(x):
+    """Orthonormal inverse 2-D DFT over the last two axes."""
+    return np.fft.ifft2(x, norm="ortho")
+
+
+def kgrid(N, dx):
+    """Spatial frequencies (k_y column, k_x row) in 1/angstrom."""
+    k = np.fft.fftfreq(N) / dx
+    return k[:, None], k[None, :]
+
+
+# ---------------------------------------------------------------- pieces
+def split_position(rho, N):
+    """Integer crop corner and sub-pixel remainder for one (y, x) position
+    (Sec. "Physical model": dr = rho - round(rho), the patch centred on rho)."""
+    r = np.round(np.asarray(rho, np.float64))      # round half to even
+    dr = np.asarray(rho, np.float64) - r
+    t = r.astype(np.int64) - N // 2
+    return t, dr
+
+
+def shift_ramp(dr, N):
+    """Fourier shift ramp R(u,v) = exp(-2 pi i (q_u dr_y + q_v dr_x)); applying
+    F^-1[R F[P]] moves the probe by +dr pixels."""
+    q = np.fft.fftfreq(N)
+    return np.exp(-2j * np.pi * (q[:, None] * dr[0] + q[None, :] * dr[1]))
+
+
+def propagator_phase(N, dx, lam, dz, tilt):
+    """Phase of the adaptive propagator, Eq. (4):
+    -pi lam |k|^2 dz + 2 pi dz (k_x tan theta_x + k_y tan theta_y)."""
+    ky, kx = kgrid(N, dx)
+    return (-np.pi * lam * dz * (kx ** 2 + ky ** 2)
+            + 2 * np.pi * dz * (kx * np.tan(tilt[1]) + ky * np.tan(tilt[0])))
+
+
+def propagator(N, dx, lam, dz, tilt):
+    """Adaptive Fresnel propagator with local tilt, Eq. (4)."""
+    return np.exp(1j * propagator_phase(N, dx, lam, dz, tilt))
+
+
+def transmission(amp, phase):
+    """Complex object from the two real arrays: O = a exp(i phi)."""
+    return amp * np.exp(1j * phase)
+
+
+def crop(arr, t, N):
+    return arr[..., t[0]:t[0] + N, t[1]:t[1] + N]
+
+
+def check_bounds(pos, N, H, W):
+    for rho in np.asarray(pos):
+        t, _ = split_position(rho, N)
+        if t[0] < 0 or t[1] < 0 or t[0] + N > H or t[1] + N > W:
+            raise ValueError(f"patch for position {rho} leaves the {H}x{W} object")
+
+
+# ---------------------------------------------------------------- forward
+@dataclass
+class ForwardTrace:
+    """Per-position intermediates kept for the gradient."""
+    t: np.ndarray          # (2,) int crop corner
+    dr: np.ndarray         # (2,) sub-pixel shift
+    R: np.ndarray          # (N,N) shift ramp
+    H: np.ndarray          # (N,N) propagator
+    phi: list              # S arrays (M,N,N): wave incident on slice s
+    chi: list              # S arrays (M,N,N): wave leaving slice s
+    Psi: np.ndarray        # (M,N,N) far-field waves
+
+
+def forward_one(O, Phat, rho, tilt, dz, dx, lam):
+    """Multislice exit wave and far-field intensity for one scan position,
+    Eq. (2)-(4).  O: (S,H,W) complex object; Phat: (M,N,N) probe spectra."""
+    S = O.shape[0]
+    N = Phat.shape[-1]
+    t, dr = split_position(rho, N)
+    R = shift_ramp(dr, N)
+    Hp = propagator(N, dx, lam, dz, tilt)
+    phi = ifft2(Phat * R)                      # shifted probe modes P_j^(m)
+    phis, chis = [], []
+    for s in range(S):
+        phis.append(phi)
+        chi = crop(O[s], t, N) * phi           # transmit through slice s
+        chis.append(chi)
+        if s < S - 1:
+            phi = ifft2(Hp * fft2(chi))        # propagate to slice s+1
+    Psi = fft2(chis[-1])
+    I = np.sum(np.abs(Psi) ** 2, axis=0)       # incoherent sum over modes
+    return I, ForwardTrace(t, dr, R, Hp, phis, chis, Psi)
+
+
+def forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=False):
+    """Model intensities for a batch of positions, fftshifted, (B,N,N) float64.
+
+    amp, phase: (S,H,W); probe: (M,N,N) complex; pos, tilt: (B,2) (y,x);
+    dz, dx in angstrom; lam in angstrom."""
+    amp = np.asarray(amp, np.float64)
+    phase = np.asarray(phase, np.float64)
+    probe = np.asarray(probe, np.complex128)
+    N = probe.shape[-1]
+    check_bounds(pos, N, amp.shape[1], amp.shape[2])
+    O = transmission(amp, phase)
+    Phat = fft2(probe)
+    out, traces = [], []
+    for j in range(len(pos)):
+        I, tr = forward_one(O, Phat, pos[j], tilt[j], dz, dx, lam)
+        out.append(np.fft.fftshift(I))
+        traces.append(tr)
+    out = np.stack(out)
+    return (out, traces) if return_trace else out
+
+
+def exit_waves(amp, phase, probe, rho, tilt, dz, dx, lam):
+    """Exit waves chi_{S-1} (M,N,N) for one position (used by invariance tests)."""
+    O = transmission(np.asarray(amp, np.float64), np.asarray(phase, np.float64))
+    _, tr = forward_one(O, fft2(np.asarray(probe, np.complex128)), rho, tilt, dz, dx, lam)
+    return tr.chi[-1]
+
+
+# ---------------------------------------------------------------- loss
+def loss(I_model, I_meas, kind="gaussian", p=None, eps=POISSON_EPS):
+    """Loss of Eq. (5) (kind='gaussian', default p=0.5) or Eq. (6)
+    (kind='poisson', default p=1), averaged over detector and batch.
+    Returns (L, dL/dI_model) with the gradient in the layout of I_model."""
+    I = np.asarray(I_model, np.float64)
+    Im = np.asarray(I_meas, np.float64)
+    if p is None:
+        p = 0.5 if kind == "gaussian" else 1.0
+    K = I.size
+    A = I ** p
+    E = Im ** p
+    Z = E.mean()
+    if Z <= 0:
+        raise ValueError("mean of the measured patterns is zero")
+    if kind == "gaussian":
+        D = np.mean((A - E) ** 2)
+        L = np.sqrt(D) / Z
+        dA = (A - E) / (K * np.sqrt(D) * Z) if D > 0 else np.zeros_like(A)
+    elif kind == "poisson":
+        L = -np.mean(E * np.log(A + eps) - A) / Z
+        dA = -(E / (A + eps) - 1.0) / (K * Z)
+    else:
+        raise ValueError(kind)
+    if p == 1.0:
+        dI = dA
+    else:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            dI = np.where(I > 0, dA * p * I ** (p - 1.0), 0.0)
+    return float(L), dI
+
+
+# ---------------------------------------------------------------- gradient
+@dataclass
+class Gradients:
+    amp: np.ndarray      # (S,H,W)
+    phase: np.ndarray    # (S,H,W)
+    probe: np.ndarray    # (M,N,N) complex, dL/dRe + i dL/dIm
+    pos: np.ndarray      # (B,2)  dL/d(rho_y, rho_x)
+    tilt: np.ndarray     # (B,2)  dL/d(theta_y, theta_x)
+    dz: float
+    loss: float
+
+
+def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian",
+              p=None):
+    """Loss and its gradient w.r.t. all six parameters for one batch.
+
+    The chain rule is taken through the forward steps in reverse:
+    far field -> last slice -> (slice s: object, then propagator) -> shift ->
+    probe spectrum.  With L real and y = A x linear, dL/dx = A^H dL/dy; with
+    y = c * x elementwise, dL/dx = conj(c) dL/dy and dL/dc = conj(x) dL/dy."""
+    amp = np.asarray(amp, np.float64)
+    phase = np.asarray(phase, np.float64)
+    probe = np.asarray(probe, np.complex128)
+    S, Hh, Ww = amp.shape
+    M, N, _ = probe.shape
+    I_model, traces = forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=True)
+    L, dI = loss(I_model, I_meas, kind, p)
+    O = transmission(amp, phase)
+    Phat = fft2(probe)
+    ky, kx = kgrid(N, dx)
+    q = np.fft.fftfreq(N)
+    G_O = np.zeros_like(O)
+    G_Phat = np.zeros_like(Phat)
+    g_pos = np.zeros((len(pos), 2))
+    g_tilt = np.zeros((len(pos), 2))
+    g_dz = 0.0
+    for j, tr in enumerate(traces):
+        gI = np.fft.ifftshift(dI[j])                       # back to DC-at-0 layout
+        G_Psi = 2.0 * gI * tr.Psi                           # I = sum_m |Psi_m|^2
+        G_chi = ifft2(G_Psi)                                # Psi = F chi_{S-1}
+        G_H = np.zeros((N, N), np.complex128)
+        for s in range(S - 1, -1, -1):
+            Oj = crop(O[s], tr.t, N)
+            crop(G_O[s], tr.t, N)[...] += np.sum(np.conj(tr.phi[s]) * G_chi, axis=0)
+            G_phi = np.conj(Oj) * G_chi                     # chi_s = O_s phi_s
+            if s > 0:                                        # phi_s = F^-1 H F chi_{s-1}
+                X = fft2(tr.chi[s - 1])
+                G_hat = fft2(G_phi)
+                G_H += np.sum(np.conj(X) * G_hat, axis=0)
+                G_chi = ifft2(np.conj(tr.H) * G_hat)
+        # shift: phi_0 = F^-1 [Phat R]
+        G_hat0 = fft2(G_phi)
+        G_Phat += np.conj(tr.R)[None] * G_hat0
+        G_R = np.sum(np.conj(Phat) * G_hat0, axis=0)
+        dR_dy = -2j * np.pi * q[:, None] * tr.R
+        dR_dx = -2j * np.pi * q[None, :] * tr.R
+        g_pos[j, 0] = np.sum(np.real(np.conj(G_R) * dR_dy))
+        g_pos[j, 1] = np.sum(np.real(np.conj(G_R) * dR_dx))
+        # propagator H = exp(i Phi(dz, theta)): dH/dt = i dPhi/dt H
+        ty, tx = np.tan(tilt[j][0]), np.tan(tilt[j][1])
+        dPhi_ddz = -np.pi * lam * (kx ** 2 + ky ** 2) + 2 * np.pi * (kx * tx + ky * ty)
+        dPhi_dty = 2 * np.pi * dz * ky / np.cos(tilt[j][0]) ** 2
+        dPhi_dtx = 2 * np.pi * dz * kx / np.cos(tilt[j][1]) ** 2
+        w = np.conj(G_H) * 1j * tr.H
+        g_dz += np.sum(np.real(w * dPhi_ddz))
+        g_tilt[j, 0] = np.sum(np.real(w * dPhi_dty))
+        g_tilt[j, 1] = np.sum(np.real(w * dPhi_dtx))
+    G_probe = ifft2(G_Phat)                                 # Phat = F P
+    g_amp = np.real(np.conj(G_O) * np.exp(1j * phase))      # O = a e^{i phi}
+    g_phase = np.imag(G_O * np.conj(O))
+    return Gradients(g_amp, g_phase, G_probe, g_pos, g_tilt, float(g_dz), L)
+
+
+def loss_of(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian", p=None):
+    """Scalar loss of the forward model (for finite differences)."""
+    I = forward(amp, phase, probe, pos, tilt, dz, dx, lam)
+    return loss(I, I_meas, kind, p)[0]
+
+
+def scatter_patches(patches, ts, S, H, W):
+    """Sum of (B,S,N,N) complex patches into an (S,H,W) array at crop corners
+    ts (B,2): the adjoint of cropping."""
+    out = np.zeros((S, H, W), np.complex128)
+    N = patches.shape[-1]
+    for b in range(len(ts)):
+        out[:, ts[b][0]:ts[b][0] + N, ts[b][1]:ts[b][1] + N] += patches[b]
+    return out
+
+
+def count_parameters(S, H, W, M, N, n_pos, n_obj_modes=1, tilt="none"):
+    """Number of real optimisable values: object amplitude + phase per slice,
+    complex probe modes, (y, x) per position, and tilts (Sec. "AD-optimizable
+    parameters")."""
+    obj = 2 * n_obj_modes * S * H * W
+    prb = 2 * M * N * N
+    ps = 2 * n_pos
+    tl = {"none": 0, "global": 2, "local": 2 * n_pos}[tilt]
+    return obj, prb, ps, tl
