@@ -1,0 +1,196 @@
+/*
+ * ptyr.h - C ABI of libptyr, a gfx950 (MI355X) library for the hot path of
+ * gradient-based multislice electron ptychography as described in the PtyRAD
+ * paper (arXiv 2505.07814): the batched mixed-state multislice forward model,
+ * its loss, its gradient with respect to all six optimisable parameters, and
+ * an Adam step.
+ *
+ * What is computed (paper, Sec. "Physical model", Eq. 1-4; Sec. "Optimizers
+ * and loss functions", Eq. 5-6; Sec. "AD-optimizable parameters"):
+ *
+ *   for every scan position j of a batch and every probe mode m
+ *     r_j  = round_half_even(rho_j),  dr_j = rho_j - r_j,  t_j = r_j - N/2
+ *     phi_0 = F^-1[ F[P_m] * exp(-2 pi i (q_y dr_y + q_x dr_x)) ]
+ *     for s = 0 .. S-1:
+ *        chi_s = O_s[t_j + (0..N-1)] * phi_s,        O_s = a_s exp(i phase_s)
+ *        phi_{s+1} = F^-1[ H_j * F[chi_s] ]           (s < S-1)
+ *     H_j(k) = exp(-i pi lambda |k|^2 dz + 2 pi i dz (k_x tan th_x + k_y tan th_y))
+ *   I_j = fftshift( sum_m |F[chi_{S-1}]|^2 )
+ *
+ *   F is the orthonormal 2-D DFT (sign -1); q = fftfreq(N); k = q / dx.
+ *   Axis 0 of every 2-D array is y; positions and tilts are (y, x) pairs;
+ *   positions are in object pixels.  S slices use S-1 propagations.
+ *
+ * Memory conventions (all entry points):
+ *  - Every array argument is a caller-owned, contiguous, row-major DEVICE
+ *    pointer unless marked "host".  Complex values are interleaved (re, im)
+ *    float32.  The library never allocates or frees caller memory: its scratch
+ *    is the caller-provided workspace of ptyr_workspace_bytes() bytes.
+ *  - All calls enqueue work on the context's HIP stream (a hipStream_t passed
+ *    as void*) and return without synchronising.  Scalars computed on the
+ *    device (loss) are written to device memory.
+ *  - Gradient outputs ACCUMULATE (+=); the caller zeroes them.  Repeated calls
+ *    on sub-batches therefore sum their gradients (gradient accumulation).
+ *    Complex gradients follow dL/dRe + i dL/dIm.
+ *
+ * Errors: argument validation runs on the host before any launch and returns
+ * a status without launching.  Positions live on the device, so a patch that
+ * leaves the object is detected by the kernels, which then skip that position
+ * (no out-of-bounds access) and raise PTYR_E_BOUNDS in a device flag that
+ * ptyr_sync() reports.  Nothing aborts.
+ */
+#ifndef PTYR_H
+#define PTYR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PTYR_OK = 0,
+    PTYR_E_ARG = 1,          /* bad size, null pointer, unsupported N, B > B_max, zero data mean */
+    PTYR_E_BOUNDS = 2,       /* a patch leaves the object */
+    PTYR_E_NOMEM = 3,        /* workspace smaller than ptyr_workspace_bytes() */
+    PTYR_E_DEVICE = 4,       /* a HIP call failed */
+    PTYR_E_NONFINITE = 5     /* NaN/Inf met with PTYR_CHECK_FINITE set */
+} ptyr_status;
+
+enum { PTYR_LOSS_GAUSSIAN = 0, PTYR_LOSS_POISSON = 1 };
+
+/* geometry flags */
+#define PTYR_GLOBAL_TILT   0x1u  /* one (th_y, th_x) pair for all positions; its gradient is summed */
+#define PTYR_CHECK_FINITE  0x2u  /* flag NaN/Inf in the loss sums as PTYR_E_NONFINITE */
+
+/* adjoint flags */
+#define PTYR_REUSE_FORWARD 0x1u  /* reuse the waves and intensities stored by the
+                                    last ptyr_forward on this context (same inputs) */
+
+typedef struct {
+    int N;                    /* probe window / detector size: 64, 128 or 256 */
+    int M;                    /* probe modes, >= 1 */
+    int S;                    /* object slices, >= 1 */
+    int H, W;                 /* object size in pixels, >= N */
+    int B_max;                /* largest batch the context serves */
+    double dx;                /* real-space pixel size, angstrom */
+    double lambda;            /* electron wavelength, angstrom */
+    int loss_kind;            /* PTYR_LOSS_GAUSSIAN (Eq. 5) or PTYR_LOSS_POISSON (Eq. 6) */
+    double loss_p;            /* power p on both intensities (paper defaults 0.5 / 1) */
+    size_t wave_budget_bytes; /* bytes of workspace the forward may keep per batch for
+                                 the gradient; less than all S waves -> per-slice
+                                 recomputation from checkpoints */
+    unsigned flags;           /* PTYR_GLOBAL_TILT | PTYR_CHECK_FINITE */
+    int n_scan;               /* scan positions ptyr_step may address (sizes its dense
+                                 position / tilt gradients); 0 if ptyr_step is unused */
+} ptyr_geom;
+
+/* Parameters of one reconstruction and their Adam moments (all device). */
+typedef struct {
+    float *amp, *phase;       /* S x H x W */
+    float *probe;             /* M x N x N complex */
+    float *pos;               /* n_pos x 2 (y, x) */
+    float *tilt;              /* n_pos x 2, or 2 with PTYR_GLOBAL_TILT */
+    float *dz;                /* 1 */
+    float *m_amp, *v_amp, *m_phase, *v_phase, *m_probe, *v_probe;
+    float *m_pos, *v_pos, *m_tilt, *v_tilt, *m_dz, *v_dz;
+    int n_pos;                /* scan positions of the whole data set */
+    int64_t step;             /* Adam updates taken so far; ptyr_step increments it */
+} ptyr_params;
+
+/* Per-parameter learning rates (0 freezes a parameter: its values and its
+ * moments are left untouched, which realises an onset iteration on the host)
+ * and the Adam constants. */
+typedef struct {
+    float amp, phase, probe, pos, tilt, dz;
+    float beta1, beta2, eps;  /* 0.9, 0.999, 1e-8 reproduce PyTorch's defaults */
+} ptyr_lr;
+
+typedef struct ptyr_ctx ptyr_ctx;
+
+/* Human-readable text for a status. */
+const char* ptyr_status_str(ptyr_status s);
+
+/* Pure host: validate a geometry (N in {64,128,256}, M,S,B_max >= 1,
+ * H,W >= N, dx, lambda > 0, loss kind and p). */
+ptyr_status ptyr_check_geom(const ptyr_geom* g);
+
+/* Pure host: validate a batch size and, when pos_host is not NULL, that every
+ * patch of the B host positions (B x 2, (y, x)) lies inside the object.
+ * Rounding follows the kernels: round half to even, corner = round - N/2. */
+ptyr_status ptyr_check_args(const ptyr_geom* g, int B, const float* pos_host);
+
+/* Pure host: bytes of device workspace a context for g needs. */
+size_t ptyr_workspace_bytes(const ptyr_geom* g);
+
+/* Pure host: how the forward keeps waves for the gradient under
+ * g->wave_budget_bytes: *stride = checkpoint spacing in slices (1 = every
+ * slice kept, S+1 = none kept, waves recomputed from the probe). */
+ptyr_status ptyr_checkpoint_plan(const ptyr_geom* g, int* stride);
+
+/* Bind a context to a workspace (device, caller-owned, >= ptyr_workspace_bytes)
+ * and a stream (hipStream_t as void*; NULL = the default stream).  The
+ * context stores pointers only. */
+ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes,
+                        void* stream, ptyr_ctx** out);
+void ptyr_destroy(ptyr_ctx* ctx);
+
+/* Wait for the context's stream and report the first asynchronous error:
+ * PTYR_E_BOUNDS / PTYR_E_NONFINITE raised by kernels since the last call, or
+ * PTYR_E_DEVICE.  Clears the device flags. */
+ptyr_status ptyr_sync(ptyr_ctx* ctx);
+
+/* Forward model, Eq. 1-4 (a_s, phase_s: S x H x W; probe: M x N x N complex;
+ * pos: rows x 2; tilt: rows x 2 or 2 (global); dz: 1 float).  Writes the
+ * fftshifted intensities I_out (B x N x N).  idx (nullable, B device ints)
+ * selects rows idx[b] (0 <= idx[b] < n_rows) of pos/tilt for batch row b;
+ * with idx NULL, row b is used and n_rows is ignored.  A row index outside
+ * [0, n_rows) is skipped by the kernels and reported by ptyr_sync as
+ * PTYR_E_ARG.  Keeps waves for a following ptyr_adjoint(PTYR_REUSE_FORWARD)
+ * within wave_budget_bytes. */
+ptyr_status ptyr_forward(ptyr_ctx* ctx, const float* amp, const float* phase,
+                         const float* probe, const float* pos, const float* tilt,
+                         const float* dz, const int* idx, int n_rows, int B,
+                         float* I_out);
+
+/* Loss of Eq. 5 (Gaussian) or Eq. 6 (Poisson, eps = 1e-6) between fftshifted
+ * model and measured intensities (B x N x N each), averaged over detector and
+ * batch.  Writes the loss to loss_dev (1 double, overwritten) and, if dLdI is
+ * not NULL, dL/dI_model (B x N x N, overwritten).  meas_idx (nullable, B
+ * device ints) selects measured pattern meas_idx[b] of the n_meas patterns in
+ * I_meas for batch row b. */
+ptyr_status ptyr_loss(ptyr_ctx* ctx, const float* I_model, const float* I_meas,
+                      const int* meas_idx, int n_meas, int B, double* loss_dev,
+                      float* dLdI);
+
+/* Loss and its gradient with respect to object amplitude and phase, probe,
+ * positions, tilts and dz (chain rule through Eq. 1-6).  Runs the forward
+ * itself unless flags has PTYR_REUSE_FORWARD.  idx (nullable, B device ints in
+ * [0, n_rows)) selects rows of pos/tilt/I_meas and the rows of g_pos/g_tilt
+ * that receive the gradient; the rows of one batch must be distinct.
+ * Gradients accumulate (+=): g_amp, g_phase S x H x W; g_probe M x N x N
+ * complex; g_pos, g_tilt like pos, tilt; g_dz 1.  Any gradient pointer may be
+ * NULL to skip it.  loss_dev (nullable) receives the batch loss. */
+ptyr_status ptyr_adjoint(ptyr_ctx* ctx, const float* amp, const float* phase,
+                         const float* probe, const float* pos, const float* tilt,
+                         const float* dz, const int* idx, int n_rows, int B,
+                         const float* I_meas, float* g_amp, float* g_phase,
+                         float* g_probe, float* g_pos, float* g_tilt, float* g_dz,
+                         double* loss_dev, unsigned flags);
+
+/* One mini-batch update (Sec. "Optimizers and loss functions": Adam by
+ * default, per-parameter learning rates): gradient of the batch idx (B
+ * distinct device ints into the p->n_pos <= g->n_scan positions / patterns of
+ * I_meas_all, n_pos x N x N), then a dense Adam update of every parameter
+ * whose rate is non-zero (entries outside the batch see a zero gradient, as
+ * in PyTorch), and p->step += 1.  loss_dev (nullable) receives the batch
+ * loss.  Row indices outside [0, n_pos) are skipped and reported by
+ * ptyr_sync as PTYR_E_ARG. */
+ptyr_status ptyr_step(ptyr_ctx* ctx, ptyr_params* p, const int* idx, int B,
+                      const float* I_meas_all, const ptyr_lr* lr, double* loss_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTYR_H */

@@ -79,6 +79,7 @@ def shift_ramp(dr, N):
 def propagator_phase(N, dx, lam, dz, tilt):
     """Phase of the adaptive propagator, Eq. (4):
     -pi lam |k|^2 dz + 2 pi dz (k_x tan theta_x + k_y tan theta_y)."""
+    dx, lam, dz, tilt = float(dx), float(lam), float(dz), np.asarray(tilt, np.float64)
     ky, kx = kgrid(N, dx)
     return (-np.pi * lam * dz * (kx ** 2 + ky ** 2)
             + 2 * np.pi * dz * (kx * np.tan(tilt[1]) + ky * np.tan(tilt[0])))
@@ -123,6 +124,8 @@ def forward_one(O, Phat, rho, tilt, dz, dx, lam):
     Eq. (2)-(4).  O: (S,H,W) complex object; Phat: (M,N,N) probe spectra."""
     S = O.shape[0]
     N = Phat.shape[-1]
+    dz, dx, lam = float(dz), float(dx), float(lam)
+    tilt = np.asarray(tilt, np.float64)
     t, dr = split_position(rho, N)
     R = shift_ramp(dr, N)
     Hp = propagator(N, dx, lam, dz, tilt)
@@ -147,6 +150,8 @@ def forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=False):
     amp = np.asarray(amp, np.float64)
     phase = np.asarray(phase, np.float64)
     probe = np.asarray(probe, np.complex128)
+    pos = np.asarray(pos, np.float64)
+    tilt = np.asarray(tilt, np.float64)
     N = probe.shape[-1]
     check_bounds(pos, N, amp.shape[1], amp.shape[2])
     O = transmission(amp, phase)
@@ -222,6 +227,9 @@ def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian"
     amp = np.asarray(amp, np.float64)
     phase = np.asarray(phase, np.float64)
     probe = np.asarray(probe, np.complex128)
+    pos = np.asarray(pos, np.float64)
+    tilt = np.asarray(tilt, np.float64)
+    dz, dx, lam = float(dz), float(dx), float(lam)   # every scalar in float64
     S, Hh, Ww = amp.shape
     M, N, _ = probe.shape
     I_model, traces = forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=True)

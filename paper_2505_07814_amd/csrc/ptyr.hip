@@ -1,0 +1,676 @@
+// ptyr.hip - libptyr: C ABI (include/ptyr.h), host validation and the
+// element-wise / reduction kernels around the fused wave kernels.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/ptyr.h"
+#include "kernels.hpp"
+
+using namespace ptyr;
+
+namespace {
+
+constexpr int NPART = 512;         // loss partial-sum blocks
+constexpr double POISSON_EPS = 1e-6;
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_zero(float* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+// O = a exp(i phase) for the whole object (accurate sincos)
+__global__ void k_transmission(const float* amp, const float* phase, float2* Oc, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float s, c;
+        sincosf(phase[i], &s, &c);
+        float a = amp[i];
+        Oc[i] = make_float2(a * c, a * s);
+    }
+}
+
+// crop corner (round half to even) and sub-pixel shift of every batch row
+__global__ void k_positions(const float* pos, const int* idx, int n_rows, int B, int N, int H, int W,
+                            PosInfo* out, int* err) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= B) return;
+    PosInfo pi;
+    pi.ty = -1; pi.tx = -1; pi.dry = 0.f; pi.drx = 0.f; pi.row = 0;
+    pi.pad[0] = pi.pad[1] = pi.pad[2] = 0;
+    int row = idx ? idx[j] : j;
+    if (row < 0 || row >= n_rows) {
+        atomicOr(err, ERR_INDEX);
+        out[j] = pi;
+        return;
+    }
+    float py = pos[2 * row], px = pos[2 * row + 1];
+    bool ok = isfinite(py) && isfinite(px);
+    if (ok) {
+        float ry = rintf(py), rx = rintf(px);
+        float half = (float)(N / 2);
+        ok = ry - half >= 0.f && rx - half >= 0.f && ry + half <= (float)H && rx + half <= (float)W;
+        if (ok) {
+            pi.ty = (int)ry - N / 2;
+            pi.tx = (int)rx - N / 2;
+            pi.dry = py - ry;
+            pi.drx = px - rx;
+            pi.row = row;
+        }
+    }
+    if (!ok) atomicOr(err, ERR_BOUNDS);
+    out[j] = pi;
+}
+
+// I[j] = sum_m Imode[j][m]  (fixed order)
+__global__ void k_modesum(const float* Imode, float* I, int B, int M, int NN) {
+    size_t n = (size_t)B * NN;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        size_t j = e / NN, p = e % NN;
+        const float* src = Imode + j * M * NN + p;
+        float s = 0.f;
+        for (int m = 0; m < M; ++m) s += src[(size_t)m * NN];
+        I[e] = s;
+    }
+}
+
+__device__ __forceinline__ double powp(double v, double p) {
+    if (p == 1.0) return v;
+    if (p == 0.5) return sqrt(v);
+    return pow(v, p);
+}
+
+// pass 1 of the loss: per-block sums of E = I_meas^p and of the residual term
+__global__ void k_loss_partial(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int NN,
+                               int kind, double p, double* part, int* err) {
+    __shared__ double sh[3 * 256];
+    double sE = 0.0, sR = 0.0, bad = 0.0;
+    size_t n = (size_t)B * NN;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        size_t j = e / NN, q = e % NN;
+        long row = midx ? (long)midx[j] : (long)j;
+        if (row < 0 || row >= n_meas) {
+            if (q == 0) atomicOr(err, ERR_INDEX);
+            continue;
+        }
+        double I = Im[e], Em = Ie[(size_t)row * NN + q];
+        if (!isfinite(I) || !isfinite(Em)) { bad += 1.0; continue; }
+        double A = powp(fmax(I, 0.0), p), E = powp(fmax(Em, 0.0), p);
+        sE += E;
+        if (kind == PTYR_LOSS_GAUSSIAN) sR += (A - E) * (A - E);
+        else sR += E * log(A + POISSON_EPS) - A;
+    }
+    sh[threadIdx.x] = sE; sh[256 + threadIdx.x] = sR; sh[512 + threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = sh[k * 256];
+}
+
+// pass 2: fixed-order total, loss and the gradient scale
+//   Gaussian: L = sqrt(D)/Z, dL/dA = (A-E) / (K sqrt(D) Z)
+//   Poisson : L = -mean(E log(A+eps) - A)/Z, dL/dA = -(E/(A+eps) - 1)/(K Z)
+__global__ void k_loss_final(const double* part, int nblk, double K, int kind, int check, double* scal,
+                             double* loss_out, int* err) {
+    __shared__ double sh[3 * 256];
+    double s[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+        for (int k = 0; k < 3; ++k) s[k] += part[3 * b + k];
+    for (int k = 0; k < 3; ++k) sh[k * 256 + threadIdx.x] = s[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double sE = sh[0], sR = sh[256], bad = sh[512];
+        double Z = sE / K, L, c;
+        if (!(Z > 0.0)) {
+            atomicOr(err, ERR_ZERO_MEAN);
+            L = 0.0; c = 0.0;
+        } else if (kind == PTYR_LOSS_GAUSSIAN) {
+            double D = sR / K;
+            L = sqrt(D) / Z;
+            c = D > 0.0 ? 1.0 / (K * sqrt(D) * Z) : 0.0;
+        } else {
+            L = -(sR / K) / Z;
+            c = 1.0 / (K * Z);
+        }
+        if (check && (bad > 0.0 || !isfinite(L))) atomicOr(err, ERR_NONFINITE);
+        scal[0] = L;
+        scal[1] = c;
+        if (loss_out) *loss_out = L;
+    }
+}
+
+// dL/dI per value (and w = 2 dL/dI for the gradient kernel)
+__global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int NN,
+                            int kind, double p, const double* scal, float* dLdI, float* w2) {
+    const double c = scal[1];
+    size_t n = (size_t)B * NN;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        size_t j = e / NN, q = e % NN;
+        long row = midx ? (long)midx[j] : (long)j;
+        if (row < 0 || row >= n_meas) {
+            if (dLdI) dLdI[e] = 0.f;
+            if (w2) w2[e] = 0.f;
+            continue;
+        }
+        double I = fmax((double)Im[e], 0.0), Em = fmax((double)Ie[(size_t)row * NN + q], 0.0);
+        double A = powp(I, p), E = powp(Em, p);
+        double dA = kind == PTYR_LOSS_GAUSSIAN ? (A - E) * c : -(E / (A + POISSON_EPS) - 1.0) * c;
+        double dI;
+        if (p == 1.0) dI = dA;
+        else dI = I > 0.0 ? dA * p * pow(I, p - 1.0) : 0.0;
+        if (dLdI) dLdI[e] = (float)dI;
+        if (w2) w2[e] = (float)(2.0 * dI);
+    }
+}
+
+// Object gradient: each workgroup owns a 32 x 32 tile of one slice and sums,
+// in batch order, the patch gradients of every (position, mode) covering it;
+// then applies the chain rule to amplitude and phase (O = a exp(i phase)):
+//   g_a += Re(conj(G) exp(i phase)),  g_phase += Im(G conj(O)).
+__global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int B, int M, int S,
+                                                        int N, int H, int W, const float* amp, const float* phase,
+                                                        float* g_amp, float* g_phase) {
+    const int ntx = (W + 31) / 32;
+    const int tile = blockIdx.x, s = blockIdx.y;
+    const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
+    const int ly = threadIdx.x / 8, lx = (threadIdx.x % 8) * 4;
+    const int y = y0 + ly;
+    float2 acc[4];
+    for (int k = 0; k < 4; ++k) acc[k] = make_float2(0.f, 0.f);
+    bool touched = false;
+    const size_t NN = (size_t)N * N;
+    for (int j = 0; j < B; ++j) {
+        PosInfo pi = pinfo[j];
+        if (pi.ty < 0) continue;
+        if (pi.ty >= y0 + 32 || pi.ty + N <= y0 || pi.tx >= x0 + 32 || pi.tx + N <= x0) continue;
+        touched = true;
+        int py = y - pi.ty;
+        if (py < 0 || py >= N) continue;
+        for (int m = 0; m < M; ++m) {
+            const float2* src = gO + ((size_t)(j * M + m) * S + s) * NN + (size_t)py * N;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int px = x0 + lx + k - pi.tx;
+                if (px >= 0 && px < N) acc[k] = cadd(acc[k], src[px]);
+            }
+        }
+    }
+    if (!touched || y >= H) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int x = x0 + lx + k;
+        if (x >= W) continue;
+        size_t o = ((size_t)s * H + y) * W + x;
+        float sn, cs;
+        sincosf(phase[o], &sn, &cs);
+        float a = amp[o];
+        float2 G = acc[k];
+        if (g_amp) g_amp[o] += G.x * cs + G.y * sn;          // Re(conj(G) e^{i phi})
+        if (g_phase) g_phase[o] += a * (G.y * cs - G.x * sn); // Im(G conj(a e^{i phi}))
+    }
+}
+
+// sum over batch rows of the probe-spectrum gradients (fixed order)
+__global__ void k_sum_rows(const float2* src, float2* dst, int B, int M, int NN) {
+    size_t n = (size_t)M * NN;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        float2 s = make_float2(0.f, 0.f);
+        for (int j = 0; j < B; ++j) s = cadd(s, src[(size_t)j * n + e]);
+        dst[e] = s;
+    }
+}
+
+// position, tilt and dz gradients from the per-(row, mode) partial sums
+//   g_rho   = 2 pi sum_m sum_k q Im(Phat R conj(G^_0))
+//   g_th    = 2 pi dz sec^2(th) sum_s,m,k k Im(G^ conj(Y))
+//   g_dz    = sum [-pi lam |k|^2 + 2 pi (k_x tan th_x + k_y tan th_y)] Im(G^ conj(Y))
+__global__ void k_param_grads(const float* part, const PosInfo* pinfo, int B, int M, const float* tilt,
+                              int global_tilt, const float* dzp, double lam, float* g_pos, float* g_tilt,
+                              float* g_dz) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double two_pi = 6.283185307179586;
+    const double dz = *dzp;
+    double gdz = 0.0, gty = 0.0, gtx = 0.0;
+    for (int j = 0; j < B; ++j) {
+        if (pinfo[j].ty < 0) continue;
+        int row = pinfo[j].row;
+        double k2 = 0, kx = 0, ky = 0, py = 0, px = 0;
+        for (int m = 0; m < M; ++m) {
+            const float* q = part + (size_t)(j * M + m) * 8;
+            k2 += q[0]; kx += q[1]; ky += q[2]; py += q[3]; px += q[4];
+        }
+        const float* th = global_tilt ? tilt : tilt + 2 * row;
+        double ty = tan((double)th[0]), tx = tan((double)th[1]);
+        double cy = cos((double)th[0]), cx = cos((double)th[1]);
+        gdz += -3.141592653589793 * lam * k2 + two_pi * (tx * kx + ty * ky);
+        double gy = two_pi * dz * ky / (cy * cy), gx = two_pi * dz * kx / (cx * cx);
+        if (global_tilt) { gty += gy; gtx += gx; }
+        else if (g_tilt) { g_tilt[2 * row] += (float)gy; g_tilt[2 * row + 1] += (float)gx; }
+        if (g_pos) { g_pos[2 * row] += (float)(two_pi * py); g_pos[2 * row + 1] += (float)(two_pi * px); }
+    }
+    if (global_tilt && g_tilt) { g_tilt[0] += (float)gty; g_tilt[1] += (float)gtx; }
+    if (g_dz) g_dz[0] += (float)gdz;
+}
+
+// Adam (PyTorch's form): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+// p -= (lr / bc1) * m / (sqrt(v) / sqrt(bc2) + eps)
+__global__ void k_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2s) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float gi = g[i];
+        float mi = b1 * m[i] + (1.f - b1) * gi;
+        float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        float denom = sqrtf(vi) / bc2s + eps;
+        p[i] -= (lr / bc1) * mi / denom;
+    }
+}
+
+// ------------------------------------------------------------------ host helpers
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, err, store, gO, gPhat, gPsum, part, gamp, gphase,
+        gprobe, gdz, gpos, gtilt, total;
+    int ckK, nck;
+};
+
+int checkpoint_stride(const ptyr_geom* g) {
+    size_t per = (size_t)g->B_max * g->M * g->N * g->N * sizeof(float2);
+    if (per == 0) return g->S + 1;
+    size_t fit = g->wave_budget_bytes / per;     // waves per chain that fit
+    if (fit >= (size_t)g->S) return 1;
+    if (fit == 0) return g->S + 1;
+    // keep ceil(S / K) waves per chain
+    int K = (int)((g->S + fit - 1) / fit);
+    while ((size_t)((g->S + K - 1) / K) > fit) ++K;
+    return K;
+}
+
+Layout make_layout(const ptyr_geom* g) {
+    Layout L;
+    const size_t NN = (size_t)g->N * g->N, HW = (size_t)g->H * g->W, B = g->B_max, M = g->M, S = g->S;
+    L.ckK = checkpoint_stride(g);
+    L.nck = L.ckK <= g->S ? (g->S + L.ckK - 1) / L.ckK : 0;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    L.Oc = take(S * HW * sizeof(float2));
+    L.Phat = take(M * NN * sizeof(float2));
+    L.pinfo = take(B * sizeof(PosInfo));
+    L.Imode = take(B * M * NN * sizeof(float));
+    L.Ibuf = take(B * NN * sizeof(float));
+    L.wbuf = take(B * NN * sizeof(float));
+    L.lpart = take(3 * NPART * sizeof(double));
+    L.scal = take(8 * sizeof(double));
+    L.err = take(sizeof(int));
+    L.store = take(B * M * (size_t)L.nck * NN * sizeof(float2));
+    L.gO = take(B * M * S * NN * sizeof(float2));
+    L.gPhat = take(B * M * NN * sizeof(float2));
+    L.gPsum = take(M * NN * sizeof(float2));
+    L.part = take(B * M * 8 * sizeof(float));
+    L.gamp = take(S * HW * sizeof(float));
+    L.gphase = take(S * HW * sizeof(float));
+    L.gprobe = take(M * NN * sizeof(float2));
+    L.gdz = take(sizeof(float));
+    L.gpos = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
+    L.gtilt = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
+    L.total = o;
+    return L;
+}
+
+int grid_for(size_t n, int block = 256, int cap = 8192) {
+    size_t g = (n + block - 1) / block;
+    return (int)std::max<size_t>(1, std::min<size_t>(g, cap));
+}
+
+}  // namespace
+
+struct ptyr_ctx {
+    ptyr_geom g;
+    char* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    Layout L;
+    int fwd_valid;   // waves / intensities of the last forward are in the workspace
+    int fwd_B;
+};
+
+template <typename T> static T* at(ptyr_ctx* c, size_t off) { return reinterpret_cast<T*>(c->ws + off); }
+
+extern "C" {
+
+const char* ptyr_status_str(ptyr_status s) {
+    switch (s) {
+        case PTYR_OK: return "ok";
+        case PTYR_E_ARG: return "invalid argument";
+        case PTYR_E_BOUNDS: return "a probe patch leaves the object";
+        case PTYR_E_NOMEM: return "workspace too small";
+        case PTYR_E_DEVICE: return "HIP device error";
+        case PTYR_E_NONFINITE: return "non-finite value in the loss inputs";
+    }
+    return "unknown status";
+}
+
+ptyr_status ptyr_check_geom(const ptyr_geom* g) {
+    if (!g) return PTYR_E_ARG;
+    if (g->N != 64 && g->N != 128) return PTYR_E_ARG;   // N = 256 path: HBM passes (not in this build)
+    if (g->M < 1 || g->S < 1 || g->B_max < 1) return PTYR_E_ARG;
+    if (g->H < g->N || g->W < g->N) return PTYR_E_ARG;
+    if (!(g->dx > 0.0) || !(g->lambda > 0.0)) return PTYR_E_ARG;
+    if (g->loss_kind != PTYR_LOSS_GAUSSIAN && g->loss_kind != PTYR_LOSS_POISSON) return PTYR_E_ARG;
+    if (!(g->loss_p > 0.0) || !isfinite(g->loss_p)) return PTYR_E_ARG;
+    if (g->flags & ~(PTYR_GLOBAL_TILT | PTYR_CHECK_FINITE)) return PTYR_E_ARG;
+    // grid and index limits of the kernels
+    if ((double)g->B_max * g->M > 2147483647.0 / 2) return PTYR_E_ARG;
+    if (g->n_scan < 0) return PTYR_E_ARG;
+    return PTYR_OK;
+}
+
+ptyr_status ptyr_check_args(const ptyr_geom* g, int B, const float* pos_host) {
+    ptyr_status st = ptyr_check_geom(g);
+    if (st != PTYR_OK) return st;
+    if (B < 1 || B > g->B_max) return PTYR_E_ARG;
+    if (pos_host) {
+        for (int j = 0; j < B; ++j) {
+            float py = pos_host[2 * j], px = pos_host[2 * j + 1];
+            if (!isfinite(py) || !isfinite(px)) return PTYR_E_BOUNDS;
+            float ry = rintf(py), rx = rintf(px), half = (float)(g->N / 2);
+            if (ry - half < 0.f || rx - half < 0.f || ry + half > (float)g->H || rx + half > (float)g->W)
+                return PTYR_E_BOUNDS;
+        }
+    }
+    return PTYR_OK;
+}
+
+size_t ptyr_workspace_bytes(const ptyr_geom* g) {
+    if (ptyr_check_geom(g) != PTYR_OK) return 0;
+    return make_layout(g).total;
+}
+
+ptyr_status ptyr_checkpoint_plan(const ptyr_geom* g, int* stride) {
+    ptyr_status st = ptyr_check_geom(g);
+    if (st != PTYR_OK) return st;
+    if (!stride) return PTYR_E_ARG;
+    *stride = checkpoint_stride(g);
+    return PTYR_OK;
+}
+
+ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, void* stream, ptyr_ctx** out) {
+    ptyr_status st = ptyr_check_geom(g);
+    if (st != PTYR_OK) return st;
+    if (!out || !workspace) return PTYR_E_ARG;
+    Layout L = make_layout(g);
+    if (ws_bytes < L.total) return PTYR_E_NOMEM;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return PTYR_E_ARG;
+    ptyr_ctx* c = new (std::nothrow) ptyr_ctx;
+    if (!c) return PTYR_E_NOMEM;
+    c->g = *g;
+    c->ws = static_cast<char*>(workspace);
+    c->ws_bytes = ws_bytes;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->L = L;
+    c->fwd_valid = 0;
+    c->fwd_B = 0;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, c->stream, at<float>(c, L.err), (size_t)1);
+    if (hipGetLastError() != hipSuccess) { delete c; return PTYR_E_DEVICE; }
+    *out = c;
+    return PTYR_OK;
+}
+
+void ptyr_destroy(ptyr_ctx* ctx) { delete ctx; }
+
+ptyr_status ptyr_sync(ptyr_ctx* ctx) {
+    if (!ctx) return PTYR_E_ARG;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return PTYR_E_DEVICE;
+    int e = 0;
+    if (hipMemcpy(&e, at<int>(ctx, ctx->L.err), sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return PTYR_E_DEVICE;
+    if (e) {
+        int z = 0;
+        if (hipMemcpy(at<int>(ctx, ctx->L.err), &z, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            return PTYR_E_DEVICE;
+    }
+    if (e & ERR_BOUNDS) return PTYR_E_BOUNDS;
+    if (e & ERR_NONFINITE) return PTYR_E_NONFINITE;
+    if (e & (ERR_ZERO_MEAN | ERR_INDEX)) return PTYR_E_ARG;
+    return PTYR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+WaveArgs wave_args(ptyr_ctx* c, const float* tilt, const float* dz, int B) {
+    const ptyr_geom& g = c->g;
+    WaveArgs a;
+    a.Oc = at<float2>(c, c->L.Oc);
+    a.Phat = at<float2>(c, c->L.Phat);
+    a.pinfo = at<PosInfo>(c, c->L.pinfo);
+    a.tilt = tilt;
+    a.dz = dz;
+    a.store = c->L.nck ? at<float2>(c, c->L.store) : nullptr;
+    a.ckK = c->L.ckK;
+    a.nck = c->L.nck;
+    a.B = B; a.M = g.M; a.S = g.S; a.H = g.H; a.W = g.W;
+    a.dx = g.dx;
+    a.lam = g.lambda;
+    a.global_tilt = (g.flags & PTYR_GLOBAL_TILT) ? 1 : 0;
+    a.Imode = at<float>(c, c->L.Imode);
+    a.wgt = at<float>(c, c->L.wbuf);
+    a.gO = at<float2>(c, c->L.gO);
+    a.gPhat = at<float2>(c, c->L.gPhat);
+    a.part = at<float>(c, c->L.part);
+    return a;
+}
+
+template <int N> void launch_forward(ptyr_ctx* c, const WaveArgs& a, int B) {
+    hipLaunchKernelGGL(k_forward<N>, dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
+}
+template <int N> void launch_gradient(ptyr_ctx* c, const WaveArgs& a, int B) {
+    hipLaunchKernelGGL(k_gradient<N>, dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
+}
+template <int N> void launch_probe_fft(ptyr_ctx* c, const float* probe) {
+    hipLaunchKernelGGL((k_fft2<N, -1, false>), dim3(c->g.M), dim3(N * N / 16), 0, c->stream,
+                       reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat));
+}
+template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe) {
+    hipLaunchKernelGGL((k_fft2<N, +1, true>), dim3(c->g.M), dim3(N * N / 16), 0, c->stream,
+                       at<float2>(c, c->L.gPsum), reinterpret_cast<float2*>(g_probe));
+}
+
+ptyr_status run_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
+                        const float* tilt, const float* dz, const int* idx, int n_rows, int B) {
+    const ptyr_geom& g = c->g;
+    size_t nobj = (size_t)g.S * g.H * g.W;
+    hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, c->stream, amp, phase,
+                       at<float2>(c, c->L.Oc), nobj);
+    hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, c->stream, pos, idx, idx ? n_rows : B, B,
+                       g.N, g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err));
+    WaveArgs a = wave_args(c, tilt, dz, B);
+    if (g.N == 64) { launch_probe_fft<64>(c, probe); launch_forward<64>(c, a, B); }
+    else { launch_probe_fft<128>(c, probe); launch_forward<128>(c, a, B); }
+    size_t NN = (size_t)g.N * g.N;
+    hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)B * NN)), dim3(256), 0, c->stream,
+                       at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, (int)NN);
+    if (hipGetLastError() != hipSuccess) return PTYR_E_DEVICE;
+    c->fwd_valid = 1;
+    c->fwd_B = B;
+    return PTYR_OK;
+}
+
+ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* midx, int n_meas, int B,
+                     double* loss_dev, float* dLdI, float* w2) {
+    const ptyr_geom& g = c->g;
+    int NN = g.N * g.N;
+    size_t n = (size_t)B * NN;
+    int nblk = std::min(NPART, grid_for(n));
+    const int nm = midx ? n_meas : B;
+    hipLaunchKernelGGL(k_loss_partial, dim3(nblk), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, g.loss_kind,
+                       g.loss_p, at<double>(c, c->L.lpart), at<int>(c, c->L.err));
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, c->stream, at<double>(c, c->L.lpart), nblk, (double)n,
+                       g.loss_kind, (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
+                       at<int>(c, c->L.err));
+    if (dLdI || w2)
+        hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN,
+                           g.loss_kind, g.loss_p, at<double>(c, c->L.scal), dLdI, w2);
+    return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
+}
+
+ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
+                        const float* tilt, const float* dz, const int* idx, int n_rows, int B,
+                        const float* I_meas, float* g_amp, float* g_phase, float* g_probe, float* g_pos,
+                        float* g_tilt, float* g_dz, double* loss_dev, unsigned flags) {
+    const ptyr_geom& g = c->g;
+    ptyr_status st;
+    if (!(flags & PTYR_REUSE_FORWARD) || !c->fwd_valid || c->fwd_B != B) {
+        st = run_forward(c, amp, phase, probe, pos, tilt, dz, idx, n_rows, B);
+        if (st != PTYR_OK) return st;
+    } else {
+        size_t NN = (size_t)g.N * g.N;
+        hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)B * NN)), dim3(256), 0, c->stream,
+                           at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, (int)NN);
+    }
+    st = run_loss(c, at<float>(c, c->L.Ibuf), I_meas, idx, n_rows, B, loss_dev, nullptr, at<float>(c, c->L.wbuf));
+    if (st != PTYR_OK) return st;
+    WaveArgs a = wave_args(c, tilt, dz, B);
+    if (g.N == 64) launch_gradient<64>(c, a, B);
+    else launch_gradient<128>(c, a, B);
+    if (g_amp || g_phase) {
+        int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
+        hipLaunchKernelGGL(k_scatter_object, dim3(ntiles, g.S), dim3(256), 0, c->stream, at<float2>(c, c->L.gO),
+                           at<PosInfo>(c, c->L.pinfo), B, g.M, g.S, g.N, g.H, g.W, amp, phase, g_amp, g_phase);
+    }
+    if (g_probe) {
+        int NN = g.N * g.N;
+        hipLaunchKernelGGL(k_sum_rows, dim3(grid_for((size_t)g.M * NN)), dim3(256), 0, c->stream,
+                           at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B, g.M, NN);
+        if (g.N == 64) launch_probe_ifft_acc<64>(c, g_probe);
+        else launch_probe_ifft_acc<128>(c, g_probe);
+    }
+    if (g_pos || g_tilt || g_dz)
+        hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(64), 0, c->stream, at<float>(c, c->L.part),
+                           at<PosInfo>(c, c->L.pinfo), B, g.M, tilt, a.global_tilt, dz, g.lambda, g_pos, g_tilt,
+                           g_dz);
+    return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
+}
+
+void zero(ptyr_ctx* c, float* p, size_t n) {
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(256), 0, c->stream, p, n);
+}
+
+void adam(ptyr_ctx* c, float* p, const float* g, float* m, float* v, size_t n, float lr, const ptyr_lr* h,
+          int64_t t) {
+    if (lr == 0.f || n == 0) return;
+    double bc1 = 1.0 - pow((double)h->beta1, (double)t);
+    double bc2 = 1.0 - pow((double)h->beta2, (double)t);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, c->stream, p, g, m, v, n, lr, h->beta1, h->beta2,
+                       h->eps, (float)bc1, (float)sqrt(bc2));
+}
+
+}  // namespace
+
+extern "C" {
+
+ptyr_status ptyr_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
+                         const float* tilt, const float* dz, const int* idx, int n_rows, int B, float* I_out) {
+    if (!c) return PTYR_E_ARG;
+    ptyr_status st = ptyr_check_args(&c->g, B, nullptr);
+    if (st != PTYR_OK) return st;
+    if (!amp || !phase || !probe || !pos || !tilt || !dz || !I_out) return PTYR_E_ARG;
+    if (idx && n_rows < 1) return PTYR_E_ARG;
+    st = run_forward(c, amp, phase, probe, pos, tilt, dz, idx, n_rows, B);
+    if (st != PTYR_OK) return st;
+    size_t n = (size_t)B * c->g.N * c->g.N;
+    if (hipMemcpyAsync(I_out, at<float>(c, c->L.Ibuf), n * sizeof(float), hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+        return PTYR_E_DEVICE;
+    return PTYR_OK;
+}
+
+ptyr_status ptyr_loss(ptyr_ctx* c, const float* I_model, const float* I_meas, const int* meas_idx, int n_meas,
+                      int B, double* loss_dev, float* dLdI) {
+    if (!c) return PTYR_E_ARG;
+    ptyr_status st = ptyr_check_args(&c->g, B, nullptr);
+    if (st != PTYR_OK) return st;
+    if (!I_model || !I_meas || !loss_dev) return PTYR_E_ARG;
+    if (meas_idx && n_meas < 1) return PTYR_E_ARG;
+    return run_loss(c, I_model, I_meas, meas_idx, n_meas, B, loss_dev, dLdI, nullptr);
+}
+
+ptyr_status ptyr_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
+                         const float* tilt, const float* dz, const int* idx, int n_rows, int B,
+                         const float* I_meas, float* g_amp, float* g_phase, float* g_probe, float* g_pos,
+                         float* g_tilt, float* g_dz, double* loss_dev, unsigned flags) {
+    if (!c) return PTYR_E_ARG;
+    ptyr_status st = ptyr_check_args(&c->g, B, nullptr);
+    if (st != PTYR_OK) return st;
+    if (!amp || !phase || !probe || !pos || !tilt || !dz || !I_meas) return PTYR_E_ARG;
+    if (flags & ~PTYR_REUSE_FORWARD) return PTYR_E_ARG;
+    if (idx && n_rows < 1) return PTYR_E_ARG;
+    return run_adjoint(c, amp, phase, probe, pos, tilt, dz, idx, n_rows, B, I_meas, g_amp, g_phase, g_probe, g_pos,
+                       g_tilt, g_dz, loss_dev, flags);
+}
+
+ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const float* I_meas_all,
+                      const ptyr_lr* lr, double* loss_dev) {
+    if (!c || !p || !lr || !idx || !I_meas_all) return PTYR_E_ARG;
+    ptyr_status st = ptyr_check_args(&c->g, B, nullptr);
+    if (st != PTYR_OK) return st;
+    if (!p->amp || !p->phase || !p->probe || !p->pos || !p->tilt || !p->dz) return PTYR_E_ARG;
+    if (p->n_pos < B || p->n_pos > c->g.n_scan) return PTYR_E_ARG;
+    const float rates[6] = {lr->amp, lr->phase, lr->probe, lr->pos, lr->tilt, lr->dz};
+    float* const mv[6][2] = {{p->m_amp, p->v_amp}, {p->m_phase, p->v_phase}, {p->m_probe, p->v_probe},
+                             {p->m_pos, p->v_pos}, {p->m_tilt, p->v_tilt}, {p->m_dz, p->v_dz}};
+    for (int k = 0; k < 6; ++k) {
+        if (!(rates[k] >= 0.f) || !isfinite(rates[k])) return PTYR_E_ARG;
+        if (rates[k] > 0.f && (!mv[k][0] || !mv[k][1])) return PTYR_E_ARG;
+    }
+    if (!(lr->beta1 >= 0.f && lr->beta1 < 1.f && lr->beta2 >= 0.f && lr->beta2 < 1.f && lr->eps >= 0.f))
+        return PTYR_E_ARG;
+    const ptyr_geom& g = c->g;
+    const bool gt = (g.flags & PTYR_GLOBAL_TILT) != 0;
+    const size_t nobj = (size_t)g.S * g.H * g.W, nprb = (size_t)g.M * g.N * g.N * 2;
+    const size_t npos = (size_t)p->n_pos * 2, ntilt = gt ? 2 : npos;
+    float* gamp = at<float>(c, c->L.gamp);
+    float* gphase = at<float>(c, c->L.gphase);
+    float* gprobe = at<float>(c, c->L.gprobe);
+    float* gdz = at<float>(c, c->L.gdz);
+    float* gpos = at<float>(c, c->L.gpos);
+    float* gtilt = at<float>(c, c->L.gtilt);
+    zero(c, gamp, nobj);
+    zero(c, gphase, nobj);
+    zero(c, gprobe, nprb);
+    zero(c, gdz, 1);
+    zero(c, gpos, npos);
+    zero(c, gtilt, ntilt);
+    st = run_adjoint(c, p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz, idx, p->n_pos, B, I_meas_all,
+                     rates[0] > 0.f ? gamp : nullptr, rates[1] > 0.f ? gphase : nullptr,
+                     rates[2] > 0.f ? gprobe : nullptr, gpos, gtilt, gdz, loss_dev, 0);
+    if (st != PTYR_OK) return st;
+    const int64_t t = p->step + 1;
+    adam(c, p->amp, gamp, p->m_amp, p->v_amp, nobj, rates[0], lr, t);
+    adam(c, p->phase, gphase, p->m_phase, p->v_phase, nobj, rates[1], lr, t);
+    adam(c, p->probe, gprobe, p->m_probe, p->v_probe, nprb, rates[2], lr, t);
+    adam(c, p->pos, gpos, p->m_pos, p->v_pos, npos, rates[3], lr, t);
+    adam(c, p->tilt, gtilt, p->m_tilt, p->v_tilt, ntilt, rates[4], lr, t);
+    adam(c, p->dz, gdz, p->m_dz, p->v_dz, 1, rates[5], lr, t);
+    p->step = t;
+    return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
+}
+
+}  // extern "C"

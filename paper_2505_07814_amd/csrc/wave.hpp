@@ -1,0 +1,281 @@
+// wave.hpp - register-resident N x N complex wave for one workgroup (gfx950).
+//
+// A workgroup of T = N*N/16 threads holds one N x N complex64 field, 16
+// values per thread.  The field is seen as N "lines" (rows or columns); a
+// line is owned by L = N/16 consecutive lanes.  Two register layouts of a
+// line are used (c = lane within the line, r = register 0..15):
+//
+//   NAT : register r holds line element  n = c + L*r
+//   MID : register r = beta*L + a holds  n = (c + L*beta) + 16*a
+//
+// A length-N DFT along the lines is split as N = 16 * L:
+//   nat2mid: 16-point DFT in registers, twiddle W_N^{c b}, LDS exchange,
+//            L-point DFT in registers            (NAT in -> MID out)
+//   mid2nat: the same factors in reverse order   (MID in -> NAT out)
+// Either direction can carry either sign, so a line FFT, a pointwise
+// multiply in frequency and a line IFFT keep the field in place.  A
+// transpose (rows <-> columns) is one more LDS exchange.  LDS slots are
+// padded linear maps (slot = base(thread) + constant(register)), so every
+// access is one base register plus an immediate offset; the paddings make the
+// line exchanges bank-conflict free for each 32-lane half-wave and leave the
+// transpose reads at most 2-way conflicted.  Transforms are unnormalised;
+// callers fold the 1/N factors into their pointwise factors.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ptyr {
+
+// ------------------------------------------------------------ complex math
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float cabs2(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
+// multiply by SG*i  (SG = +1 or -1)
+template <int SG> __device__ __forceinline__ float2 mul_si(float2 a) {
+    return SG > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// Constant twiddles are applied with compensated ("double-float") constants:
+// c = c_hi + c_lo with c_hi the float nearest c.  A plain float constant such
+// as float(sqrt(1/2)) has |w| = 1 - 1.7e-8, and because the same constants
+// are hit on every pass of every slice that bias would add up linearly over
+// the slices; the compensated product keeps the error of each multiply
+// unbiased at the half-ulp level.
+struct KC {
+    float hi, lo;
+};
+constexpr KC kc(double v) { return KC{(float)v, (float)(v - (double)(float)v)}; }
+constexpr KC RSQ2 = kc(0.70710678118654752440);   // cos(pi/4)
+constexpr KC C8 = kc(0.92387953251128675613);     // cos(pi/8)
+constexpr KC S8 = kc(0.38268343236508977173);     // sin(pi/8)
+
+__device__ __forceinline__ float kmul(float x, KC c) { return fmaf(x, c.hi, x * c.lo); }
+// x * c + y * d with compensated constants
+__device__ __forceinline__ float kdot(float x, KC c, float y, KC d) {
+    return fmaf(x, c.hi, fmaf(y, d.hi, fmaf(x, c.lo, y * d.lo)));
+}
+// (x + i y) * (cr + i ci) for compensated constants; ncr / nci negate the parts
+template <bool NCR, bool NCI>
+__device__ __forceinline__ float2 kcmul(float2 a, KC cr, KC ci) {
+    KC r = NCR ? KC{-cr.hi, -cr.lo} : cr;
+    KC i = NCI ? KC{-ci.hi, -ci.lo} : ci;
+    KC mi = KC{-i.hi, -i.lo};
+    return make_float2(kdot(a.x, r, a.y, mi), kdot(a.x, i, a.y, r));
+}
+// multiply by exp(SG * 2 pi i m / 16) for the twiddles m the 16-point DFT uses
+template <int SG> __device__ __forceinline__ float2 tw16(float2 a, int m) {
+    constexpr bool NEG = SG < 0;
+    switch (m & 15) {
+        case 1: return kcmul<false, NEG>(a, C8, S8);            // ( c8,  s8)
+        case 2: return kcmul<false, NEG>(a, RSQ2, RSQ2);        // ( r,   r )
+        case 3: return kcmul<false, NEG>(a, S8, C8);            // ( s8,  c8)
+        case 4: return mul_si<SG>(a);                           // ( 0,   1 )
+        case 6: return kcmul<true, NEG>(a, RSQ2, RSQ2);         // (-r,   r )
+        case 9: return kcmul<true, !NEG>(a, C8, S8);            // (-c8, -s8)
+        default: return a;
+    }
+}
+
+// Round a unit complex number given in double to the float pair (one of the
+// four neighbouring roundings) whose modulus is closest to 1.  Table factors
+// applied on every slice (twiddles, propagator) would otherwise carry a
+// fixed per-entry modulus error that compounds over the slices.
+__device__ __forceinline__ float2 unit_round(double c, double s) {
+    float c0 = (float)c, s0 = (float)s;
+    float c1 = ((double)c0 > c) ? nextafterf(c0, -2.0f) : nextafterf(c0, 2.0f);
+    float s1 = ((double)s0 > s) ? nextafterf(s0, -2.0f) : nextafterf(s0, 2.0f);
+    float cs[2] = {c0, c1}, ss[2] = {s0, s1};
+    float2 best = make_float2(c0, s0);
+    double be = fabs((double)c0 * c0 + (double)s0 * s0 - 1.0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            double e = fabs((double)cs[i] * cs[i] + (double)ss[j] * ss[j] - 1.0);
+            if (e < be) { be = e; best = make_float2(cs[i], ss[j]); }
+        }
+    return best;
+}
+
+// ------------------------------------------------------------ small DFTs
+template <int SG> __device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d) {
+    float2 y0 = cadd(a, c), y1 = csub(a, c), y2 = cadd(b, d), y3 = mul_si<SG>(csub(b, d));
+    a = cadd(y0, y2);
+    c = csub(y0, y2);
+    b = cadd(y1, y3);
+    d = csub(y1, y3);
+}
+
+template <int SG> __device__ __forceinline__ void dft8(float2* x) {
+    float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+    float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+    dft4<SG>(e0, e1, e2, e3);
+    dft4<SG>(o0, o1, o2, o3);
+    // W8^1 = r (1 + SG i), W8^3 = r (-1 + SG i), r = sqrt(1/2)
+    o1 = make_float2(kmul(o1.x - SG * o1.y, RSQ2), kmul(SG * o1.x + o1.y, RSQ2));
+    o2 = mul_si<SG>(o2);
+    o3 = make_float2(kmul(-o3.x - SG * o3.y, RSQ2), kmul(SG * o3.x - o3.y, RSQ2));
+    x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
+    x[1] = cadd(e1, o1); x[5] = csub(e1, o1);
+    x[2] = cadd(e2, o2); x[6] = csub(e2, o2);
+    x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
+}
+
+// 16-point DFT in natural order, 4 x 4 split: X[k1 + 4 k2] =
+// sum_n2 W16^{n2 k1} W4^{n2 k2} sum_n1 x[4 n1 + n2] W4^{n1 k1}
+template <int SG> __device__ __forceinline__ void dft16(float2* x) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<SG>(x[n2], x[4 + n2], x[8 + n2], x[12 + n2]);
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+        for (int n2 = 1; n2 < 4; ++n2) x[4 * k1 + n2] = tw16<SG>(x[4 * k1 + n2], n2 * k1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<SG>(x[4 * k1], x[4 * k1 + 1], x[4 * k1 + 2], x[4 * k1 + 3]);
+    float2 t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = x[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = t[i];
+}
+
+template <int L, int SG> __device__ __forceinline__ void dftL(float2* x) {
+    if constexpr (L == 4) dft4<SG>(x[0], x[1], x[2], x[3]);
+    else dft8<SG>(x);
+}
+
+// ------------------------------------------------------------ layouts
+enum { ROW = 0, COL = 1 };
+enum { NAT = 0, MID = 1 };
+
+template <int N> struct WaveGeo {
+    static constexpr int L = N / 16;
+    static constexpr int T = N * N / 16;
+    static constexpr int G = 16 / L;
+    // LDS paddings (float2 slots): exchange element (line l, b, lane c) at
+    // l*SL + b*SB + c; field element (y, x) at y*SY + x.
+    static constexpr int SB = (N == 128) ? 9 : 5;
+    static constexpr int SL = (N == 128) ? 152 : 100;
+    static constexpr int SY = N + L;
+    static constexpr int LDS_SLOTS = (N - 1) * SL + 15 * SB + L;   // >= N*SY
+};
+
+// position along the line of register r
+template <int N, int K> __device__ __forceinline__ int line_pos(int c, int r) {
+    constexpr int L = N / 16;
+    if constexpr (K == NAT) return c + L * r;
+    else return (c + L * (r / L)) + 16 * (r % L);
+}
+
+// (y, x) of register r of thread (line l, lane c)
+template <int N, int D, int K> __device__ __forceinline__ void reg_yx(int l, int c, int r, int& y, int& x) {
+    int n = line_pos<N, K>(c, r);
+    if constexpr (D == ROW) { y = l; x = n; }
+    else { y = n; x = l; }
+}
+
+// LDS slot of exchange element (line l, b, lane c')
+template <int N> __device__ __forceinline__ int slot_x(int l, int b, int c) {
+    return l * WaveGeo<N>::SL + b * WaveGeo<N>::SB + c;
+}
+
+// LDS slot of field element (y, x) for a transpose
+template <int N> __device__ __forceinline__ int slot_t(int y, int x) { return y * WaveGeo<N>::SY + x; }
+
+// Table factors are kept as compensated pairs (hi, lo) in one float4:
+// w = (x + z) + i (y + w).  Their product with a value is unbiased at the
+// half-ulp level, so the fixed table entries applied on every pass of every
+// slice do not add up a systematic modulus error.
+__device__ __forceinline__ float4 unit_pair(double c, double s) {
+    float2 h = unit_round(c, s);
+    return make_float4(h.x, h.y, (float)(c - (double)h.x), (float)(s - (double)h.y));
+}
+// a * w  (CONJ: a * conj(w)) for a compensated table factor w
+template <bool CONJ> __device__ __forceinline__ float2 tmul(float2 a, float4 w) {
+    float wi = CONJ ? -w.y : w.y, li = CONJ ? -w.w : w.w;
+    return make_float2(fmaf(a.x, w.x, fmaf(-a.y, wi, fmaf(a.x, w.z, -a.y * li))),
+                       fmaf(a.x, wi, fmaf(a.y, w.x, fmaf(a.x, li, a.y * w.z))));
+}
+
+// ------------------------------------------------------------ line transforms
+// NAT -> MID, DFT of sign SG along every line.
+template <int N, int SG>
+__device__ __forceinline__ void nat2mid(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
+    constexpr int L = N / 16, G = 16 / L;
+    dft16<SG>(v);
+    const float4* twc = tw + c * 16;
+#pragma unroll
+    for (int b = 1; b < 16; ++b) v[b] = tmul<(SG > 0)>(v[b], twc[b]);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) lds[slot_x<N>(l, b, c)] = v[b];
+    __syncthreads();
+#pragma unroll
+    for (int be = 0; be < G; ++be)
+#pragma unroll
+        for (int a = 0; a < L; ++a) v[be * L + a] = lds[slot_x<N>(l, c + L * be, a)];
+    __syncthreads();
+#pragma unroll
+    for (int be = 0; be < G; ++be) dftL<L, SG>(&v[be * L]);
+}
+
+// MID -> NAT, DFT of sign SG along every line.
+template <int N, int SG>
+__device__ __forceinline__ void mid2nat(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
+    constexpr int L = N / 16, G = 16 / L;
+#pragma unroll
+    for (int be = 0; be < G; ++be) dftL<L, SG>(&v[be * L]);
+#pragma unroll
+    for (int be = 0; be < G; ++be)
+#pragma unroll
+        for (int a = 0; a < L; ++a) lds[slot_x<N>(l, c + L * be, a)] = v[be * L + a];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = lds[slot_x<N>(l, b, c)];
+    __syncthreads();
+    const float4* twc = tw + c * 16;
+#pragma unroll
+    for (int b = 1; b < 16; ++b) v[b] = tmul<(SG > 0)>(v[b], twc[b]);
+    dft16<SG>(v);
+}
+
+// Re-distribute the field from layout (D0, K0) to (D1, K1) through LDS.
+template <int N, int D0, int K0, int D1, int K1>
+__device__ __forceinline__ void relayout(float2 (&v)[16], float2* lds, int l, int c) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int y, x;
+        reg_yx<N, D0, K0>(l, c, r, y, x);
+        lds[slot_t<N>(y, x)] = v[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int y, x;
+        reg_yx<N, D1, K1>(l, c, r, y, x);
+        v[r] = lds[slot_t<N>(y, x)];
+    }
+    __syncthreads();
+}
+
+// fftfreq index -> signed frequency in cycles per pixel times N
+template <int N> __device__ __forceinline__ int sfreq(int n) { return n < N / 2 ? n : n - N; }
+
+// XCD-aware block order: the hardware deals consecutive workgroups round
+// robin over 8 XCDs (each with its own L2); renumber so that each XCD gets a
+// contiguous range of logical ids (neighbouring positions / modes share L2).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    int q = nb / 8, r = nb % 8;
+    int x = b % 8;
+    return x * q + min(x, r) + b / 8;
+}
+
+}  // namespace ptyr

@@ -1,0 +1,98 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+function include/ptyr.h declares, and its pure-host validators return the
+documented status codes."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2505_07814_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ptyr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptyr_[a-z_]+)\s*\(", src)))
+
+
+def geom(**kw):
+    d = dict(N=128, M=6, S=12, H=640, W=640, B_max=64, dx=0.15, lam=0.0197, loss_kind=0, loss_p=0.5,
+             wave_budget_bytes=64 * 6 * 12 * 128 * 128 * 8, flags=0, n_scan=16384)
+    d.update(kw)
+    return L.Geom(*[d[f[0]] for f in L.Geom._fields_])
+
+
+def test_library_exports_every_header_function():
+    lib = L.lib()
+    names = header_functions()
+    assert set(names) == set(L.HEADER_SYMBOLS), names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    lib = L.lib()
+    for s in range(6):
+        assert lib.ptyr_status_str(s)
+    assert b"leaves" in lib.ptyr_status_str(L.PTYR_E_BOUNDS)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    ({}, L.PTYR_OK),
+    (dict(N=64, H=128, W=128), L.PTYR_OK),
+    (dict(N=96), L.PTYR_E_ARG),
+    (dict(M=0), L.PTYR_E_ARG),
+    (dict(S=0), L.PTYR_E_ARG),
+    (dict(B_max=0), L.PTYR_E_ARG),
+    (dict(H=100), L.PTYR_E_ARG),
+    (dict(dx=0.0), L.PTYR_E_ARG),
+    (dict(lam=-1.0), L.PTYR_E_ARG),
+    (dict(loss_kind=7), L.PTYR_E_ARG),
+    (dict(loss_p=0.0), L.PTYR_E_ARG),
+    (dict(flags=0x80), L.PTYR_E_ARG),
+    (dict(n_scan=-1), L.PTYR_E_ARG),
+])
+def test_check_geom(kw, expect):
+    g = geom(**kw)
+    assert L.lib().ptyr_check_geom(C.byref(g)) == expect
+
+
+def test_check_args_positions():
+    lib = L.lib()
+    g = geom(N=64, H=128, W=128, B_max=4)
+    ok = (C.c_float * 4)(64.0, 64.0, 32.0, 96.0)
+    assert lib.ptyr_check_args(C.byref(g), 2, ok) == L.PTYR_OK
+    assert lib.ptyr_check_args(C.byref(g), 0, ok) == L.PTYR_E_ARG
+    assert lib.ptyr_check_args(C.byref(g), 5, None) == L.PTYR_E_ARG
+    for bad in [(31.4, 64.0), (64.0, 96.6), (float("nan"), 64.0), (1e30, 64.0)]:
+        arr = (C.c_float * 2)(*bad)
+        assert lib.ptyr_check_args(C.byref(g), 1, arr) == L.PTYR_E_BOUNDS, bad
+    # round half to even: 31.5 -> 32 (corner 0) is inside, 96.5 -> 96 (corner 64) is inside
+    edge = (C.c_float * 2)(31.5, 96.5)
+    assert lib.ptyr_check_args(C.byref(g), 1, edge) == L.PTYR_OK
+
+
+def test_workspace_and_checkpoint_plan():
+    lib = L.lib()
+    full = geom()
+    k = C.c_int()
+    assert lib.ptyr_checkpoint_plan(C.byref(full), C.byref(k)) == L.PTYR_OK and k.value == 1
+    none = geom(wave_budget_bytes=0)
+    assert lib.ptyr_checkpoint_plan(C.byref(none), C.byref(k)) == L.PTYR_OK and k.value == 13
+    per = 64 * 6 * 128 * 128 * 8
+    third = geom(wave_budget_bytes=4 * per)           # 4 kept waves of 12 slices -> stride 3
+    assert lib.ptyr_checkpoint_plan(C.byref(third), C.byref(k)) == L.PTYR_OK and k.value == 3
+    assert lib.ptyr_workspace_bytes(C.byref(full)) > lib.ptyr_workspace_bytes(C.byref(none))
+    assert lib.ptyr_workspace_bytes(C.byref(geom(N=96))) == 0
+
+
+def test_create_rejects_small_workspace_without_device_work():
+    lib = L.lib()
+    g = geom()
+    ctx = C.c_void_p()
+    n = lib.ptyr_workspace_bytes(C.byref(g))
+    assert lib.ptyr_create(C.byref(g), C.c_void_p(256), n - 1, None, C.byref(ctx)) == L.PTYR_E_NOMEM
+    assert lib.ptyr_create(C.byref(g), None, n, None, C.byref(ctx)) == L.PTYR_E_ARG

@@ -1,0 +1,303 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Both sides get the same float32-rounded inputs from the seeded generator; the
+measured patterns are Poisson samples of the oracle's own forward model.
+Bars: intensities relative L2 <= 1e-5, loss relative <= 1e-6 on identical
+inputs, every gradient block relative L2 <= 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import multislice as ms
+from oracle.adam import adam_step
+from paper_2505_07814_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.ravel(np.asarray(a)), np.ravel(np.asarray(b))
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+class Case:
+    """float32-rounded inputs shared by the oracle and the GPU."""
+
+    def __init__(self, w, B=None, start=0, perturb=True, seed=0):
+        rng = np.random.default_rng(1000 + seed)
+        B = w.pos.shape[0] if B is None else B
+        self.w = w
+        self.lam = synth.wavelength_A(w.kv)
+        self.amp_true = w.amp.astype(np.float32)
+        self.phase_true = w.phase.astype(np.float32)
+        self.probe = w.probe.astype(np.complex64)
+        self.pos = w.pos[start:start + B].astype(np.float32)
+        self.tilt = w.tilt[start:start + B].astype(np.float32)
+        self.dz = np.float32(w.dz)
+        I = ms.forward(self.amp_true, self.phase_true, self.probe, self.pos, self.tilt, self.dz, w.dx, self.lam)
+        self.I_true = I
+        self.meas = rng.poisson(I).astype(np.float32)
+        if perturb:  # evaluate gradients away from the truth
+            self.amp = (1.0 + 0.9 * (self.amp_true - 1.0)).astype(np.float32)
+            self.phase = (0.8 * self.phase_true + 0.02 * rng.standard_normal(self.phase_true.shape)).astype(np.float32)
+        else:
+            self.amp, self.phase = self.amp_true, self.phase_true
+        self.B = B
+
+    def engine(self, loss="gaussian", p=None, **kw):
+        from paper_2505_07814_amd.ptyr import Engine
+        w = self.w
+        return Engine(w.N, w.M, w.S, w.H, w.W, self.B, w.dx, self.lam, loss=loss, p=p, device=DEV, **kw)
+
+    def gpu_args(self, amp=None, phase=None):
+        amp = self.amp if amp is None else amp
+        phase = self.phase if phase is None else phase
+        return (T(amp), T(phase), T(self.probe), T(self.pos), T(self.tilt), T(np.array([self.dz], np.float32)))
+
+    def oracle_grad(self, kind="gaussian", p=None):
+        return ms.gradients(self.amp, self.phase, self.probe, self.pos, self.tilt, self.dz, self.w.dx, self.lam,
+                            self.meas, kind, p)
+
+
+def small(N, S, M, B, seed, H=None, W=None, tilt=2e-3):
+    H = H or N + 37
+    W = W or N + 41
+    return synth.small_case(N=N, S=S, M=M, B=B, H=H, W=W, seed=seed, tilt_scale=tilt)
+
+
+SMALL = [(64, 1, 1, 1, 1), (64, 3, 2, 5, 2), (64, 4, 3, 7, 3), (128, 2, 2, 3, 4), (128, 3, 1, 2, 5)]
+
+
+@pytest.mark.parametrize("N,S,M,B,seed", SMALL)
+def test_forward_parity_small(N, S, M, B, seed):
+    print(f"forward small N={N} S={S} M={M} B={B}", flush=True)
+    c = Case(small(N, S, M, B, seed), perturb=False)
+    eng = c.engine()
+    I = eng.forward(*c.gpu_args())
+    eng.sync()
+    e = rel(I.cpu().numpy(), c.I_true)
+    print(f"forward rel-L2 {e:.2e}", flush=True)
+    assert e < 1e-5
+
+
+def test_forward_parity_single_slice_64():
+    print("forward single_slice_64", flush=True)
+    c = Case(synth.workload("single_slice_64"), perturb=False)
+    eng = c.engine()
+    I = eng.forward(*c.gpu_args())
+    eng.sync()
+    e = rel(I.cpu().numpy(), c.I_true)
+    print(f"forward rel-L2 {e:.2e}", flush=True)
+    assert e < 1e-5
+
+
+def test_forward_parity_multislice_128_batch():
+    """The benchmark's launch: N=128, 12 slices, 6 modes, one batch of 64."""
+    print("forward multislice_128 B=64", flush=True)
+    c = Case(synth.workload("multislice_128", scan=64), perturb=False)
+    eng = c.engine()
+    I = eng.forward(*c.gpu_args())
+    eng.sync()
+    e = rel(I.cpu().numpy(), c.I_true)
+    print(f"forward rel-L2 {e:.2e}", flush=True)
+    assert e < 1e-5
+
+
+@pytest.mark.parametrize("kind,p", [("gaussian", 0.5), ("poisson", 1.0), ("gaussian", 1.0), ("poisson", 0.5)])
+def test_loss_parity(kind, p):
+    rng = np.random.default_rng(7)
+    Im = rng.gamma(2.0, 20.0, (5, 64, 64)).astype(np.float32)
+    Im[:, :3, :3] = 0.0                                  # exact zeros in the model
+    Ie = rng.poisson(Im + 0.5).astype(np.float32)
+    from paper_2505_07814_amd.ptyr import Engine
+    eng = Engine(64, 1, 1, 64, 64, 5, 0.2, 0.02, loss=kind, p=p, device=DEV)
+    L, g = eng.loss(T(Im), T(Ie), want_grad=True)
+    eng.sync()
+    L0, g0 = ms.loss(Im, Ie, kind, p)
+    assert abs(float(L.cpu()[0]) - L0) <= 1e-6 * abs(L0)
+    assert rel(g.cpu().numpy(), g0) < 1e-6
+
+
+GRAD_SMALL = [(64, 1, 1, 3, 11), (64, 3, 2, 5, 12), (128, 3, 2, 3, 13), (64, 5, 3, 6, 14)]
+
+
+def _check_grads(c, eng, kind="gaussian", p=None, tol=1e-4, **kw):
+    loss, g = eng.adjoint(*c.gpu_args(), T(c.meas), **kw)
+    eng.sync()
+    ref = c.oracle_grad(kind, p)
+    errs = {
+        "loss": abs(float(loss.cpu()[0]) - ref.loss) / abs(ref.loss),
+        "amp": rel(g["amp"].cpu().numpy(), ref.amp),
+        "phase": rel(g["phase"].cpu().numpy(), ref.phase),
+        "probe": rel(g["probe"].cpu().numpy(), ref.probe),
+        "pos": rel(g["pos"].cpu().numpy(), ref.pos),
+        "dz": rel(g["dz"].cpu().numpy(), [ref.dz]),
+    }
+    if c.w.S > 1:
+        errs["tilt"] = rel(g["tilt"].cpu().numpy(), ref.tilt)
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < (1e-5 if k == "loss" else tol), (k, v)
+    return g
+
+
+@pytest.mark.parametrize("N,S,M,B,seed", GRAD_SMALL)
+@pytest.mark.parametrize("kind", ["gaussian", "poisson"])
+def test_gradient_parity_small(N, S, M, B, seed, kind):
+    print(f"gradient small N={N} S={S} M={M} B={B} {kind}", flush=True)
+    c = Case(small(N, S, M, B, seed))
+    _check_grads(c, c.engine(kind), kind)
+
+
+def test_gradient_parity_diffcheck_64():
+    """24 slices, local tilts (the differentiation-check workload)."""
+    print("gradient diffcheck_64", flush=True)
+    c = Case(synth.workload("diffcheck_64"))
+    _check_grads(c, c.engine())
+
+
+def test_gradient_parity_multislice_128():
+    print("gradient multislice_128 B=8", flush=True)
+    c = Case(synth.workload("multislice_128", scan=8))
+    _check_grads(c, c.engine())
+
+
+def test_recompute_equals_stored_waves():
+    print("recompute vs store", flush=True)
+    c = Case(synth.workload("diffcheck_64"))
+    g_store = c.engine().adjoint(*c.gpu_args(), T(c.meas))[1]
+    for budget in (0, 3 * 16 * 64 * 64 * 8, 7 * 16 * 64 * 64 * 8):
+        eng = c.engine(wave_budget=budget)
+        g_rec = eng.adjoint(*c.gpu_args(), T(c.meas))[1]
+        eng.sync()
+        for k in g_store:
+            a, b = g_rec[k].cpu().numpy(), g_store[k].cpu().numpy()
+            assert rel(a, b) <= 1e-7, (budget, eng.checkpoint_stride, k, rel(a, b))
+
+
+def test_deterministic():
+    c = Case(small(64, 3, 2, 6, 21))
+    eng = c.engine()
+    g1 = eng.adjoint(*c.gpu_args(), T(c.meas))[1]
+    g2 = eng.adjoint(*c.gpu_args(), T(c.meas))[1]
+    eng.sync()
+    for k in g1:
+        assert torch.equal(g1[k], g2[k]), k
+
+
+def test_reuse_forward_matches_recompute():
+    c = Case(small(64, 3, 2, 4, 22))
+    eng = c.engine()
+    eng.forward(*c.gpu_args())
+    g1 = eng.adjoint(*c.gpu_args(), T(c.meas), reuse=True)[1]
+    g2 = eng.adjoint(*c.gpu_args(), T(c.meas), reuse=False)[1]
+    eng.sync()
+    for k in g1:
+        assert torch.equal(g1[k], g2[k]), k
+
+
+def test_accumulation_over_sub_batches():
+    """Two calls on the halves of a batch add their gradients (+=)."""
+    c = Case(small(64, 2, 1, 6, 23))
+    from paper_2505_07814_amd.ptyr import Engine
+    eng = Engine(64, 1, 2, c.w.H, c.w.W, 3, c.w.dx, c.lam, device=DEV)
+    args = c.gpu_args()
+    grads = None
+    for h in (0, 1):
+        idx = torch.arange(3 * h, 3 * h + 3, dtype=torch.int32, device=DEV)
+        _, grads = eng.adjoint(*args, T(c.meas), idx=idx, grads=grads)
+    eng.sync()
+    ref = {k: np.zeros_like(v) for k, v in [("amp", c.amp), ("phase", c.phase)]}
+    for h in (0, 1):
+        sl = slice(3 * h, 3 * h + 3)
+        r = ms.gradients(c.amp, c.phase, c.probe, c.pos[sl], c.tilt[sl], c.dz, c.w.dx, c.lam, c.meas[sl])
+        ref["amp"] += r.amp
+        ref["phase"] += r.phase
+    assert rel(grads["amp"].cpu().numpy(), ref["amp"]) < 1e-4
+    assert rel(grads["phase"].cpu().numpy(), ref["phase"]) < 1e-4
+
+
+def test_out_of_bounds_position_is_reported_and_skipped():
+    c = Case(small(64, 2, 1, 3, 24), perturb=False)
+    pos = c.pos.copy()
+    pos[1] = [5.0, 50.0]                                 # patch leaves the object
+    from paper_2505_07814_amd import _lib as L
+    eng = c.engine()
+    args = list(c.gpu_args())
+    args[3] = T(pos)
+    I = eng.forward(*args)
+    with pytest.raises(L.PtyrError) as e:
+        eng.sync()
+    assert e.value.status == L.PTYR_E_BOUNDS
+    I = I.cpu().numpy()
+    assert np.all(I[1] == 0.0)
+    assert rel(I[[0, 2]], c.I_true[[0, 2]]) < 1e-5
+    eng.sync()                                            # flag was cleared
+
+
+def test_bad_row_index_is_reported():
+    c = Case(small(64, 2, 1, 3, 25), perturb=False)
+    from paper_2505_07814_amd import _lib as L
+    eng = c.engine()
+    idx = torch.tensor([0, 7, 2], dtype=torch.int32, device=DEV)
+    eng.forward(*c.gpu_args(), idx=idx)
+    with pytest.raises(L.PtyrError) as e:
+        eng.sync()
+    assert e.value.status == L.PTYR_E_ARG
+
+
+def test_adam_step_parity():
+    """Two mini-batch steps: GPU ptyr_step vs oracle gradient + oracle Adam."""
+    from paper_2505_07814_amd.ptyr import AdamState, Engine
+    w = small(64, 3, 2, 8, 26)
+    c = Case(w)
+    eng = Engine(64, 2, 3, w.H, w.W, 4, w.dx, c.lam, device=DEV, n_scan=8)
+    st = AdamState(*[t.clone() for t in c.gpu_args()])
+    lr = dict(amp=1e-3, phase=2e-3, probe=1e-2, pos=1e-2, tilt=1e-4, dz=1e-1)
+    ref = dict(amp=c.amp.astype(np.float64), phase=c.phase.astype(np.float64), probe=c.probe.astype(np.complex128),
+               pos=c.pos.astype(np.float64), tilt=c.tilt.astype(np.float64), dz=np.array([float(c.dz)]))
+    mom = {k: (np.zeros_like(v), np.zeros_like(v)) for k, v in ref.items()}
+    batches = [np.array([0, 2, 4, 6]), np.array([7, 5, 3, 1])]
+    meas = T(c.meas)
+    for t, b in enumerate(batches):
+        eng.step(st, torch.tensor(b, dtype=torch.int32, device=DEV), meas, lr)
+        gr = ms.gradients(ref["amp"], ref["phase"], ref["probe"], ref["pos"][b], ref["tilt"][b], ref["dz"][0],
+                          w.dx, c.lam, c.meas[b])
+        dense = dict(amp=gr.amp, phase=gr.phase, probe=gr.probe, dz=np.array([gr.dz]))
+        dense["pos"] = np.zeros_like(ref["pos"]); dense["pos"][b] = gr.pos
+        dense["tilt"] = np.zeros_like(ref["tilt"]); dense["tilt"][b] = gr.tilt
+        for k in ref:
+            ref[k], m, v = adam_step(ref[k], dense[k], mom[k][0], mom[k][1], t, lr[k])
+            mom[k] = (m, v)
+    eng.sync()
+    assert st.step == 2
+    for k in ref:
+        init = np.ravel(np.asarray(getattr(c, k) if k != "dz" else [c.dz])).astype(ref[k].dtype)
+        d_got = np.ravel(getattr(st, k).cpu().numpy()).astype(ref[k].dtype) - init
+        d_ref = np.ravel(ref[k]) - init
+        err = rel(d_got, d_ref)
+        print(k, f"update rel-L2 {err:.2e}", flush=True)
+        # Adam divides by sqrt(v): entries whose gradient nearly cancels keep an
+        # O(1) relative difference, so the bar is on the whole update
+        assert err < 1e-3, (k, err)
+
+
+def test_autograd_function_matches_adjoint():
+    from paper_2505_07814_amd.ptyr import multislice_loss
+    c = Case(small(64, 3, 2, 4, 27))
+    eng = c.engine()
+    args = [t.clone().requires_grad_(True) for t in c.gpu_args()]
+    loss = multislice_loss(eng, *args, T(c.meas))
+    (2.0 * loss).backward()
+    ref = c.oracle_grad()
+    assert abs(float(loss.detach().cpu()) - ref.loss) < 1e-5 * abs(ref.loss)
+    assert rel(args[1].grad.cpu().numpy(), 2 * ref.phase) < 1e-4
+    assert rel(args[2].grad.cpu().numpy(), 2 * ref.probe) < 1e-4
+    assert rel(args[3].grad.cpu().numpy(), 2 * ref.pos) < 1e-4
