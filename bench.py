@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the multislice reconstruction step on one MI355X.
+
+A step is one mini-batch update of the whole hot path through the C ABI
+(ptyr_step): sub-pixel probe shift, object transmission and tilted Fresnel
+propagation through every slice, far-field intensity summed over modes, the
+amplitude (Gaussian, p = 0.5) loss, the gradient with respect to object
+amplitude and phase, probe, positions, tilts and slice spacing (object
+gradient reduced per tile), and a dense Adam update of all six parameters.
+
+Workload (seeded, synthetic): detector / probe window 128 x 128 at 0.15 A/px,
+300 kV, 6 orthogonalised Hermite-Gaussian probe modes, object 12 slices of
+640 x 640 (square Gaussian-atom lattice, 5 % vacancies, dz = 20 A), a
+128 x 128 raster (step 4 px, +-0.5 px jitter), Poisson data at 1e6
+electrons per pattern, 64 positions per update.  All inputs are resident in
+device memory before the timed region.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3          # MI355X: 256 CU x 2.4 GHz x 128 FP32 FMA/clk x 2
+PEAK_FP32_UNPACKED_TFLOPS = 78.6         # the same without packed FP32 (disabled in this build)
+WORKLOAD = "multislice_128"
+
+
+def fft_flops(N):
+    """Nominal flops of one N x N complex 2-D FFT: 5 N^2 log2(N^2)."""
+    import math
+    return 5.0 * N * N * math.log2(N * N)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2505_07814_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, B):
+    """The FP64 oracle on one batch of the same workload: forward, loss,
+    gradient of all six parameters and the Adam update, on the host."""
+    import numpy as np
+    from oracle import multislice as ms
+    from oracle.adam import adam_step
+    from paper_2505_07814_amd import synth
+
+    lam = synth.wavelength_A(w.kv)
+    sl = slice(0, B)
+    pos, tilt = w.pos[sl], w.tilt[sl]
+    # measured patterns for the sample come from the oracle itself (untimed)
+    I = ms.forward(w.amp, w.phase, w.probe, pos, tilt, w.dz, w.dx, lam)
+    meas = synth.poisson(I, w.seed_base + 4).astype(np.float64)
+    amp0, ph0 = synth.plain_init(w.S, w.H, w.W, w.seed_base + 5)
+    t0 = time.perf_counter()
+    g = ms.gradients(amp0, ph0, w.probe, pos, tilt, w.dz, w.dx, lam, meas)
+    z = np.zeros
+    adam_step(amp0, g.amp, z(amp0.shape), z(amp0.shape), 0, 1e-3)
+    adam_step(ph0, g.phase, z(ph0.shape), z(ph0.shape), 0, 1e-3)
+    adam_step(w.probe, g.probe, z(w.probe.shape, complex), z(w.probe.shape, complex), 0, 1e-3)
+    adam_step(pos, g.pos, z(pos.shape), z(pos.shape), 0, 1e-3)
+    adam_step(tilt, g.tilt, z(tilt.shape), z(tilt.shape), 0, 1e-3)
+    dt = time.perf_counter() - t0
+    return {"value": B / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
+            "sample": f"one batch of {B} positions of the same workload (forward, loss, gradient of all six "
+                      f"parameters and Adam, FP64 NumPy, single thread), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=256, help="timed steps (256 = one pass over the scan)")
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on a single GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2505_07814_amd import synth
+    from paper_2505_07814_amd.ptyr import AdamState, Engine
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.workload(WORKLOAD)
+    B = args.batch
+    lam = synth.wavelength_A(w.kv)
+    n_pos = w.pos.shape[0]
+    T = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a if dt is None else a.astype(dt))).to(dev)
+
+    eng = Engine(w.N, w.M, w.S, w.H, w.W, B, w.dx, lam, n_scan=n_pos, device=dev)
+    # synthetic measured data: forward model of the true object, Poisson-sampled
+    true = dict(amp=T(w.amp, np.float32), phase=T(w.phase, np.float32), probe=T(w.probe, np.complex64),
+                pos=T(w.pos, np.float32), tilt=T(w.tilt, np.float32), dz=T(np.array([w.dz], np.float32)))
+    meas = torch.empty((n_pos, w.N, w.N), dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(w.seed_base + 4)
+    for b0 in range(0, n_pos, B):
+        idx = torch.arange(b0, min(b0 + B, n_pos), dtype=torch.int32, device=dev)
+        I = eng.forward(true["amp"], true["phase"], true["probe"], true["pos"], true["tilt"], true["dz"], idx=idx)
+        meas[b0:b0 + len(idx)] = torch.poisson(I, generator=gen)
+    eng.sync()
+    del true
+
+    amp0, ph0 = synth.plain_init(w.S, w.H, w.W, w.seed_base + 5)
+    st = AdamState(T(amp0, np.float32), T(ph0, np.float32), T(w.probe, np.complex64), T(w.pos, np.float32),
+                   T(np.zeros_like(w.pos), np.float32), T(np.array([w.dz], np.float32)))
+    lr = dict(amp=5e-4, phase=5e-4, probe=1e-4, pos=1e-3, tilt=1e-5, dz=1e-2)
+    perm = np.random.default_rng(w.seed_base + 6).permutation(n_pos)
+    nb = n_pos // B
+    batches = [torch.tensor(perm[b * B:(b + 1) * B], dtype=torch.int32, device=dev) for b in range(nb)]
+
+    stream = torch.cuda.current_stream(dev)
+    for s in range(args.warmup):
+        eng.step(st, batches[s % nb], meas, lr)
+    eng.sync()
+    eng.timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for s in range(args.steps):
+        eng.step(st, batches[(args.warmup + s) % nb], meas, lr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    kt = eng.timing_read()
+    eng.timing(False)
+    eng.sync()
+
+    ms_step = ms_total / args.steps
+    value = B * args.steps / (ms_total / 1e3)
+    per_launch = {k: (v[0] / v[1] if v[1] else float("nan")) for k, v in kt.items()}
+    dom = max(per_launch, key=lambda k: kt[k][0])
+    flops = B * w.M * 2 * w.S * fft_flops(w.N)          # nominal FFT flops of either fused kernel
+    achieved = flops / (per_launch[dom] * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu", "kernel": f"k_{dom}<128>", "achieved": round(achieved, 3),
+        "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+        "traffic": read_traffic(dom, WORKLOAD),
+        "launch_ms": round(per_launch[dom], 4),
+        "flops_per_launch": flops,
+        "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+        "other_kernel_ms": {k: round(v, 4) for k, v in per_launch.items() if k != dom},
+    }
+    out = {
+        "metric": "fwd+adjoint patterns/s (N=128, 12 slices, 6 modes)",
+        "value": round(value, 1), "unit": "patterns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "multislice_128: probe 128x128 at 0.15 A/px, 6 modes, object 12 x 640 x 640, "
+                               "dz 20 A, 128x128 scan, 64 positions per Adam step (forward + loss + gradient "
+                               "of all six parameters + Adam)",
+                   "global_batch": B, "N": w.N, "slices": w.S, "modes": w.M, "positions": n_pos},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, B)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

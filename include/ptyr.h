@@ -125,8 +125,12 @@ ptyr_status ptyr_check_args(const ptyr_geom* g, int B, const float* pos_host);
 size_t ptyr_workspace_bytes(const ptyr_geom* g);
 
 /* Pure host: how the forward keeps waves for the gradient under
- * g->wave_budget_bytes: *stride = checkpoint spacing in slices (1 = every
- * slice kept, S+1 = none kept, waves recomputed from the probe). */
+ * g->wave_budget_bytes, counted in N x N complex64 waves per (row, mode)
+ * chain of a B_max batch.  *stride = 1: all 2S waves of a chain are kept
+ * (incident wave and its spectrum per slice, far field).  Otherwise three
+ * waves per chain are scratch for recomputation and the incident wave is
+ * kept every *stride >= 2 slices; *stride = S+1: none is kept and the
+ * gradient recomputes from the probe (O(S^2) slice steps). */
 ptyr_status ptyr_checkpoint_plan(const ptyr_geom* g, int* stride);
 
 /* Bind a context to a workspace (device, caller-owned, >= ptyr_workspace_bytes)
@@ -189,6 +193,19 @@ ptyr_status ptyr_adjoint(ptyr_ctx* ctx, const float* amp, const float* phase,
  * ptyr_sync as PTYR_E_ARG. */
 ptyr_status ptyr_step(ptyr_ctx* ctx, ptyr_params* p, const int* idx, int B,
                       const float* I_meas_all, const ptyr_lr* lr, double* loss_dev);
+
+/* Instrumentation (not part of the method): when enabled, the context brackets
+ * each launch of its fused wave kernels with HIP events on its stream.
+ * kernel ids: PTYR_K_FORWARD (the multislice forward kernel) and
+ * PTYR_K_GRADIENT (the gradient kernel).  Enabling creates the events (no
+ * device memory is allocated); at most 4096 launches are recorded between
+ * reads, later ones are not timed. */
+enum { PTYR_K_FORWARD = 0, PTYR_K_GRADIENT = 1 };
+ptyr_status ptyr_timing_enable(ptyr_ctx* ctx, int on);
+/* Synchronise the stream and write the summed kernel time in milliseconds and
+ * the number of timed launches of kernel `which` since timing was last
+ * enabled (ptyr_timing_enable clears the record). */
+ptyr_status ptyr_timing_read(ptyr_ctx* ctx, int which, double* total_ms, int* launches);
 
 #ifdef __cplusplus
 }

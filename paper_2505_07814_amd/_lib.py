@@ -73,6 +73,8 @@ def lib():
         "ptyr_adjoint": (st, [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, vp,
                               vp, vp, vp, vp, vp, vp, vp, C.c_uint]),
         "ptyr_step": (st, [vp, C.POINTER(Params), vp, C.c_int, vp, C.POINTER(LR), vp]),
+        "ptyr_timing_enable": (st, [vp, C.c_int]),
+        "ptyr_timing_read": (st, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -89,4 +91,6 @@ def check(status, what):
 
 HEADER_SYMBOLS = ["ptyr_status_str", "ptyr_check_geom", "ptyr_check_args", "ptyr_workspace_bytes",
                   "ptyr_checkpoint_plan", "ptyr_create", "ptyr_destroy", "ptyr_sync", "ptyr_forward",
-                  "ptyr_loss", "ptyr_adjoint", "ptyr_step"]
+                  "ptyr_loss", "ptyr_adjoint", "ptyr_step", "ptyr_timing_enable", "ptyr_timing_read"]
+
+PTYR_K_FORWARD, PTYR_K_GRADIENT = 0, 1

@@ -1,7 +1,14 @@
-// kernels.hpp - gfx950 kernels of the multislice forward model, its loss, its
-// gradient and the Adam step.  The fused per-(position, mode) kernels keep the
-// whole N x N wave (N = 64 or 128) in registers across all slices and use LDS
+// kernels.hpp - gfx950 kernels of the multislice forward model and its
+// gradient.  One workgroup per (batch row, probe mode) keeps the whole N x N
+// complex wave (N = 64 or 128) in registers across all slices and uses LDS
 // only for line exchanges and transposes (wave.hpp).
+//
+// Per slice the forward takes the full 2-D spectrum of the transmitted wave,
+// multiplies by the propagator and transforms back, so the spectrum of every
+// incident wave, Y_s = F[phi_s], is formed on the way.  Kept for the gradient
+// (when the memory budget allows): phi_s (space), Y_s (spectrum) and the
+// far field.  The gradient kernel then holds a single wave in registers and
+// streams those kept arrays element by element.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,6 +26,12 @@ struct PosInfo {      // integer crop corner and sub-pixel shift of one batch ro
     int pad[3];
 };
 
+// How the forward keeps waves for the gradient.
+//   FULL : phi_s for every slice, Y_s for s >= 1, and the far field
+//   CKPT : phi_s for s % ckK == 0 (ckK <= S) or nothing (ckK > S); the gradient
+//          recomputes phi_s / Y_s into a 3-wave scratch per chain (phi, Y, G)
+enum : int { KEEP_FULL = 0, KEEP_CKPT = 1 };
+
 // Arguments shared by the fused forward / gradient kernels.
 struct WaveArgs {
     const float2* Oc;      // S x H x W complex transmission a exp(i phase)
@@ -26,105 +39,86 @@ struct WaveArgs {
     const PosInfo* pinfo;  // B, with validated rows
     const float* tilt;     // rows of (th_y, th_x)
     const float* dz;       // 1
-    float2* store;         // B x M x nck x N x N kept waves (nullable)
-    int ckK;               // keep phi_s for s % ckK == 0 (ckK > S: none kept)
-    int nck;               // kept waves per chain
+    float2* store;         // kept waves, per chain: FULL 2S waves, CKPT nck + 3
+    int keep;              // KEEP_FULL / KEEP_CKPT
+    int ckK;               // checkpoint spacing (CKPT)
+    int nck;               // checkpoints per chain (CKPT)
     int B, M, S, H, W;
     double dx, lam;
     int global_tilt;
-    // forward output
-    float* Imode;          // B x M x N x N, fftshifted
-    // gradient inputs / outputs
-    const float* wgt;      // B x N x N fftshifted, 2 dL/dI
+    float* Imode;          // B x M x N x N, zero frequency at (0, 0)
+    const float* wgt;      // B x N x N, 2 dL/dI, zero frequency at (0, 0)
     float2* gO;            // B x M x S x N x N object-patch gradients
     float2* gPhat;         // B x M x N x N probe-spectrum gradients
     float* part;           // B x M x 8 scalar partial sums
 };
 
+// Wave slots of one chain in the store.
+template <int N> struct Slots {
+    float2* base;
+    int S, nck;
+    __device__ Slots(const WaveArgs& a, int chain) : S(a.S), nck(a.nck) {
+        const int per = a.keep == KEEP_FULL ? 2 * a.S : a.nck + 3;
+        base = a.store ? a.store + (size_t)chain * per * (N * N) : nullptr;
+    }
+    // FULL: [phi_0 .. phi_{S-1}] [Y_1 .. Y_{S-1}] [far field]
+    __device__ float2* phi(int s) const { return base + (size_t)s * N * N; }
+    __device__ float2* spec(int s) const { return base + (size_t)(S + s - 1) * N * N; }
+    __device__ float2* far() const { return base + (size_t)(2 * S - 1) * N * N; }
+    // CKPT: [checkpoints 0 .. nck-1] [scratch phi] [scratch Y] [scratch G]
+    __device__ float2* ckpt(int k) const { return base + (size_t)k * N * N; }
+    __device__ float2* sc_phi() const { return base + (size_t)nck * N * N; }
+    __device__ float2* sc_spec() const { return base + (size_t)(nck + 1) * N * N; }
+    __device__ float2* sc_g() const { return base + (size_t)(nck + 2) * N * N; }
+};
+
 // ------------------------------------------------------------------ tables
-// Per-workgroup LDS tables: twiddles and the separable propagator / shift.
+// Per-workgroup LDS tables: twiddles and the separable propagator factors.
 template <int N> struct Tables {
     float4 tw[N];          // per-lane twiddles: tw[c*16 + b] = exp(-2 pi i c b / N)
     float4 hy[N], hx[N];   // propagator factors along y and x (unscaled)
-    float dry, drx;        // sub-pixel shift of the position
+    float2 ry[N], rx[N];   // shift ramp factors exp(-2 pi i q_n dr_y), exp(-2 pi i q_n dr_x)
 };
 
-// shift ramp factor exp(-2 pi i q_n dr) (used once per chain, computed in place)
-template <int N> __device__ __forceinline__ float2 ramp(int n, float dr) {
-    float s, c;
-    sincospif(-2.0f * (float)sfreq<N>(n) / N * dr, &s, &c);
-    return make_float2(c, s);
-}
-
 template <int N>
-__device__ void build_tables(Tables<N>& t, const WaveArgs& a, const PosInfo& pi, float thy, float thx,
-                             float dz) {
+__device__ __forceinline__ void build_tables(Tables<N>& t, const WaveArgs& a, const PosInfo& pi, float thy,
+                                             float thx, float dz) {
     constexpr int T = N * N / 16;
     const double pi_d = 3.14159265358979323846;
-    if (threadIdx.x == 0) { t.dry = pi.dry; t.drx = pi.drx; }
-    for (int i = threadIdx.x; i < 3 * N; i += T) {
+    for (int i = threadIdx.x; i < 5 * N; i += T) {
         int which = i / N, n = i % N;
         double q = (double)sfreq<N>(n) / N;            // cycles per pixel
         double k = q / a.dx;                            // 1/angstrom
         double ph;
         if (which == 0) ph = -2.0 * pi_d * (double)((n / 16) * (n % 16)) / N;
         else if (which == 1) ph = -pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan((double)thy);
-        else ph = -pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan((double)thx);
+        else if (which == 2) ph = -pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan((double)thx);
+        else if (which == 3) ph = -2.0 * pi_d * q * pi.dry;
+        else ph = -2.0 * pi_d * q * pi.drx;
         double s, c;
         sincos(ph, &s, &c);
         float4 w = unit_pair(c, s);
         if (which == 0) t.tw[n] = w;
         else if (which == 1) t.hy[n] = w;
-        else t.hx[n] = w;
+        else if (which == 2) t.hx[n] = w;
+        else if (which == 3) t.ry[n] = make_float2(w.x, w.y);
+        else t.rx[n] = make_float2(w.x, w.y);
     }
     __syncthreads();
 }
 
 // ------------------------------------------------------------------ steps
-// chi = O_s[t + (y, x)] * v  in layout (D, NAT)
-template <int N, int D>
+// chi = O_s[t + (y, x)] * v  in layout (COL, NAT)
+template <int N>
 __device__ __forceinline__ void transmit(float2 (&v)[16], const float2* Os, int W, int ty, int tx, int l, int c) {
+    using Y = Lay<N, COL, NAT>;
+    const float2* base = Os + (size_t)ty * W + tx;
+    const unsigned o = Y::toff(l, c, W);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        int y, x;
-        reg_yx<N, D, NAT>(l, c, r, y, x);
-        v[r] = cmul(v[r], Os[(size_t)(ty + y) * W + tx + x]);
+        v[r] = cmul(v[r], (base + Y::dy(r) * W)[o]);
+        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
-}
-
-// F^-1_line [ h * F_line [v] ] along the lines of direction D, times scale
-template <int N>
-__device__ __forceinline__ void line_prop(float2 (&v)[16], float2* lds, const float4* tw, const float4* h,
-                                          float scale, int l, int c) {
-    nat2mid<N, -1>(v, lds, tw, l, c);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cscale(tmul<false>(v[r], h[line_pos<N, MID>(c, r)]), scale);
-    mid2nat<N, +1>(v, lds, tw, l, c);
-}
-
-// One propagation between slices, separable: F^-1 H F = (F^-1 h_y F)_y (F^-1 h_x F)_x.
-// The field enters in (st, NAT) and leaves in (other, NAT); returns the new state.
-template <int N>
-__device__ __forceinline__ int propagate(float2 (&v)[16], int st, float2* lds, const Tables<N>& t, int l, int c) {
-    const float sc = 1.0f / N;
-    if (st == COL) {
-        line_prop<N>(v, lds, t.tw, t.hy, sc, l, c);
-        relayout<N, COL, NAT, ROW, NAT>(v, lds, l, c);
-        line_prop<N>(v, lds, t.tw, t.hx, sc, l, c);
-        return ROW;
-    } else {
-        line_prop<N>(v, lds, t.tw, t.hx, sc, l, c);
-        relayout<N, ROW, NAT, COL, NAT>(v, lds, l, c);
-        line_prop<N>(v, lds, t.tw, t.hy, sc, l, c);
-        return COL;
-    }
-}
-
-template <int N>
-__device__ __forceinline__ void transmit_state(float2 (&v)[16], int st, const float2* Os, int W, int ty, int tx,
-                                               int l, int c) {
-    if (st == COL) transmit<N, COL>(v, Os, W, ty, tx, l, c);
-    else transmit<N, ROW>(v, Os, W, ty, tx, l, c);
 }
 
 // phi_0 = F^-1[ Phat_m * R ] (orthonormal), leaves in (COL, NAT)
@@ -132,11 +126,10 @@ template <int N>
 __device__ __forceinline__ void shift_probe(float2 (&v)[16], const float2* Pm, float2* lds, const Tables<N>& t,
                                             int l, int c) {
     const float sc = 1.0f / N;
+    wload<N, ROW, MID>(v, Pm, N, l, c);
+    const float2 ru = cscale(t.ry[l], sc);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        int u = l, w = line_pos<N, MID>(c, r);
-        v[r] = cscale(cmul(cmul(Pm[u * N + w], ramp<N>(u, t.dry)), ramp<N>(w, t.drx)), sc);
-    }
+    for (int r = 0; r < 16; ++r) v[r] = cmul(cmul(v[r], ru), t.rx[line_pos<N, MID>(c, r)]);
     mid2nat<N, +1>(v, lds, t.tw, l, c);
     relayout<N, ROW, NAT, COL, MID>(v, lds, l, c);
     mid2nat<N, +1>(v, lds, t.tw, l, c);
@@ -149,13 +142,6 @@ __device__ __forceinline__ void fft2_from_col(float2 (&v)[16], float2* lds, cons
     relayout<N, COL, MID, ROW, NAT>(v, lds, l, c);
     nat2mid<N, -1>(v, lds, tw, l, c);
 }
-// unnormalised 2-D DFT of sign -1 from (ROW, NAT); leaves in (COL, MID)
-template <int N>
-__device__ __forceinline__ void fft2_from_row(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
-    nat2mid<N, -1>(v, lds, tw, l, c);
-    relayout<N, ROW, MID, COL, NAT>(v, lds, l, c);
-    nat2mid<N, -1>(v, lds, tw, l, c);
-}
 // unnormalised 2-D inverse DFT from (ROW, MID); leaves in (COL, NAT)
 template <int N>
 __device__ __forceinline__ void ifft2_to_col(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
@@ -164,46 +150,28 @@ __device__ __forceinline__ void ifft2_to_col(float2 (&v)[16], float2* lds, const
     mid2nat<N, +1>(v, lds, tw, l, c);
 }
 
-template <int N>
-__device__ __forceinline__ void store_wave_col(const float2 (&v)[16], float2* dst, int l, int c) {
+// Multiply a (ROW, MID) spectrum by H (or conj(H)) and a scale.
+template <int N, bool CONJ>
+__device__ __forceinline__ void apply_h(float2 (&v)[16], const Tables<N>& t, float scale, int l, int c) {
+    const float4 hy = t.hy[l];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        int y, x;
-        reg_yx<N, COL, NAT>(l, c, r, y, x);
-        dst[y * N + x] = v[r];
-    }
-}
-template <int N>
-__device__ __forceinline__ void load_wave_col(float2 (&v)[16], const float2* src, int l, int c) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        int y, x;
-        reg_yx<N, COL, NAT>(l, c, r, y, x);
-        v[r] = src[y * N + x];
+        v[r] = cscale(tmul<CONJ>(tmul<CONJ>(v[r], hy), t.hx[line_pos<N, MID>(c, r)]), scale);
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// Incident wave of slice s in (COL, NAT): from the nearest kept wave (or the
-// shifted probe when none is kept), re-running the slice steps in between
-// with exactly the forward's code.
+// One slice step: v = phi_s (COL, NAT) -> chi_s -> (F, H, F^-1) -> phi_{s+1}
+// (COL, NAT).  The spectrum Y'_{s+1} = H F_raw[chi_s] / N^2 = F_raw[phi_{s+1}] / N^2
+// is written to spec when spec != nullptr.
 template <int N>
-__device__ void incident_wave(float2 (&v)[16], int s, const WaveArgs& a, int j, int m, int ty, int tx, float2* lds,
-                              const Tables<N>& t, int l, int c) {
-    int s0;
-    if (a.ckK <= a.S) {
-        s0 = (s / a.ckK) * a.ckK;
-        const float2* src = a.store + ((size_t)(j * a.M + m) * a.nck + s0 / a.ckK) * (N * N);
-        load_wave_col<N>(v, src, l, c);
-    } else {
-        s0 = 0;
-        shift_probe<N>(v, a.Phat + (size_t)m * N * N, lds, t, l, c);
-    }
-    int st = COL;
-    for (int u = s0; u < s; ++u) {
-        transmit_state<N>(v, st, a.Oc + (size_t)u * a.H * a.W, a.W, ty, tx, l, c);
-        st = propagate<N>(v, st, lds, t, l, c);
-    }
-    if (st == ROW) relayout<N, ROW, NAT, COL, NAT>(v, lds, l, c);
+__device__ __forceinline__ void slice_step(float2 (&v)[16], const float2* Os, int W, int ty, int tx, float2* spec,
+                                           float2* lds, const Tables<N>& t, int l, int c) {
+    transmit<N>(v, Os, W, ty, tx, l, c);
+    fft2_from_col<N>(v, lds, t.tw, l, c);
+    apply_h<N, false>(v, t, 1.0f / ((float)N * N), l, c);
+    if (spec) wstore<N, ROW, MID>(v, spec, N, l, c);
+    ifft2_to_col<N>(v, lds, t.tw, l, c);
 }
 
 // block-wide sum of NV floats, result valid in thread 0
@@ -245,59 +213,65 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
         return;
     }
     const float* th = a.global_tilt ? a.tilt : a.tilt + 2 * pi.row;
-    const float dz = *a.dz;
-    build_tables<N>(tab, a, pi, th[0], th[1], dz);
+    build_tables<N>(tab, a, pi, th[0], th[1], *a.dz);
+    const Slots<N> sl(a, j * a.M + m);
+    const bool full = sl.base && a.keep == KEEP_FULL;
+    const bool ckpt = sl.base && a.keep == KEEP_CKPT && a.ckK <= a.S;
+    const size_t HW = (size_t)a.H * a.W;
 
     float2 v[16];
     shift_probe<N>(v, a.Phat + (size_t)m * N * N, lds, tab, l, c);
-    int st = COL;
-    for (int s = 0; s < a.S; ++s) {
-        if (a.store && a.ckK <= a.S && s % a.ckK == 0) {
-            float2* dst = a.store + ((size_t)(j * a.M + m) * a.nck + s / a.ckK) * (N * N);
-            if (st == COL) store_wave_col<N>(v, dst, l, c);
-            else {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    int y, x;
-                    reg_yx<N, ROW, NAT>(l, c, r, y, x);
-                    dst[y * N + x] = v[r];
-                }
-            }
-        }
-        transmit_state<N>(v, st, a.Oc + (size_t)s * a.H * a.W, a.W, pi.ty, pi.tx, l, c);
-        if (s < a.S - 1) st = propagate<N>(v, st, lds, tab, l, c);
+    for (int s = 0; s < a.S - 1; ++s) {
+        if (full) wstore<N, COL, NAT>(v, sl.phi(s), N, l, c);
+        else if (ckpt && s % a.ckK == 0) wstore<N, COL, NAT>(v, sl.ckpt(s / a.ckK), N, l, c);
+        slice_step<N>(v, a.Oc + (size_t)s * HW, a.W, pi.ty, pi.tx, full ? sl.spec(s + 1) : nullptr, lds, tab, l, c);
     }
-    // far field |F chi|^2 / N^2, written with zero frequency at (N/2, N/2)
+    const int s = a.S - 1;
+    if (full) wstore<N, COL, NAT>(v, sl.phi(s), N, l, c);
+    else if (ckpt && s % a.ckK == 0) wstore<N, COL, NAT>(v, sl.ckpt(s / a.ckK), N, l, c);
+    transmit<N>(v, a.Oc + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
+    fft2_from_col<N>(v, lds, tab.tw, l, c);
+    if (full) wstore<N, ROW, MID>(v, sl.far(), N, l, c);
+    // far field |F chi|^2 / N^2 (zero frequency at (0, 0); the mode sum shifts it)
     const float s2 = 1.0f / ((float)N * N);
-    if (st == COL) {
-        fft2_from_col<N>(v, lds, tab.tw, l, c);
+    float iv[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            int y, x;
-            reg_yx<N, ROW, MID>(l, c, r, y, x);
-            Iout[((y + N / 2) % N) * N + (x + N / 2) % N] = cabs2(v[r]) * s2;
-        }
+    for (int r = 0; r < 16; ++r) iv[r] = cabs2(v[r]) * s2;
+    wstore<N, ROW, MID>(iv, Iout, N, l, c);
+}
+
+// Recompute phi_s (COL, NAT) with the forward's own slice steps, starting
+// from the last kept checkpoint at or before slice s-1 (or from the shifted
+// probe when none is kept), so that for s > 0 the last step also yields
+// Y'_s, written to spec.  Recomputed values are bitwise those of the forward.
+template <int N>
+__device__ __forceinline__ void recompute_phi(float2 (&v)[16], int s, const WaveArgs& a, const Slots<N>& sl, int m,
+                                              int ty, int tx, float2* spec, float2* lds, const Tables<N>& t, int l,
+                                              int c) {
+    int s0 = 0;
+    if (a.ckK <= a.S) {
+        s0 = s > 0 ? ((s - 1) / a.ckK) * a.ckK : 0;
+        wload<N, COL, NAT>(v, sl.ckpt(s0 / a.ckK), N, l, c);
     } else {
-        fft2_from_row<N>(v, lds, tab.tw, l, c);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            int y, x;
-            reg_yx<N, COL, MID>(l, c, r, y, x);
-            Iout[((y + N / 2) % N) * N + (x + N / 2) % N] = cabs2(v[r]) * s2;
-        }
+        shift_probe<N>(v, a.Phat + (size_t)m * N * N, lds, t, l, c);
     }
+    const size_t HW = (size_t)a.H * a.W;
+    for (int u = s0; u < s; ++u)
+        slice_step<N>(v, a.Oc + (size_t)u * HW, a.W, ty, tx, u == s - 1 ? spec : nullptr, lds, t, l, c);
 }
 
 // Gradient: one workgroup per (batch row j, probe mode m).  Walks the slices
-// backwards (chain rule through Eq. 2-4), writing per-slice object-patch
-// gradients, the probe-spectrum gradient and partial sums for the position,
+// backwards (chain rule through Eq. 2-4) holding only the adjoint field G in
+// registers; phi_s, Y_s and the far field are streamed from the store
+// (KEEP = KEEP_FULL) or recomputed into the chain's scratch (KEEP_CKPT).
+// Writes per-slice object-patch gradients conj(phi_s) G_chi, the
+// probe-spectrum gradient conj(R) G^_0 and partial sums for the position,
 // tilt and dz gradients.
-template <int N>
+template <int N, int KEEP>
 __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     constexpr int L = N / 16;
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ Tables<N> tab;
-    __shared__ float red[16 * 8];
     const int l = threadIdx.x / L, c = threadIdx.x % L;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int j = wg / a.M, m = wg % a.M;
@@ -310,79 +284,110 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
         return;   // the object-gradient scatter skips such rows
     }
     const float* th = a.global_tilt ? a.tilt : a.tilt + 2 * pi.row;
-    const float dz = *a.dz;
-    build_tables<N>(tab, a, pi, th[0], th[1], dz);
+    build_tables<N>(tab, a, pi, th[0], th[1], *a.dz);
+    const Slots<N> sl(a, j * a.M + m);
     const size_t HW = (size_t)a.H * a.W;
     const float inv_n = 1.0f / N, inv_n2 = 1.0f / ((float)N * N);
 
-    float2 g[16], p[16];
-    // G_chi_{S-1} = F^-1[ w * F[chi_{S-1}] ]   (w = 2 dL/dI)
-    incident_wave<N>(g, a.S - 1, a, j, m, pi.ty, pi.tx, lds, tab, l, c);
-    transmit<N, COL>(g, a.Oc + (size_t)(a.S - 1) * HW, a.W, pi.ty, pi.tx, l, c);
-    fft2_from_col<N>(g, lds, tab.tw, l, c);
-    const float* wj = a.wgt + (size_t)j * N * N;
+    float2 g[16];
+    // far field: kept, or recomputed from phi_{S-1}
+    if (KEEP == KEEP_FULL) {
+        wload<N, ROW, MID>(g, sl.far(), N, l, c);
+    } else {
+        recompute_phi<N>(g, a.S - 1, a, sl, m, pi.ty, pi.tx, sl.sc_spec(), lds, tab, l, c);
+        transmit<N>(g, a.Oc + (size_t)(a.S - 1) * HW, a.W, pi.ty, pi.tx, l, c);
+        fft2_from_col<N>(g, lds, tab.tw, l, c);
+    }
+    {   // G_chi_{S-1} = F^-1[ w F[chi_{S-1}] ]   (w = 2 dL/dI)
+        float wv[16];
+        wload<N, ROW, MID>(wv, a.wgt + (size_t)j * N * N, N, l, c);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        int y, x;
-        reg_yx<N, ROW, MID>(l, c, r, y, x);
-        g[r] = cscale(g[r], wj[((y + N / 2) % N) * N + (x + N / 2) % N] * inv_n2);
+        for (int r = 0; r < 16; ++r) g[r] = cscale(g[r], wv[r] * inv_n2);
     }
     ifft2_to_col<N>(g, lds, tab.tw, l, c);
 
-    float acc_k2 = 0.f, acc_kx = 0.f, acc_ky = 0.f, acc_py = 0.f, acc_px = 0.f;
-    const float dk = (float)(1.0 / (N * a.dx));
-    for (int s = a.S - 1; s >= 0; --s) {
-        const float2* Os = a.Oc + (size_t)s * HW;
-        incident_wave<N>(p, s, a, j, m, pi.ty, pi.tx, lds, tab, l, c);
+    using YC = Lay<N, COL, NAT>;
+    using YR = Lay<N, ROW, MID>;
+    const unsigned oN = YC::toff(l, c, N);
+    const unsigned oW = YC::toff(l, c, a.W);
+    const unsigned oM = YR::toff(l, c, N);
+
+    // chi_s = O_s phi_s: gO_s = conj(phi_s) G_chi, then G_phi = conj(O_s) G_chi,
+    // then G^ = F_raw G_phi.  Returns the stream of Y'_s for s > 0.
+    auto slice_back = [&](int s) -> const float2* {
+        const float2 *phi_s, *Y_s;
+        if (KEEP == KEEP_FULL) {
+            phi_s = sl.phi(s);
+            Y_s = s > 0 ? sl.spec(s) : nullptr;
+        } else {
+            // park G, recompute phi_s and Y'_s into the scratch, take G back
+            wstore<N, COL, NAT>(g, sl.sc_g(), N, l, c);
+            recompute_phi<N>(g, s, a, sl, m, pi.ty, pi.tx, sl.sc_spec(), lds, tab, l, c);
+            wstore<N, COL, NAT>(g, sl.sc_phi(), N, l, c);
+            wload<N, COL, NAT>(g, sl.sc_g(), N, l, c);
+            phi_s = sl.sc_phi();
+            Y_s = sl.sc_spec();
+        }
+        const float2* Os = a.Oc + (size_t)s * HW + (size_t)pi.ty * a.W + pi.tx;
         float2* go = a.gO + ((size_t)(j * a.M + m) * a.S + s) * N * N;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            int y, x;
-            reg_yx<N, COL, NAT>(l, c, r, y, x);
-            go[y * N + x] = cmulc(g[r], p[r]);                       // conj(phi) G_chi
-            float2 o = Os[(size_t)(pi.ty + y) * a.W + pi.tx + x];
-            g[r] = cmulc(g[r], o);                                    // G_phi = conj(O) G_chi
+            const float2 ph = (phi_s + YC::dy(r) * N)[oN];
+            (go + YC::dy(r) * N)[oN] = cmulc(g[r], ph);                       // conj(phi) G_chi
+            g[r] = cmulc(g[r], (Os + YC::dy(r) * a.W)[oW]);                    // G_phi = conj(O) G_chi
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
-        if (s > 0) {
-            fft2_from_col<N>(p, lds, tab.tw, l, c);   // Y = F phi_s (raw)
-            fft2_from_col<N>(g, lds, tab.tw, l, c);   // G^ = F G_phi (raw)
+        fft2_from_col<N>(g, lds, tab.tw, l, c);                               // G^ = F_raw G_phi
+        return Y_s;
+    };
+
+    float acc_k2 = 0.f, acc_kx = 0.f, acc_ky = 0.f;
+    const float dk = (float)(1.0 / (N * a.dx));
+    const float ky = sfreq<N>(l) * dk;
+    for (int s = a.S - 1; s >= 1; --s) {
+        const float2* Y_s = slice_back(s);
+        // dL/d(dz, th) += sum_k dPhi/dt(k) Im(G^ conj(Y)), Y = F phi_s (raw G^ x Y')
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                int y, x;
-                reg_yx<N, ROW, MID>(l, c, r, y, x);
-                float e = g[r].y * p[r].x - g[r].x * p[r].y;          // Im(G^ conj(Y))
-                float ky = sfreq<N>(y) * dk, kx = sfreq<N>(x) * dk;
-                acc_k2 = fmaf(e, kx * kx + ky * ky, acc_k2);
-                acc_kx = fmaf(e, kx, acc_kx);
-                acc_ky = fmaf(e, ky, acc_ky);
-                g[r] = cscale(tmul<true>(tmul<true>(g[r], tab.hy[y]), tab.hx[x]), inv_n2);   // conj(H) G^ / N^2
-            }
-            ifft2_to_col<N>(g, lds, tab.tw, l, c);                    // G_chi_{s-1}
-        } else {
-            fft2_from_col<N>(g, lds, tab.tw, l, c);                   // G^_0 (raw)
-            const float2* Pm = a.Phat + (size_t)m * N * N;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                int y, x;
-                reg_yx<N, ROW, MID>(l, c, r, y, x);
-                float2 G0 = cscale(g[r], inv_n);
-                float2 R = cmul(ramp<N>(y, tab.dry), ramp<N>(x, tab.drx));
-                gP[y * N + x] = cmulc(G0, R);                          // conj(R) G^_0
-                float2 z = cmulc(cmul(Pm[y * N + x], R), G0);          // Phat R conj(G^_0)
-                acc_py = fmaf(z.y, (float)sfreq<N>(y) * inv_n, acc_py);
-                acc_px = fmaf(z.y, (float)sfreq<N>(x) * inv_n, acc_px);
-            }
+        for (int r = 0; r < 16; ++r) {
+            const float2 y = (Y_s + YR::dx(r))[oM];
+            const float e = g[r].y * y.x - g[r].x * y.y;
+            const float kx = sfreq<N>(line_pos<N, MID>(c, r)) * dk;
+            acc_k2 = fmaf(e, kx * kx + ky * ky, acc_k2);
+            acc_kx = fmaf(e, kx, acc_kx);
+            acc_ky = fmaf(e, ky, acc_ky);
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
+        apply_h<N, true>(g, tab, inv_n2, l, c);                               // conj(H) G^ / N^2
+        ifft2_to_col<N>(g, lds, tab.tw, l, c);                                // G_chi_{s-1}
     }
-    float sums[5] = {acc_k2 * inv_n2, acc_kx * inv_n2, acc_ky * inv_n2, acc_py, acc_px};
-    block_sum<5>(sums, red);
+    slice_back(0);
+    // probe spectrum and position: phi_0 = F^-1[Phat R]
+    float acc_py = 0.f, acc_px = 0.f;
+    {
+        const float2* Pm = a.Phat + (size_t)m * N * N;
+        const float2 ry = tab.ry[l];
+        const float qy = (float)sfreq<N>(l) * inv_n;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int x = line_pos<N, MID>(c, r);
+            const float2 G0 = cscale(g[r], inv_n);
+            const float2 R = cmul(ry, tab.rx[x]);
+            g[r] = cmulc(G0, R);                                               // conj(R) G^_0
+            const float2 z = cmulc(cmul((Pm + YR::dx(r))[oM], R), G0);         // Phat R conj(G^_0)
+            acc_py = fmaf(z.y, qy, acc_py);
+            acc_px = fmaf(z.y, (float)sfreq<N>(x) * inv_n, acc_px);
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        wstore<N, ROW, MID>(g, gP, N, l, c);
+    }
+    float sums[5] = {acc_k2, acc_kx, acc_ky, acc_py, acc_px};
+    block_sum<5>(sums, reinterpret_cast<float*>(lds));   // the exchange buffer is free again
     if (threadIdx.x == 0) {
         for (int k = 0; k < 5; ++k) part[k] = sums[k];
         part[5] = part[6] = part[7] = 0.f;
     }
 }
 
-// Orthonormal 2-D DFT of sign SG of `count` N x N waves; out = or += result.
 template <int N, int SG, bool ACC>
 __global__ __launch_bounds__(N * N / 16) void k_fft2(const float2* in, float2* out) {
     constexpr int L = N / 16;
@@ -398,24 +403,16 @@ __global__ __launch_bounds__(N * N / 16) void k_fft2(const float2* in, float2* o
     const float2* src = in + (size_t)blockIdx.x * N * N;
     float2* dst = out + (size_t)blockIdx.x * N * N;
     float2 v[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        int y, x;
-        reg_yx<N, ROW, NAT>(l, c, r, y, x);
-        v[r] = src[y * N + x];
-    }
+    wload<N, ROW, NAT>(v, src, N, l, c);
     nat2mid<N, SG>(v, lds, tw, l, c);
     relayout<N, ROW, MID, COL, NAT>(v, lds, l, c);
     nat2mid<N, SG>(v, lds, tw, l, c);
     const float sc = 1.0f / N;
+    float2 o[16];
+    if (ACC) wload<N, COL, MID>(o, dst, N, l, c);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        int y, x;
-        reg_yx<N, COL, MID>(l, c, r, y, x);
-        float2 val = cscale(v[r], sc);
-        if (ACC) val = cadd(val, dst[y * N + x]);
-        dst[y * N + x] = val;
-    }
+    for (int r = 0; r < 16; ++r) o[r] = ACC ? cadd(cscale(v[r], sc), o[r]) : cscale(v[r], sc);
+    wstore<N, COL, MID>(o, dst, N, l, c);
 }
 
 }  // namespace ptyr

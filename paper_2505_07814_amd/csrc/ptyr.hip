@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/ptyr.h"
 #include "kernels.hpp"
@@ -67,12 +68,20 @@ __global__ void k_positions(const float* pos, const int* idx, int n_rows, int B,
     out[j] = pi;
 }
 
-// I[j] = sum_m Imode[j][m]  (fixed order)
-__global__ void k_modesum(const float* Imode, float* I, int B, int M, int NN) {
+// fftshift index of an N x N array (its own inverse for even N)
+__device__ __forceinline__ int shift_index(int q, int N) {
+    int y = q / N, x = q % N;
+    return ((y + N / 2) % N) * N + (x + N / 2) % N;
+}
+
+// I[j] (zero frequency at (N/2, N/2)) = sum_m Imode[j][m] (zero frequency at (0, 0)), fixed order
+__global__ void k_modesum(const float* Imode, float* I, int B, int M, int N) {
+    const int NN = N * N;
     size_t n = (size_t)B * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        size_t j = e / NN, p = e % NN;
-        const float* src = Imode + j * M * NN + p;
+        size_t j = e / NN;
+        int q = (int)(e % NN);
+        const float* src = Imode + j * M * NN + shift_index(q, N);
         float s = 0.f;
         for (int m = 0; m < M; ++m) s += src[(size_t)m * NN];
         I[e] = s;
@@ -153,17 +162,20 @@ __global__ void k_loss_final(const double* part, int nblk, double K, int kind, i
     }
 }
 
-// dL/dI per value (and w = 2 dL/dI for the gradient kernel)
-__global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int NN,
+// dL/dI per value (layout of I_model) and w = 2 dL/dI for the gradient kernel
+// (zero frequency at (0, 0))
+__global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int N,
                             int kind, double p, const double* scal, float* dLdI, float* w2) {
+    const int NN = N * N;
     const double c = scal[1];
     size_t n = (size_t)B * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         size_t j = e / NN, q = e % NN;
         long row = midx ? (long)midx[j] : (long)j;
+        const size_t e2 = j * NN + shift_index((int)q, N);
         if (row < 0 || row >= n_meas) {
             if (dLdI) dLdI[e] = 0.f;
-            if (w2) w2[e] = 0.f;
+            if (w2) w2[e2] = 0.f;
             continue;
         }
         double I = fmax((double)Im[e], 0.0), Em = fmax((double)Ie[(size_t)row * NN + q], 0.0);
@@ -173,7 +185,7 @@ __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, i
         if (p == 1.0) dI = dA;
         else dI = I > 0.0 ? dA * p * pow(I, p - 1.0) : 0.0;
         if (dLdI) dLdI[e] = (float)dI;
-        if (w2) w2[e] = (float)(2.0 * dI);
+        if (w2) w2[e2] = (float)(2.0 * dI);
     }
 }
 
@@ -287,26 +299,37 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, err, store, gO, gPhat, gPsum, part, gamp, gphase,
         gprobe, gdz, gpos, gtilt, total;
-    int ckK, nck;
+    int keep, ckK, nck, waves_per_chain;
 };
 
-int checkpoint_stride(const ptyr_geom* g) {
+// How the forward keeps waves under the budget (in waves of N x N complex
+// per chain, B_max * M chains): all 2S (phi_s, Y_s, far field) -> stride 1;
+// else a 3-wave scratch plus checkpoints of phi every K >= 2 slices; with no
+// room for a checkpoint, K = S + 1 (recompute from the probe).
+void keep_plan(const ptyr_geom* g, int* keep, int* K, int* nck) {
     size_t per = (size_t)g->B_max * g->M * g->N * g->N * sizeof(float2);
-    if (per == 0) return g->S + 1;
-    size_t fit = g->wave_budget_bytes / per;     // waves per chain that fit
-    if (fit >= (size_t)g->S) return 1;
-    if (fit == 0) return g->S + 1;
-    // keep ceil(S / K) waves per chain
-    int K = (int)((g->S + fit - 1) / fit);
-    while ((size_t)((g->S + K - 1) / K) > fit) ++K;
+    size_t fit = g->wave_budget_bytes / per;
+    if (fit >= (size_t)(2 * g->S)) { *keep = KEEP_FULL; *K = 1; *nck = 0; return; }
+    *keep = KEEP_CKPT;
+    size_t avail = fit > 3 ? fit - 3 : 0;
+    if (avail == 0) { *K = g->S + 1; *nck = 0; return; }
+    int k = std::max(2, (int)((g->S + avail - 1) / avail));
+    while ((size_t)((g->S + k - 1) / k) > avail) ++k;
+    *K = k;
+    *nck = (g->S + k - 1) / k;
+}
+
+int checkpoint_stride(const ptyr_geom* g) {
+    int keep, K, nck;
+    keep_plan(g, &keep, &K, &nck);
     return K;
 }
 
 Layout make_layout(const ptyr_geom* g) {
     Layout L;
     const size_t NN = (size_t)g->N * g->N, HW = (size_t)g->H * g->W, B = g->B_max, M = g->M, S = g->S;
-    L.ckK = checkpoint_stride(g);
-    L.nck = L.ckK <= g->S ? (g->S + L.ckK - 1) / L.ckK : 0;
+    keep_plan(g, &L.keep, &L.ckK, &L.nck);
+    L.waves_per_chain = L.keep == KEEP_FULL ? 2 * g->S : L.nck + 3;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     L.Oc = take(S * HW * sizeof(float2));
@@ -318,7 +341,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.lpart = take(3 * NPART * sizeof(double));
     L.scal = take(8 * sizeof(double));
     L.err = take(sizeof(int));
-    L.store = take(B * M * (size_t)L.nck * NN * sizeof(float2));
+    L.store = take(B * M * (size_t)L.waves_per_chain * NN * sizeof(float2));
     L.gO = take(B * M * S * NN * sizeof(float2));
     L.gPhat = take(B * M * NN * sizeof(float2));
     L.gPsum = take(M * NN * sizeof(float2));
@@ -348,7 +371,30 @@ struct ptyr_ctx {
     Layout L;
     int fwd_valid;   // waves / intensities of the last forward are in the workspace
     int fwd_B;
+    // instrumentation: event pairs around the fused kernels
+    int timing = 0;
+    std::vector<hipEvent_t> ev;      // 2 per launch
+    std::vector<int> ev_kind;
+    int ev_used = 0;
 };
+
+namespace {
+constexpr int MAX_TIMED = 4096;
+struct TimedLaunch {
+    ptyr_ctx* c;
+    int slot;
+    TimedLaunch(ptyr_ctx* cc, int kind) : c(cc), slot(-1) {
+        if (c->timing && c->ev_used < MAX_TIMED) {
+            slot = c->ev_used++;
+            c->ev_kind[slot] = kind;
+            hipEventRecord(c->ev[2 * slot], c->stream);
+        }
+    }
+    ~TimedLaunch() {
+        if (slot >= 0) hipEventRecord(c->ev[2 * slot + 1], c->stream);
+    }
+};
+}  // namespace
 
 template <typename T> static T* at(ptyr_ctx* c, size_t off) { return reinterpret_cast<T*>(c->ws + off); }
 
@@ -432,7 +478,41 @@ ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, vo
     return PTYR_OK;
 }
 
-void ptyr_destroy(ptyr_ctx* ctx) { delete ctx; }
+void ptyr_destroy(ptyr_ctx* ctx) {
+    if (!ctx) return;
+    for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+    delete ctx;
+}
+
+ptyr_status ptyr_timing_enable(ptyr_ctx* c, int on) {
+    if (!c) return PTYR_E_ARG;
+    if (on && c->ev.empty()) {
+        c->ev.resize(2 * MAX_TIMED);
+        c->ev_kind.assign(MAX_TIMED, -1);
+        for (auto& e : c->ev)
+            if (hipEventCreate(&e) != hipSuccess) return PTYR_E_DEVICE;
+    }
+    c->timing = on ? 1 : 0;
+    c->ev_used = 0;
+    return PTYR_OK;
+}
+
+ptyr_status ptyr_timing_read(ptyr_ctx* c, int which, double* total_ms, int* launches) {
+    if (!c || !total_ms || !launches) return PTYR_E_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return PTYR_E_DEVICE;
+    double tot = 0.0;
+    int n = 0;
+    for (int i = 0; i < c->ev_used; ++i) {
+        if (c->ev_kind[i] != which) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) return PTYR_E_DEVICE;
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    return PTYR_OK;
+}
 
 ptyr_status ptyr_sync(ptyr_ctx* ctx) {
     if (!ctx) return PTYR_E_ARG;
@@ -463,7 +543,8 @@ WaveArgs wave_args(ptyr_ctx* c, const float* tilt, const float* dz, int B) {
     a.pinfo = at<PosInfo>(c, c->L.pinfo);
     a.tilt = tilt;
     a.dz = dz;
-    a.store = c->L.nck ? at<float2>(c, c->L.store) : nullptr;
+    a.store = at<float2>(c, c->L.store);
+    a.keep = c->L.keep;
     a.ckK = c->L.ckK;
     a.nck = c->L.nck;
     a.B = B; a.M = g.M; a.S = g.S; a.H = g.H; a.W = g.W;
@@ -479,10 +560,15 @@ WaveArgs wave_args(ptyr_ctx* c, const float* tilt, const float* dz, int B) {
 }
 
 template <int N> void launch_forward(ptyr_ctx* c, const WaveArgs& a, int B) {
+    TimedLaunch t(c, PTYR_K_FORWARD);
     hipLaunchKernelGGL(k_forward<N>, dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
 }
 template <int N> void launch_gradient(ptyr_ctx* c, const WaveArgs& a, int B) {
-    hipLaunchKernelGGL(k_gradient<N>, dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
+    TimedLaunch t(c, PTYR_K_GRADIENT);
+    if (a.keep == KEEP_FULL)
+        hipLaunchKernelGGL((k_gradient<N, KEEP_FULL>), dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((k_gradient<N, KEEP_CKPT>), dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
 }
 template <int N> void launch_probe_fft(ptyr_ctx* c, const float* probe) {
     hipLaunchKernelGGL((k_fft2<N, -1, false>), dim3(c->g.M), dim3(N * N / 16), 0, c->stream,
@@ -506,7 +592,7 @@ ptyr_status run_forward(ptyr_ctx* c, const float* amp, const float* phase, const
     else { launch_probe_fft<128>(c, probe); launch_forward<128>(c, a, B); }
     size_t NN = (size_t)g.N * g.N;
     hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)B * NN)), dim3(256), 0, c->stream,
-                       at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, (int)NN);
+                       at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, g.N);
     if (hipGetLastError() != hipSuccess) return PTYR_E_DEVICE;
     c->fwd_valid = 1;
     c->fwd_B = B;
@@ -526,7 +612,7 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
                        g.loss_kind, (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
                        at<int>(c, c->L.err));
     if (dLdI || w2)
-        hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN,
+        hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, g.N,
                            g.loss_kind, g.loss_p, at<double>(c, c->L.scal), dLdI, w2);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
@@ -543,7 +629,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     } else {
         size_t NN = (size_t)g.N * g.N;
         hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)B * NN)), dim3(256), 0, c->stream,
-                           at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, (int)NN);
+                           at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, g.N);
     }
     st = run_loss(c, at<float>(c, c->L.Ibuf), I_meas, idx, n_rows, B, loss_dev, nullptr, at<float>(c, c->L.wbuf));
     if (st != PTYR_OK) return st;

@@ -183,6 +183,36 @@ template <int N, int D, int K> __device__ __forceinline__ void reg_yx(int l, int
     else { y = n; x = l; }
 }
 
+// Affine split of a register's (y, x): y = yl + dy(r), x = xl + dx(r), with
+// (yl, xl) the thread part and (dy, dx) a compile-time register part, so an
+// element at row stride S sits at  [thread: yl*S + xl] + [uniform: dy*S + dx].
+// Memory accesses use that form (one 32-bit thread offset plus a scalar base
+// per register) instead of a 64-bit address per register.
+template <int N, int D, int K> struct Lay {
+    static constexpr int L = N / 16;
+    static constexpr int n_of(int r) { return K == NAT ? L * r : L * (r / L) + 16 * (r % L); }
+    static constexpr int dy(int r) { return D == ROW ? 0 : n_of(r); }
+    static constexpr int dx(int r) { return D == ROW ? n_of(r) : 0; }
+    __device__ static int yl(int l, int c) { return D == ROW ? l : c; }
+    __device__ static int xl(int l, int c) { return D == ROW ? c : l; }
+    __device__ static unsigned toff(int l, int c, int stride) { return (unsigned)(yl(l, c) * stride + xl(l, c)); }
+};
+
+template <int N, int D, int K, typename T>
+__device__ __forceinline__ void wload(T (&v)[16], const T* base, int stride, int l, int c) {
+    using Y = Lay<N, D, K>;
+    const unsigned o = Y::toff(l, c, stride);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = (base + (Y::dy(r) * stride + Y::dx(r)))[o];
+}
+template <int N, int D, int K, typename T>
+__device__ __forceinline__ void wstore(const T (&v)[16], T* base, int stride, int l, int c) {
+    using Y = Lay<N, D, K>;
+    const unsigned o = Y::toff(l, c, stride);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) (base + (Y::dy(r) * stride + Y::dx(r)))[o] = v[r];
+}
+
 // LDS slot of exchange element (line l, b, lane c')
 template <int N> __device__ __forceinline__ int slot_x(int l, int b, int c) {
     return l * WaveGeo<N>::SL + b * WaveGeo<N>::SB + c;
@@ -206,15 +236,25 @@ template <bool CONJ> __device__ __forceinline__ float2 tmul(float2 a, float4 w) 
                        fmaf(a.x, wi, fmaf(a.y, w.x, fmaf(a.x, li, a.y * w.z))));
 }
 
+// v[b] *= W_N^{SG c b} for b = 1..15 from the per-lane compensated table.
+// Scheduling fences keep at most four table entries (16 VGPRs) in flight;
+// left alone the scheduler hoists all fifteen 128-bit reads.
+template <int SG> __device__ __forceinline__ void twiddle_pass(float2 (&v)[16], const float4* twc) {
+#pragma unroll
+    for (int b0 = 1; b0 < 16; b0 += 4) {
+#pragma unroll
+        for (int b = b0; b < b0 + 4 && b < 16; ++b) v[b] = tmul<(SG > 0)>(v[b], twc[b]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // ------------------------------------------------------------ line transforms
 // NAT -> MID, DFT of sign SG along every line.
 template <int N, int SG>
 __device__ __forceinline__ void nat2mid(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
     constexpr int L = N / 16, G = 16 / L;
     dft16<SG>(v);
-    const float4* twc = tw + c * 16;
-#pragma unroll
-    for (int b = 1; b < 16; ++b) v[b] = tmul<(SG > 0)>(v[b], twc[b]);
+    twiddle_pass<SG>(v, tw + c * 16);
 #pragma unroll
     for (int b = 0; b < 16; ++b) lds[slot_x<N>(l, b, c)] = v[b];
     __syncthreads();
@@ -241,9 +281,7 @@ __device__ __forceinline__ void mid2nat(float2 (&v)[16], float2* lds, const floa
 #pragma unroll
     for (int b = 0; b < 16; ++b) v[b] = lds[slot_x<N>(l, b, c)];
     __syncthreads();
-    const float4* twc = tw + c * 16;
-#pragma unroll
-    for (int b = 1; b < 16; ++b) v[b] = tmul<(SG > 0)>(v[b], twc[b]);
+    twiddle_pass<SG>(v, tw + c * 16);
     dft16<SG>(v);
 }
 

@@ -42,8 +42,8 @@ class Engine:
 
     loss: 'gaussian' (Eq. 5, default p=0.5) or 'poisson' (Eq. 6, default p=1).
     wave_budget: bytes the forward may keep for the gradient (None = all
-    waves); below B_max*M*S*N*N*8 the gradient recomputes waves per slice from
-    checkpoints.  n_scan: positions addressable by step()."""
+    waves, B_max*M*2S*N*N*8); below that the gradient recomputes waves per
+    slice from checkpoints.  n_scan: positions addressable by step()."""
 
     def __init__(self, N, M, S, H, W, B_max, dx, lam, loss="gaussian", p=None, wave_budget=None,
                  global_tilt=False, check_finite=False, n_scan=0, device=None, stream=None):
@@ -52,7 +52,7 @@ class Engine:
         if p is None:
             p = 0.5 if kind == L.PTYR_LOSS_GAUSSIAN else 1.0
         if wave_budget is None:
-            wave_budget = B_max * M * S * N * N * 8
+            wave_budget = B_max * M * 2 * S * N * N * 8     # keep every slice's waves
         flags = (L.PTYR_GLOBAL_TILT if global_tilt else 0) | (L.PTYR_CHECK_FINITE if check_finite else 0)
         self.geom = L.Geom(N, M, S, H, W, B_max, float(dx), float(lam), kind, float(p),
                            int(wave_budget), flags, int(n_scan))
@@ -110,6 +110,21 @@ class Engine:
         elif rows < B:
             raise ValueError("fewer positions than the batch")
         return rows
+
+    def timing(self, on: bool = True):
+        """Bracket the fused kernels with HIP events on the engine's stream."""
+        L.check(self.lib.ptyr_timing_enable(self._ctx, 1 if on else 0), "ptyr_timing_enable")
+
+    def timing_read(self):
+        """{'forward': (total_ms, launches), 'gradient': (...)}; clears the record
+        (the record is read once, so both kernels are read together)."""
+        out = {}
+        for name, k in (("forward", L.PTYR_K_FORWARD), ("gradient", L.PTYR_K_GRADIENT)):
+            ms, n = C.c_double(), C.c_int()
+            L.check(self.lib.ptyr_timing_read(self._ctx, k, C.byref(ms), C.byref(n)), "ptyr_timing_read")
+            out[name] = (ms.value, n.value)
+        L.check(self.lib.ptyr_timing_enable(self._ctx, 1), "ptyr_timing_enable")
+        return out
 
     def sync(self):
         """Wait for the stream; raise on asynchronous errors (bounds, indices, non-finite)."""

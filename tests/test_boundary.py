@@ -20,7 +20,7 @@ def header_functions():
 
 def geom(**kw):
     d = dict(N=128, M=6, S=12, H=640, W=640, B_max=64, dx=0.15, lam=0.0197, loss_kind=0, loss_p=0.5,
-             wave_budget_bytes=64 * 6 * 12 * 128 * 128 * 8, flags=0, n_scan=16384)
+             wave_budget_bytes=64 * 6 * 24 * 128 * 128 * 8, flags=0, n_scan=16384)
     d.update(kw)
     return L.Geom(*[d[f[0]] for f in L.Geom._fields_])
 
@@ -83,8 +83,12 @@ def test_workspace_and_checkpoint_plan():
     none = geom(wave_budget_bytes=0)
     assert lib.ptyr_checkpoint_plan(C.byref(none), C.byref(k)) == L.PTYR_OK and k.value == 13
     per = 64 * 6 * 128 * 128 * 8
-    third = geom(wave_budget_bytes=4 * per)           # 4 kept waves of 12 slices -> stride 3
+    third = geom(wave_budget_bytes=(3 + 4) * per)     # scratch + 4 checkpoints of 12 slices -> stride 3
     assert lib.ptyr_checkpoint_plan(C.byref(third), C.byref(k)) == L.PTYR_OK and k.value == 3
+    almost = geom(wave_budget_bytes=(2 * 12 - 1) * per)   # one wave short of keeping everything
+    assert lib.ptyr_checkpoint_plan(C.byref(almost), C.byref(k)) == L.PTYR_OK and k.value == 2
+    scratch_only = geom(wave_budget_bytes=3 * per)
+    assert lib.ptyr_checkpoint_plan(C.byref(scratch_only), C.byref(k)) == L.PTYR_OK and k.value == 13
     assert lib.ptyr_workspace_bytes(C.byref(full)) > lib.ptyr_workspace_bytes(C.byref(none))
     assert lib.ptyr_workspace_bytes(C.byref(geom(N=96))) == 0
 
