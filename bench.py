@@ -103,6 +103,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--positions", type=int, default=0,
+                    help="use only the first P scan positions (profiling runs; 0 = all)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, copy a 512 MiB buffer 4 times (known-size kernel for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -117,7 +121,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    w = synth.workload(WORKLOAD)
+    w = synth.workload(WORKLOAD, scan=args.positions or None)
     B = args.batch
     lam = synth.wavelength_A(w.kv)
     n_pos = w.pos.shape[0]
@@ -191,6 +195,13 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, B)
+    if args.copy_calibration:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)     # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
     print(json.dumps(out), flush=True)
 
 

@@ -75,7 +75,7 @@ template <int N> struct Slots {
 // ------------------------------------------------------------------ tables
 // Per-workgroup LDS tables: twiddles and the separable propagator factors.
 template <int N> struct Tables {
-    float4 tw[N];          // per-lane twiddles: tw[c*16 + b] = exp(-2 pi i c b / N)
+    float4 tw[N];          // twiddles, b-major: tw[b*L + c] = exp(-2 pi i c b / N)
     float4 hy[N], hx[N];   // propagator factors along y and x (unscaled)
     float2 ry[N], rx[N];   // shift ramp factors exp(-2 pi i q_n dr_y), exp(-2 pi i q_n dr_x)
 };
@@ -90,7 +90,7 @@ __device__ __forceinline__ void build_tables(Tables<N>& t, const WaveArgs& a, co
         double q = (double)sfreq<N>(n) / N;            // cycles per pixel
         double k = q / a.dx;                            // 1/angstrom
         double ph;
-        if (which == 0) ph = -2.0 * pi_d * (double)((n / 16) * (n % 16)) / N;
+        if (which == 0) ph = -2.0 * pi_d * (double)((n / (N / 16)) * (n % (N / 16))) / N;
         else if (which == 1) ph = -pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan((double)thy);
         else if (which == 2) ph = -pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan((double)thx);
         else if (which == 3) ph = -2.0 * pi_d * q * pi.dry;
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(N * N / 16) void k_fft2(const float2* in, float2* o
     const int l = threadIdx.x / L, c = threadIdx.x % L;
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
         double s, co;
-        sincos(-2.0 * 3.14159265358979323846 * (double)((n / 16) * (n % 16)) / N, &s, &co);
+        sincos(-2.0 * 3.14159265358979323846 * (double)((n / (N / 16)) * (n % (N / 16))) / N, &s, &co);
         tw[n] = unit_pair(co, s);
     }
     __syncthreads();

@@ -193,6 +193,10 @@ __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, i
 // in batch order, the patch gradients of every (position, mode) covering it;
 // then applies the chain rule to amplitude and phase (O = a exp(i phase)):
 //   g_a += Re(conj(G) exp(i phase)),  g_phase += Im(G conj(O)).
+// A thread owns 4 consecutive pixels of a tile row; the loads of up to
+// MB modes of one position are issued together before they are added (in
+// mode order), to keep enough bytes in flight per workgroup.
+constexpr int SCATTER_MB = 8;
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int B, int M, int S,
                                                         int N, int H, int W, const float* amp, const float* phase,
                                                         float* g_amp, float* g_phase) {
@@ -200,31 +204,42 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
     const int tile = blockIdx.x, s = blockIdx.y;
     const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
     const int ly = threadIdx.x / 8, lx = (threadIdx.x % 8) * 4;
-    const int y = y0 + ly;
+    const int y = y0 + ly, xb = x0 + lx;
     float2 acc[4];
     for (int k = 0; k < 4; ++k) acc[k] = make_float2(0.f, 0.f);
     bool touched = false;
     const size_t NN = (size_t)N * N;
     for (int j = 0; j < B; ++j) {
-        PosInfo pi = pinfo[j];
+        const PosInfo pi = pinfo[j];
         if (pi.ty < 0) continue;
         if (pi.ty >= y0 + 32 || pi.ty + N <= y0 || pi.tx >= x0 + 32 || pi.tx + N <= x0) continue;
         touched = true;
-        int py = y - pi.ty;
+        const int py = y - pi.ty, px0 = xb - pi.tx;
         if (py < 0 || py >= N) continue;
-        for (int m = 0; m < M; ++m) {
-            const float2* src = gO + ((size_t)(j * M + m) * S + s) * NN + (size_t)py * N;
+        const bool all4 = px0 >= 0 && px0 + 3 < N;
+        for (int m0 = 0; m0 < M; m0 += SCATTER_MB) {
+            float2 buf[SCATTER_MB][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                int px = x0 + lx + k - pi.tx;
-                if (px >= 0 && px < N) acc[k] = cadd(acc[k], src[px]);
+            for (int mm = 0; mm < SCATTER_MB; ++mm) {
+                const int m = m0 + mm;
+                const float2* src = gO + ((size_t)(j * M + m) * S + s) * NN + (size_t)py * N;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int px = px0 + k;
+                    const bool in = m < M && (all4 || (px >= 0 && px < N));
+                    buf[mm][k] = in ? src[px] : make_float2(0.f, 0.f);
+                }
             }
+#pragma unroll
+            for (int mm = 0; mm < SCATTER_MB; ++mm)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k] = cadd(acc[k], buf[mm][k]);
         }
     }
     if (!touched || y >= H) return;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int x = x0 + lx + k;
+        int x = xb + k;
         if (x >= W) continue;
         size_t o = ((size_t)s * H + y) * W + x;
         float sn, cs;
@@ -250,32 +265,44 @@ __global__ void k_sum_rows(const float2* src, float2* dst, int B, int M, int NN)
 //   g_rho   = 2 pi sum_m sum_k q Im(Phat R conj(G^_0))
 //   g_th    = 2 pi dz sec^2(th) sum_s,m,k k Im(G^ conj(Y))
 //   g_dz    = sum [-pi lam |k|^2 + 2 pi (k_x tan th_x + k_y tan th_y)] Im(G^ conj(Y))
-__global__ void k_param_grads(const float* part, const PosInfo* pinfo, int B, int M, const float* tilt,
-                              int global_tilt, const float* dzp, double lam, float* g_pos, float* g_tilt,
-                              float* g_dz) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One thread per batch row (rows of a batch are distinct, so the row
+// updates do not collide); dz and a global tilt are summed over rows in
+// fixed order by a block tree.
+__global__ __launch_bounds__(256) void k_param_grads(const float* part, const PosInfo* pinfo, int B, int M,
+                                                     const float* tilt, int global_tilt, const float* dzp,
+                                                     double lam, float* g_pos, float* g_tilt, float* g_dz) {
+    __shared__ double sh[3][256];
     const double two_pi = 6.283185307179586;
     const double dz = *dzp;
-    double gdz = 0.0, gty = 0.0, gtx = 0.0;
-    for (int j = 0; j < B; ++j) {
+    double sdz = 0.0, sty = 0.0, stx = 0.0;
+    for (int j = threadIdx.x; j < B; j += blockDim.x) {
         if (pinfo[j].ty < 0) continue;
-        int row = pinfo[j].row;
+        const int row = pinfo[j].row;
         double k2 = 0, kx = 0, ky = 0, py = 0, px = 0;
         for (int m = 0; m < M; ++m) {
             const float* q = part + (size_t)(j * M + m) * 8;
             k2 += q[0]; kx += q[1]; ky += q[2]; py += q[3]; px += q[4];
         }
         const float* th = global_tilt ? tilt : tilt + 2 * row;
-        double ty = tan((double)th[0]), tx = tan((double)th[1]);
-        double cy = cos((double)th[0]), cx = cos((double)th[1]);
-        gdz += -3.141592653589793 * lam * k2 + two_pi * (tx * kx + ty * ky);
-        double gy = two_pi * dz * ky / (cy * cy), gx = two_pi * dz * kx / (cx * cx);
-        if (global_tilt) { gty += gy; gtx += gx; }
+        const double ty = tan((double)th[0]), tx = tan((double)th[1]);
+        const double cy = cos((double)th[0]), cx = cos((double)th[1]);
+        sdz += -3.141592653589793 * lam * k2 + two_pi * (tx * kx + ty * ky);
+        const double gy = two_pi * dz * ky / (cy * cy), gx = two_pi * dz * kx / (cx * cx);
+        if (global_tilt) { sty += gy; stx += gx; }
         else if (g_tilt) { g_tilt[2 * row] += (float)gy; g_tilt[2 * row + 1] += (float)gx; }
         if (g_pos) { g_pos[2 * row] += (float)(two_pi * py); g_pos[2 * row + 1] += (float)(two_pi * px); }
     }
-    if (global_tilt && g_tilt) { g_tilt[0] += (float)gty; g_tilt[1] += (float)gtx; }
-    if (g_dz) g_dz[0] += (float)gdz;
+    sh[0][threadIdx.x] = sdz; sh[1][threadIdx.x] = sty; sh[2][threadIdx.x] = stx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (global_tilt && g_tilt) { g_tilt[0] += (float)sh[1][0]; g_tilt[1] += (float)sh[2][0]; }
+        if (g_dz) g_dz[0] += (float)sh[0][0];
+    }
 }
 
 // Adam (PyTorch's form): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
@@ -649,7 +676,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         else launch_probe_ifft_acc<128>(c, g_probe);
     }
     if (g_pos || g_tilt || g_dz)
-        hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(64), 0, c->stream, at<float>(c, c->L.part),
+        hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(256), 0, c->stream, at<float>(c, c->L.part),
                            at<PosInfo>(c, c->L.pinfo), B, g.M, tilt, a.global_tilt, dz, g.lambda, g_pos, g_tilt,
                            g_dz);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;

@@ -236,14 +236,15 @@ template <bool CONJ> __device__ __forceinline__ float2 tmul(float2 a, float4 w) 
                        fmaf(a.x, wi, fmaf(a.y, w.x, fmaf(a.x, li, a.y * w.z))));
 }
 
-// v[b] *= W_N^{SG c b} for b = 1..15 from the per-lane compensated table.
+// v[b] *= W_N^{SG c b} for b = 1..15 from the compensated table, stored
+// b-major (tw[b*L + c]) so that the lanes of a wave read consecutive entries.
 // Scheduling fences keep at most four table entries (16 VGPRs) in flight;
 // left alone the scheduler hoists all fifteen 128-bit reads.
-template <int SG> __device__ __forceinline__ void twiddle_pass(float2 (&v)[16], const float4* twc) {
+template <int L, int SG> __device__ __forceinline__ void twiddle_pass(float2 (&v)[16], const float4* twc) {
 #pragma unroll
     for (int b0 = 1; b0 < 16; b0 += 4) {
 #pragma unroll
-        for (int b = b0; b < b0 + 4 && b < 16; ++b) v[b] = tmul<(SG > 0)>(v[b], twc[b]);
+        for (int b = b0; b < b0 + 4 && b < 16; ++b) v[b] = tmul<(SG > 0)>(v[b], twc[b * L]);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -254,7 +255,7 @@ template <int N, int SG>
 __device__ __forceinline__ void nat2mid(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
     constexpr int L = N / 16, G = 16 / L;
     dft16<SG>(v);
-    twiddle_pass<SG>(v, tw + c * 16);
+    twiddle_pass<L, SG>(v, tw + c);
 #pragma unroll
     for (int b = 0; b < 16; ++b) lds[slot_x<N>(l, b, c)] = v[b];
     __syncthreads();
@@ -281,7 +282,7 @@ __device__ __forceinline__ void mid2nat(float2 (&v)[16], float2* lds, const floa
 #pragma unroll
     for (int b = 0; b < 16; ++b) v[b] = lds[slot_x<N>(l, b, c)];
     __syncthreads();
-    twiddle_pass<SG>(v, tw + c * 16);
+    twiddle_pass<L, SG>(v, tw + c);
     dft16<SG>(v);
 }
 

@@ -1,0 +1,73 @@
+"""Summarise rocprofv3 counter runs of bench.py into profiles/*.txt.
+
+FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of a kernel are scaled by the
+ratio (known bytes / counted bytes) of a plain device copy of known size
+measured in the same run, and written with the hash of the kernel sources
+so that bench.py can tell whether they still describe the current kernels.
+
+usage: python -m paper_2505_07814_amd.profile_summary FETCH_CSV WRITE_CSV
+           KERNEL_SUBSTRING OUT_TXT COMMAND...
+"""
+import csv
+import hashlib
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2505_07814_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def per_kernel(path, counter):
+    """{kernel name: [values of counter per dispatch]}"""
+    out = {}
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def main(argv):
+    fetch_csv, write_csv, kname, out_txt = argv[:4]
+    cmd = " ".join(argv[4:])
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    copy_f = [v for k, v in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+    copy_w = [v for k, v in write.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+    big_f = max((x for vals in copy_f for x in vals), default=0.0)
+    big_w = max((x for vals in copy_w for x in vals), default=0.0)
+    known = 512.0 * 1024                                  # KiB read and written by one copy
+    kf = known / big_f if big_f else float("nan")
+    kw = known / big_w if big_w else float("nan")
+    kf_vals = [v for k, vals in fetch.items() if kname in k for v in vals]
+    kw_vals = [v for k, vals in write.items() if kname in k for v in vals]
+    af = sum(kf_vals) / len(kf_vals)
+    aw = sum(kw_vals) / len(kw_vals)
+    hbm = (af * kf + aw * kw) * 1024
+    lines = [
+        f"# HBM traffic of {kname} (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)",
+        f"# command: {cmd}",
+        f"# dispatches: fetch {len(kf_vals)}, write {len(kw_vals)}",
+        f"# copy calibration (512 MiB device copy): FETCH_SIZE {big_f:.0f} KiB, WRITE_SIZE {big_w:.0f} KiB",
+        f"fetch_kib_per_launch = {af:.1f}",
+        f"write_kib_per_launch = {aw:.1f}",
+        f"fetch_scale = {kf:.4f}",
+        f"write_scale = {kw:.4f}",
+        f"hbm_bytes_per_launch = {hbm:.0f}",
+        f"source_hash = {source_hash()}",
+    ]
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
