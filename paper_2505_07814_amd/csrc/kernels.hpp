@@ -130,24 +130,24 @@ __device__ __forceinline__ void shift_probe(float2 (&v)[16], const float2* Pm, f
     const float2 ru = cscale(t.ry[l], sc);
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = cmul(cmul(v[r], ru), t.rx[line_pos<N, MID>(c, r)]);
-    mid2nat<N, +1>(v, lds, t.tw, l, c);
+    mid2nat<WaveGeo<N>, +1>(v, lds, t.tw, l, c);
     relayout<N, ROW, NAT, COL, MID>(v, lds, l, c);
-    mid2nat<N, +1>(v, lds, t.tw, l, c);
+    mid2nat<WaveGeo<N>, +1>(v, lds, t.tw, l, c);
 }
 
 // unnormalised 2-D DFT of sign -1 from (COL, NAT); leaves in (ROW, MID)
 template <int N>
 __device__ __forceinline__ void fft2_from_col(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
-    nat2mid<N, -1>(v, lds, tw, l, c);
+    nat2mid<WaveGeo<N>, -1>(v, lds, tw, l, c);
     relayout<N, COL, MID, ROW, NAT>(v, lds, l, c);
-    nat2mid<N, -1>(v, lds, tw, l, c);
+    nat2mid<WaveGeo<N>, -1>(v, lds, tw, l, c);
 }
 // unnormalised 2-D inverse DFT from (ROW, MID); leaves in (COL, NAT)
 template <int N>
 __device__ __forceinline__ void ifft2_to_col(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
-    mid2nat<N, +1>(v, lds, tw, l, c);
+    mid2nat<WaveGeo<N>, +1>(v, lds, tw, l, c);
     relayout<N, ROW, NAT, COL, MID>(v, lds, l, c);
-    mid2nat<N, +1>(v, lds, tw, l, c);
+    mid2nat<WaveGeo<N>, +1>(v, lds, tw, l, c);
 }
 
 // Multiply a (ROW, MID) spectrum by H (or conj(H)) and a scale.
@@ -404,9 +404,9 @@ __global__ __launch_bounds__(N * N / 16) void k_fft2(const float2* in, float2* o
     float2* dst = out + (size_t)blockIdx.x * N * N;
     float2 v[16];
     wload<N, ROW, NAT>(v, src, N, l, c);
-    nat2mid<N, SG>(v, lds, tw, l, c);
+    nat2mid<WaveGeo<N>, SG>(v, lds, tw, l, c);
     relayout<N, ROW, MID, COL, NAT>(v, lds, l, c);
-    nat2mid<N, SG>(v, lds, tw, l, c);
+    nat2mid<WaveGeo<N>, SG>(v, lds, tw, l, c);
     const float sc = 1.0f / N;
     float2 o[16];
     if (ACC) wload<N, COL, MID>(o, dst, N, l, c);

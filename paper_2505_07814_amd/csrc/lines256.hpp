@@ -1,0 +1,330 @@
+// lines256.hpp - the multislice forward model and its gradient for N = 256.
+//
+// A 256 x 256 complex64 wave (512 KiB) does not fit one compute unit, so it
+// stays in device memory (L2 / Infinity Cache resident for the batch) and
+// each slice is two line passes over all (row, mode) chains of the batch:
+//
+//   row pass    : inverse DFT along x, keep phi_s, transmit by O_s, DFT along x
+//   column pass : DFT along y (full 2-D spectrum), multiply by H, keep Y_s,
+//                 inverse DFT along y
+//
+// A workgroup transforms 16 lines of 256 points with the register / LDS line
+// machinery of wave.hpp (16 lanes per line, 16 values per lane).  Row passes
+// map lanes along x and column passes map lanes across the 16 columns, so
+// both read and write 128-byte contiguous segments.  The gradient runs the
+// same two passes per slice in reverse with the adjoint operations.
+#pragma once
+#include "kernels.hpp"
+
+namespace ptyr {
+
+constexpr int N256 = 256;
+constexpr int LINES256 = 16;                   // lines per workgroup
+constexpr int NBLK256 = N256 / LINES256;       // line blocks per wave
+
+// lanes along the line (row passes): thread = line * 16 + lane
+struct RowGeo256 { static constexpr int NL = 256, L = 16, SB = 17, SL = 272; };
+// lanes across lines (column passes): thread = lane * 16 + line
+struct ColGeo256 { static constexpr int NL = 256, L = 16, SB = 17, SL = 274; };
+constexpr int LDS256 = (LINES256 - 1) * 274 + 15 * 17 + 16;
+
+struct Tables256 {
+    float4 tw[N256];       // tw[b*16 + c] = exp(-2 pi i c b / 256)
+    float4 h[N256];        // propagator factor along the pass direction
+    float2 r[N256];        // shift ramp along the pass direction
+    float4 hl[LINES256];   // propagator factor of each line of the block (column passes)
+    float2 rl[LINES256];   // shift ramp of each line of the block (column passes)
+};
+
+// Build the twiddles and, for a position, the propagator / ramp factors along
+// the pass direction (AXIS 0: y, 1: x) for all 256 frequencies, and the
+// factors of the block's 16 lines along the other axis.
+template <int AXIS>
+__device__ __forceinline__ void build256(Tables256& t, const WaveArgs& a, const PosInfo& pi, int line0) {
+    const double pi_d = 3.14159265358979323846;
+    const float* th = a.global_tilt ? a.tilt : a.tilt + 2 * pi.row;
+    const double dz = *a.dz;
+    const double tan_p = tan((double)th[AXIS]), tan_o = tan((double)th[1 - AXIS]);
+    const double dr_p = AXIS == 0 ? pi.dry : pi.drx, dr_o = AXIS == 0 ? pi.drx : pi.dry;
+    const int n = threadIdx.x;                       // blockDim.x == 256
+    {
+        double s, c;
+        sincos(-2.0 * pi_d * (double)((n / 16) * (n % 16)) / N256, &s, &c);
+        t.tw[n] = unit_pair(c, s);
+        const double q = (double)sfreq<N256>(n) / N256, k = q / a.dx;
+        sincos(-pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan_p, &s, &c);
+        t.h[n] = unit_pair(c, s);
+        sincos(-2.0 * pi_d * q * dr_p, &s, &c);
+        const float4 r = unit_pair(c, s);
+        t.r[n] = make_float2(r.x, r.y);
+    }
+    if (n < LINES256) {
+        const int m = line0 + n;
+        const double q = (double)sfreq<N256>(m) / N256, k = q / a.dx;
+        double s, c;
+        sincos(-pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan_o, &s, &c);
+        t.hl[n] = unit_pair(c, s);
+        sincos(-2.0 * pi_d * q * dr_o, &s, &c);
+        const float4 r = unit_pair(c, s);
+        t.rl[n] = make_float2(r.x, r.y);
+    }
+    __syncthreads();
+}
+
+// block of 16 rows (row passes) or 16 columns (column passes) of one wave:
+// register r of lane c of line l is element (line0 + l, c + 16 r) for rows and
+// (c + 16 r, line0 + l) for columns.
+__device__ __forceinline__ void rows_load(float2 (&v)[16], const float2* w, int y, int c) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = w[y * N256 + c + 16 * r];
+}
+__device__ __forceinline__ void rows_store(const float2 (&v)[16], float2* w, int y, int c) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) w[y * N256 + c + 16 * r] = v[r];
+}
+__device__ __forceinline__ void cols_load(float2 (&v)[16], const float2* w, int x, int c) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = w[(c + 16 * r) * N256 + x];
+}
+__device__ __forceinline__ void cols_store(const float2 (&v)[16], float2* w, int x, int c) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) w[(c + 16 * r) * N256 + x] = v[r];
+}
+
+struct Pass256 {
+    WaveArgs a;
+    float2* wave;          // B x M x 256 x 256 working waves
+    int s;                 // slice of the pass
+};
+
+// Forward row pass of slice s: wave holds (y, k_x) of the previous column
+// pass (for s == 0 the shifted probe still lacking its x ramp); keeps phi_s,
+// transmits by O_s and transforms along x.
+__global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
+    __shared__ float2 lds[LDS256];
+    __shared__ Tables256 tab;
+    const WaveArgs& a = P.a;
+    const int ch = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int j = ch / a.M;
+    const PosInfo pi = a.pinfo[j];
+    if (pi.ty < 0) return;
+    const int l = threadIdx.x / 16, c = threadIdx.x % 16, y = blk * LINES256 + l;
+    build256<1>(tab, a, pi, blk * LINES256);
+    float2* w = P.wave + (size_t)ch * N256 * N256;
+    float2 v[16];
+    rows_load(v, w, y, c);
+    if (P.s == 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], tab.r[c + 16 * r]);
+    }
+    mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                      // phi_s (space)
+    const Slots<N256> sl(a, ch);
+    if (sl.base && a.keep == KEEP_FULL) rows_store(v, sl.phi(P.s), y, c);
+    else if (sl.base && a.ckK <= a.S && P.s % a.ckK == 0) rows_store(v, sl.ckpt(P.s / a.ckK), y, c);
+    const float2* Os = a.Oc + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], Os[c + 16 * r]);
+    nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
+    rows_store(v, w, y, c);
+}
+
+// Forward column pass: s < 0 builds the shifted probe (inverse along y of
+// Phat R_y / N); 0 <= s < S-1 propagates to slice s+1 (keeping Y'_{s+1});
+// s == S-1 forms the far field and its intensity.
+__global__ __launch_bounds__(256) void k256_fwd_col(Pass256 P) {
+    __shared__ float2 lds[LDS256];
+    __shared__ Tables256 tab;
+    const WaveArgs& a = P.a;
+    const int ch = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int j = ch / a.M, m = ch % a.M;
+    const PosInfo pi = a.pinfo[j];
+    const int l = threadIdx.x % 16, c = threadIdx.x / 16, x = blk * LINES256 + l;
+    float* Iout = a.Imode + (size_t)ch * N256 * N256;
+    if (pi.ty < 0) {
+        if (P.s == a.S - 1) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) Iout[(c + 16 * r) * N256 + x] = 0.f;
+        }
+        return;
+    }
+    build256<0>(tab, a, pi, blk * LINES256);
+    float2* w = P.wave + (size_t)ch * N256 * N256;
+    float2 v[16];
+    if (P.s < 0) {
+        cols_load(v, a.Phat + (size_t)m * N256 * N256, x, c);
+        const float sc = 1.0f / N256;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = cscale(cmul(v[r], tab.r[c + 16 * r]), sc);
+        mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
+        cols_store(v, w, x, c);
+        return;
+    }
+    cols_load(v, w, x, c);
+    nat2mid<ColGeo256, -1>(v, lds, tab.tw, l, c);                       // full 2-D spectrum (raw)
+    const Slots<N256> sl(a, ch);
+    const bool full = sl.base && a.keep == KEEP_FULL;
+    if (P.s < a.S - 1) {
+        const float4 hx = tab.hl[l];
+        const float sc = 1.0f / ((float)N256 * N256);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = cscale(tmul<false>(tmul<false>(v[r], tab.h[c + 16 * r]), hx), sc);
+        if (full) cols_store(v, sl.spec(P.s + 1), x, c);
+        mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
+        cols_store(v, w, x, c);
+    } else {
+        if (full) cols_store(v, sl.far(), x, c);
+        const float s2 = 1.0f / ((float)N256 * N256);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Iout[(c + 16 * r) * N256 + x] = cabs2(v[r]) * s2;
+    }
+}
+
+// Gradient column pass.  s == S: start, G_Psi = w F[chi_{S-1}] -> inverse
+// along y.  1 <= s < S: the adjoint of slice s's propagation (after the row
+// pass of slice s): G^ -> dz / tilt partial sums with Y'_s -> conj(H) G^ / N^2
+// -> inverse along y.  s == 0: probe-spectrum and position terms.
+__global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
+    __shared__ float2 lds[LDS256];
+    __shared__ Tables256 tab;
+    const WaveArgs& a = P.a;
+    const int ch = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int j = ch / a.M, m = ch % a.M;
+    const PosInfo pi = a.pinfo[j];
+    const int l = threadIdx.x % 16, c = threadIdx.x / 16, x = blk * LINES256 + l;
+    float* part = a.part + ((size_t)ch * NBLK256 + blk) * 8;
+    if (pi.ty < 0) {
+        if (P.s == 0) {
+            float2* gP = a.gPhat + (size_t)ch * N256 * N256;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) gP[(c + 16 * r) * N256 + x] = make_float2(0.f, 0.f);
+            if (threadIdx.x < 8) part[threadIdx.x] = 0.f;
+        }
+        return;
+    }
+    build256<0>(tab, a, pi, blk * LINES256);
+    const Slots<N256> sl(a, ch);
+    float2* w = P.wave + (size_t)ch * N256 * N256;
+    const float inv_n = 1.0f / N256, inv_n2 = 1.0f / ((float)N256 * N256);
+    float2 v[16];
+    if (P.s == a.S) {
+        cols_load(v, sl.far(), x, c);
+        const float* wj = a.wgt + (size_t)j * N256 * N256;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = cscale(v[r], wj[(c + 16 * r) * N256 + x] * inv_n2);
+        mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
+        cols_store(v, w, x, c);
+        if (threadIdx.x < 8) part[threadIdx.x] = 0.f;
+        return;
+    }
+    cols_load(v, w, x, c);
+    nat2mid<ColGeo256, -1>(v, lds, tab.tw, l, c);                       // G^ (raw), (k_y, k_x)
+    const float dk = (float)(1.0 / (N256 * a.dx));
+    const float kx = sfreq<N256>(x) * dk;
+    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if (P.s > 0) {
+        const float2* Y = sl.spec(P.s);
+        const float4 hx = tab.hl[l];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int ky_i = c + 16 * r;
+            const float2 yv = Y[ky_i * N256 + x];
+            const float e = v[r].y * yv.x - v[r].x * yv.y;               // Im(G^ conj(Y))
+            const float ky = sfreq<N256>(ky_i) * dk;
+            acc[0] = fmaf(e, kx * kx + ky * ky, acc[0]);
+            acc[1] = fmaf(e, kx, acc[1]);
+            acc[2] = fmaf(e, ky, acc[2]);
+            v[r] = cscale(tmul<true>(tmul<true>(v[r], tab.h[ky_i]), hx), inv_n2);
+        }
+        mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
+        cols_store(v, w, x, c);
+    } else {
+        const float2* Pm = a.Phat + (size_t)m * N256 * N256;
+        float2* gP = a.gPhat + (size_t)ch * N256 * N256;
+        const float2 rx = tab.rl[l];
+        const float qx = (float)sfreq<N256>(x) * inv_n;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int ky_i = c + 16 * r;
+            const float2 G0 = cscale(v[r], inv_n);
+            const float2 R = cmul(tab.r[ky_i], rx);
+            gP[ky_i * N256 + x] = cmulc(G0, R);                          // conj(R) G^_0
+            const float2 z = cmulc(cmul(Pm[ky_i * N256 + x], R), G0);    // Phat R conj(G^_0)
+            acc[3] = fmaf(z.y, (float)sfreq<N256>(ky_i) * inv_n, acc[3]);
+            acc[4] = fmaf(z.y, qx, acc[4]);
+        }
+    }
+    block_sum<5>(acc, reinterpret_cast<float*>(lds));
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) part[k] += acc[k];
+}
+
+// Gradient row pass of slice s: wave holds (y, k_x) of G after the inverse
+// along y; inverse along x gives G_chi_s; writes gO_s = conj(phi_s) G_chi,
+// then G_phi = conj(O_s) G_chi transformed along x.
+__global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
+    __shared__ float2 lds[LDS256];
+    __shared__ Tables256 tab;
+    const WaveArgs& a = P.a;
+    const int ch = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int j = ch / a.M;
+    const PosInfo pi = a.pinfo[j];
+    if (pi.ty < 0) return;
+    const int l = threadIdx.x / 16, c = threadIdx.x % 16, y = blk * LINES256 + l;
+    build256<1>(tab, a, pi, blk * LINES256);
+    const Slots<N256> sl(a, ch);
+    float2* w = P.wave + (size_t)ch * N256 * N256;
+    float2 v[16];
+    rows_load(v, w, y, c);
+    mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                      // G_chi_s (space)
+    const float2* phi = sl.phi(P.s) + y * N256;
+    float2* go = a.gO + (((size_t)ch * a.S + P.s) * N256 + y) * N256;
+    const float2* Os = a.Oc + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int xx = c + 16 * r;
+        go[xx] = cmulc(v[r], phi[xx]);                                    // conj(phi) G_chi
+        v[r] = cmulc(v[r], Os[xx]);                                       // conj(O) G_chi
+    }
+    nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
+    rows_store(v, w, y, c);
+}
+
+// Orthonormal 2-D DFT of `count` 256 x 256 waves as two passes:
+// rows (ROWS = true) then columns; the column pass scales by 1/256 and
+// stores or accumulates.
+template <int SG, bool ROWS, bool ACC>
+__global__ __launch_bounds__(256) void k256_fft(const float2* in, float2* out) {
+    __shared__ float2 lds[LDS256];
+    __shared__ float4 tw[N256];
+    const int wv = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    {
+        const int n = threadIdx.x;
+        double s, c;
+        sincos(-2.0 * 3.14159265358979323846 * (double)((n / 16) * (n % 16)) / N256, &s, &c);
+        tw[n] = unit_pair(c, s);
+    }
+    __syncthreads();
+    const float2* src = in + (size_t)wv * N256 * N256;
+    float2* dst = out + (size_t)wv * N256 * N256;
+    float2 v[16];
+    if (ROWS) {
+        const int l = threadIdx.x / 16, c = threadIdx.x % 16, y = blk * LINES256 + l;
+        rows_load(v, src, y, c);
+        nat2mid<RowGeo256, SG>(v, lds, tw, l, c);
+        rows_store(v, dst, y, c);
+    } else {
+        const int l = threadIdx.x % 16, c = threadIdx.x / 16, x = blk * LINES256 + l;
+        cols_load(v, src, x, c);
+        nat2mid<ColGeo256, SG>(v, lds, tw, l, c);
+        const float sc = 1.0f / N256;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            float2 o = cscale(v[r], sc);
+            if (ACC) o = cadd(o, dst[(c + 16 * r) * N256 + x]);
+            v[r] = o;
+        }
+        cols_store(v, dst, x, c);
+    }
+}
+
+}  // namespace ptyr

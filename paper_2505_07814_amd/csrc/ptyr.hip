@@ -12,6 +12,7 @@
 
 #include "../../include/ptyr.h"
 #include "kernels.hpp"
+#include "lines256.hpp"
 
 using namespace ptyr;
 
@@ -268,8 +269,8 @@ __global__ void k_sum_rows(const float2* src, float2* dst, int B, int M, int NN)
 // One thread per batch row (rows of a batch are distinct, so the row
 // updates do not collide); dz and a global tilt are summed over rows in
 // fixed order by a block tree.
-__global__ __launch_bounds__(256) void k_param_grads(const float* part, const PosInfo* pinfo, int B, int M,
-                                                     const float* tilt, int global_tilt, const float* dzp,
+__global__ __launch_bounds__(256) void k_param_grads(const float* part, int nblk, const PosInfo* pinfo, int B,
+                                                     int M, const float* tilt, int global_tilt, const float* dzp,
                                                      double lam, float* g_pos, float* g_tilt, float* g_dz) {
     __shared__ double sh[3][256];
     const double two_pi = 6.283185307179586;
@@ -279,10 +280,11 @@ __global__ __launch_bounds__(256) void k_param_grads(const float* part, const Po
         if (pinfo[j].ty < 0) continue;
         const int row = pinfo[j].row;
         double k2 = 0, kx = 0, ky = 0, py = 0, px = 0;
-        for (int m = 0; m < M; ++m) {
-            const float* q = part + (size_t)(j * M + m) * 8;
-            k2 += q[0]; kx += q[1]; ky += q[2]; py += q[3]; px += q[4];
-        }
+        for (int m = 0; m < M; ++m)
+            for (int b = 0; b < nblk; ++b) {
+                const float* q = part + ((size_t)(j * M + m) * nblk + b) * 8;
+                k2 += q[0]; kx += q[1]; ky += q[2]; py += q[3]; px += q[4];
+            }
         const float* th = global_tilt ? tilt : tilt + 2 * row;
         const double ty = tan((double)th[0]), tx = tan((double)th[1]);
         const double cy = cos((double)th[0]), cx = cos((double)th[1]);
@@ -325,7 +327,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, err, store, gO, gPhat, gPsum, part, gamp, gphase,
-        gprobe, gdz, gpos, gtilt, total;
+        gprobe, gdz, gpos, gtilt, wave, total;
     int keep, ckK, nck, waves_per_chain;
 };
 
@@ -372,13 +374,14 @@ Layout make_layout(const ptyr_geom* g) {
     L.gO = take(B * M * S * NN * sizeof(float2));
     L.gPhat = take(B * M * NN * sizeof(float2));
     L.gPsum = take(M * NN * sizeof(float2));
-    L.part = take(B * M * 8 * sizeof(float));
+    L.part = take(B * M * (g->N == 256 ? NBLK256 : 1) * 8 * sizeof(float));
     L.gamp = take(S * HW * sizeof(float));
     L.gphase = take(S * HW * sizeof(float));
     L.gprobe = take(M * NN * sizeof(float2));
     L.gdz = take(sizeof(float));
     L.gpos = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
     L.gtilt = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
+    L.wave = take(g->N == 256 ? B * M * NN * sizeof(float2) : 0);
     L.total = o;
     return L;
 }
@@ -441,7 +444,7 @@ const char* ptyr_status_str(ptyr_status s) {
 
 ptyr_status ptyr_check_geom(const ptyr_geom* g) {
     if (!g) return PTYR_E_ARG;
-    if (g->N != 64 && g->N != 128) return PTYR_E_ARG;   // N = 256 path: HBM passes (not in this build)
+    if (g->N != 64 && g->N != 128 && g->N != 256) return PTYR_E_ARG;
     if (g->M < 1 || g->S < 1 || g->B_max < 1) return PTYR_E_ARG;
     if (g->H < g->N || g->W < g->N) return PTYR_E_ARG;
     if (!(g->dx > 0.0) || !(g->lambda > 0.0)) return PTYR_E_ARG;
@@ -451,6 +454,11 @@ ptyr_status ptyr_check_geom(const ptyr_geom* g) {
     // grid and index limits of the kernels
     if ((double)g->B_max * g->M > 2147483647.0 / 2) return PTYR_E_ARG;
     if (g->n_scan < 0) return PTYR_E_ARG;
+    if (g->N == 256) {   // the line-pass path keeps every wave (no recomputation)
+        int keep, K, nck;
+        keep_plan(g, &keep, &K, &nck);
+        if (keep != KEEP_FULL) return PTYR_E_ARG;
+    }
     return PTYR_OK;
 }
 
@@ -597,6 +605,33 @@ template <int N> void launch_gradient(ptyr_ctx* c, const WaveArgs& a, int B) {
     else
         hipLaunchKernelGGL((k_gradient<N, KEEP_CKPT>), dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
 }
+// N = 256: forward and gradient as line passes (lines256.hpp)
+Pass256 pass256(ptyr_ctx* c, const WaveArgs& a, int s) {
+    Pass256 P;
+    P.a = a;
+    P.wave = at<float2>(c, c->L.wave);
+    P.s = s;
+    return P;
+}
+void forward256(ptyr_ctx* c, const WaveArgs& a, int B) {
+    TimedLaunch t(c, PTYR_K_FORWARD);
+    const dim3 grid(B * c->g.M * NBLK256), blk(256);
+    hipLaunchKernelGGL(k256_fwd_col, grid, blk, 0, c->stream, pass256(c, a, -1));
+    for (int s = 0; s < a.S; ++s) {
+        hipLaunchKernelGGL(k256_fwd_row, grid, blk, 0, c->stream, pass256(c, a, s));
+        hipLaunchKernelGGL(k256_fwd_col, grid, blk, 0, c->stream, pass256(c, a, s));
+    }
+}
+void gradient256(ptyr_ctx* c, const WaveArgs& a, int B) {
+    TimedLaunch t(c, PTYR_K_GRADIENT);
+    const dim3 grid(B * c->g.M * NBLK256), blk(256);
+    hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, c->stream, pass256(c, a, a.S));
+    for (int s = a.S - 1; s >= 0; --s) {
+        hipLaunchKernelGGL(k256_grad_row, grid, blk, 0, c->stream, pass256(c, a, s));
+        hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, c->stream, pass256(c, a, s));
+    }
+}
+
 template <int N> void launch_probe_fft(ptyr_ctx* c, const float* probe) {
     hipLaunchKernelGGL((k_fft2<N, -1, false>), dim3(c->g.M), dim3(N * N / 16), 0, c->stream,
                        reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat));
@@ -616,7 +651,15 @@ ptyr_status run_forward(ptyr_ctx* c, const float* amp, const float* phase, const
                        g.N, g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err));
     WaveArgs a = wave_args(c, tilt, dz, B);
     if (g.N == 64) { launch_probe_fft<64>(c, probe); launch_forward<64>(c, a, B); }
-    else { launch_probe_fft<128>(c, probe); launch_forward<128>(c, a, B); }
+    else if (g.N == 128) { launch_probe_fft<128>(c, probe); launch_forward<128>(c, a, B); }
+    else {
+        const dim3 grid(g.M * NBLK256), blk(256);
+        hipLaunchKernelGGL((k256_fft<-1, true, false>), grid, blk, 0, c->stream,
+                           reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat));
+        hipLaunchKernelGGL((k256_fft<-1, false, false>), grid, blk, 0, c->stream, at<float2>(c, c->L.Phat),
+                           at<float2>(c, c->L.Phat));
+        forward256(c, a, B);
+    }
     size_t NN = (size_t)g.N * g.N;
     hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)B * NN)), dim3(256), 0, c->stream,
                        at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, g.N);
@@ -662,7 +705,8 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     if (st != PTYR_OK) return st;
     WaveArgs a = wave_args(c, tilt, dz, B);
     if (g.N == 64) launch_gradient<64>(c, a, B);
-    else launch_gradient<128>(c, a, B);
+    else if (g.N == 128) launch_gradient<128>(c, a, B);
+    else gradient256(c, a, B);
     if (g_amp || g_phase) {
         int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
         hipLaunchKernelGGL(k_scatter_object, dim3(ntiles, g.S), dim3(256), 0, c->stream, at<float2>(c, c->L.gO),
@@ -673,12 +717,19 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         hipLaunchKernelGGL(k_sum_rows, dim3(grid_for((size_t)g.M * NN)), dim3(256), 0, c->stream,
                            at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B, g.M, NN);
         if (g.N == 64) launch_probe_ifft_acc<64>(c, g_probe);
-        else launch_probe_ifft_acc<128>(c, g_probe);
+        else if (g.N == 128) launch_probe_ifft_acc<128>(c, g_probe);
+        else {
+            const dim3 grid(g.M * NBLK256), blk(256);
+            hipLaunchKernelGGL((k256_fft<+1, true, false>), grid, blk, 0, c->stream, at<float2>(c, c->L.gPsum),
+                               at<float2>(c, c->L.gPsum));
+            hipLaunchKernelGGL((k256_fft<+1, false, true>), grid, blk, 0, c->stream, at<float2>(c, c->L.gPsum),
+                               reinterpret_cast<float2*>(g_probe));
+        }
     }
     if (g_pos || g_tilt || g_dz)
         hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(256), 0, c->stream, at<float>(c, c->L.part),
-                           at<PosInfo>(c, c->L.pinfo), B, g.M, tilt, a.global_tilt, dz, g.lambda, g_pos, g_tilt,
-                           g_dz);
+                           g.N == 256 ? NBLK256 : 1, at<PosInfo>(c, c->L.pinfo), B, g.M, tilt, a.global_tilt, dz,
+                           g.lambda, g_pos, g_tilt, g_dz);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
 

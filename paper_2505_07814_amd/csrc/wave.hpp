@@ -149,8 +149,10 @@ template <int SG> __device__ __forceinline__ void dft16(float2* x) {
 }
 
 template <int L, int SG> __device__ __forceinline__ void dftL(float2* x) {
+    static_assert(L == 4 || L == 8 || L == 16, "lanes per line must be 4, 8 or 16");
     if constexpr (L == 4) dft4<SG>(x[0], x[1], x[2], x[3]);
-    else dft8<SG>(x);
+    else if constexpr (L == 8) dft8<SG>(x);
+    else dft16<SG>(x);
 }
 
 // ------------------------------------------------------------ layouts
@@ -158,6 +160,7 @@ enum { ROW = 0, COL = 1 };
 enum { NAT = 0, MID = 1 };
 
 template <int N> struct WaveGeo {
+    static constexpr int NL = N;          // line length
     static constexpr int L = N / 16;
     static constexpr int T = N * N / 16;
     static constexpr int G = 16 / L;
@@ -213,9 +216,10 @@ __device__ __forceinline__ void wstore(const T (&v)[16], T* base, int stride, in
     for (int r = 0; r < 16; ++r) (base + (Y::dy(r) * stride + Y::dx(r)))[o] = v[r];
 }
 
-// LDS slot of exchange element (line l, b, lane c')
-template <int N> __device__ __forceinline__ int slot_x(int l, int b, int c) {
-    return l * WaveGeo<N>::SL + b * WaveGeo<N>::SB + c;
+// LDS slot of exchange element (line l, b, lane c') for line geometry GEO
+// (GEO::L lanes per line, paddings GEO::SB, GEO::SL)
+template <class GEO> __device__ __forceinline__ int slot_x(int l, int b, int c) {
+    return l * GEO::SL + b * GEO::SB + c;
 }
 
 // LDS slot of field element (y, x) for a transpose
@@ -251,36 +255,36 @@ template <int L, int SG> __device__ __forceinline__ void twiddle_pass(float2 (&v
 
 // ------------------------------------------------------------ line transforms
 // NAT -> MID, DFT of sign SG along every line.
-template <int N, int SG>
+template <class GEO, int SG>
 __device__ __forceinline__ void nat2mid(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
-    constexpr int L = N / 16, G = 16 / L;
+    constexpr int L = GEO::L, G = 16 / L;
     dft16<SG>(v);
     twiddle_pass<L, SG>(v, tw + c);
 #pragma unroll
-    for (int b = 0; b < 16; ++b) lds[slot_x<N>(l, b, c)] = v[b];
+    for (int b = 0; b < 16; ++b) lds[slot_x<GEO>(l, b, c)] = v[b];
     __syncthreads();
 #pragma unroll
     for (int be = 0; be < G; ++be)
 #pragma unroll
-        for (int a = 0; a < L; ++a) v[be * L + a] = lds[slot_x<N>(l, c + L * be, a)];
+        for (int a = 0; a < L; ++a) v[be * L + a] = lds[slot_x<GEO>(l, c + L * be, a)];
     __syncthreads();
 #pragma unroll
     for (int be = 0; be < G; ++be) dftL<L, SG>(&v[be * L]);
 }
 
 // MID -> NAT, DFT of sign SG along every line.
-template <int N, int SG>
+template <class GEO, int SG>
 __device__ __forceinline__ void mid2nat(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
-    constexpr int L = N / 16, G = 16 / L;
+    constexpr int L = GEO::L, G = 16 / L;
 #pragma unroll
     for (int be = 0; be < G; ++be) dftL<L, SG>(&v[be * L]);
 #pragma unroll
     for (int be = 0; be < G; ++be)
 #pragma unroll
-        for (int a = 0; a < L; ++a) lds[slot_x<N>(l, c + L * be, a)] = v[be * L + a];
+        for (int a = 0; a < L; ++a) lds[slot_x<GEO>(l, c + L * be, a)] = v[be * L + a];
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < 16; ++b) v[b] = lds[slot_x<N>(l, b, c)];
+    for (int b = 0; b < 16; ++b) v[b] = lds[slot_x<GEO>(l, b, c)];
     __syncthreads();
     twiddle_pass<L, SG>(v, tw + c);
     dft16<SG>(v);

@@ -44,6 +44,8 @@ def test_status_strings():
     ({}, L.PTYR_OK),
     (dict(N=64, H=128, W=128), L.PTYR_OK),
     (dict(N=96), L.PTYR_E_ARG),
+    (dict(N=256, H=1024, W=1024, B_max=16, M=8, S=30, wave_budget_bytes=16 * 8 * 60 * 256 * 256 * 8), L.PTYR_OK),
+    (dict(N=256, H=1024, W=1024, B_max=16, M=8, S=30, wave_budget_bytes=0), L.PTYR_E_ARG),
     (dict(M=0), L.PTYR_E_ARG),
     (dict(S=0), L.PTYR_E_ARG),
     (dict(B_max=0), L.PTYR_E_ARG),

@@ -301,3 +301,41 @@ def test_autograd_function_matches_adjoint():
     assert rel(args[1].grad.cpu().numpy(), 2 * ref.phase) < 1e-4
     assert rel(args[2].grad.cpu().numpy(), 2 * ref.probe) < 1e-4
     assert rel(args[3].grad.cpu().numpy(), 2 * ref.pos) < 1e-4
+
+
+# ---------------------------------------------------------------- N = 256 (line passes through HBM)
+@pytest.mark.parametrize("S,M,B,seed", [(1, 1, 2, 31), (3, 2, 3, 32)])
+def test_forward_parity_small_256(S, M, B, seed):
+    print(f"forward small N=256 S={S} M={M} B={B}", flush=True)
+    c = Case(small(256, S, M, B, seed), perturb=False)
+    eng = c.engine()
+    I = eng.forward(*c.gpu_args())
+    eng.sync()
+    e = rel(I.cpu().numpy(), c.I_true)
+    print(f"forward rel-L2 {e:.2e}", flush=True)
+    assert e < 1e-5
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "poisson"])
+def test_gradient_parity_small_256(kind):
+    print(f"gradient small N=256 {kind}", flush=True)
+    c = Case(small(256, 3, 2, 3, 33))
+    _check_grads(c, c.engine(kind), kind)
+
+
+def test_forward_parity_large_256_batch():
+    """The N=256 / 30-slice / 8-mode workload at its launch batch of 16."""
+    print("forward large_256 B=16", flush=True)
+    c = Case(synth.workload("large_256", scan=16), perturb=False)
+    eng = c.engine()
+    I = eng.forward(*c.gpu_args())
+    eng.sync()
+    e = rel(I.cpu().numpy(), c.I_true)
+    print(f"forward rel-L2 {e:.2e}", flush=True)
+    assert e < 1e-5
+
+
+def test_gradient_parity_large_256():
+    print("gradient large_256 B=2", flush=True)
+    c = Case(synth.workload("large_256", scan=2))
+    _check_grads(c, c.engine())
