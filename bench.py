@@ -18,7 +18,6 @@ device memory before the timed region.
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,15 +38,6 @@ def fft_flops(N):
     return 5.0 * N * N * math.log2(N * N)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2505_07814_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
-
-
 def read_traffic(kernel, workload):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
     taken on the current kernel sources (else None)."""
@@ -59,7 +49,8 @@ def read_traffic(kernel, workload):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_hash") != kernel_source_hash():
+    from paper_2505_07814_amd.profile_summary import source_hash
+    if vals.get("source_hash") != source_hash():
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -101,7 +92,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=256, help="timed steps (256 = one pass over the scan)")
     ap.add_argument("--warmup", type=int, default=16)
-    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=0, help="positions per step (0 = the workload's: 64, or 16 at N=256)")
+    ap.add_argument("--workload", default=WORKLOAD, choices=["multislice_128", "large_256"],
+                    help="multislice_128 is the headline configuration; large_256 measures the N=256 line passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--positions", type=int, default=0,
                     help="use only the first P scan positions (profiling runs; 0 = all)")
@@ -121,8 +114,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    w = synth.workload(WORKLOAD, scan=args.positions or None)
-    B = args.batch
+    workload = args.workload
+    w = synth.workload(workload, scan=args.positions or None)
+    B = args.batch or w.B
     lam = synth.wavelength_A(w.kv)
     n_pos = w.pos.shape[0]
     T = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a if dt is None else a.astype(dt))).to(dev)
@@ -174,23 +168,30 @@ def main():
     flops = B * w.M * 2 * w.S * fft_flops(w.N)          # nominal FFT flops of either fused kernel
     achieved = flops / (per_launch[dom] * 1e-3) / 1e12
     roofline = {
-        "bound": "alu", "kernel": f"k_{dom}<128>", "achieved": round(achieved, 3),
+        "bound": "alu", "kernel": f"k_{dom}<{w.N}>" if w.N < 256 else f"{dom} line passes (N=256)", "achieved": round(achieved, 3),
         "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-        "traffic": read_traffic(dom, WORKLOAD),
+        "traffic": read_traffic(dom, workload),
         "launch_ms": round(per_launch[dom], 4),
         "flops_per_launch": flops,
         "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
         "other_kernel_ms": {k: round(v, 4) for k, v in per_launch.items() if k != dom},
     }
+    desc = {
+        "multislice_128": "multislice_128: probe 128x128 at 0.15 A/px, 6 modes, object 12 x 640 x 640, dz 20 A, "
+                          "128x128 scan, 64 positions per Adam step (forward + loss + gradient of all six "
+                          "parameters + Adam)",
+        "large_256": "large_256: probe 256x256 at 0.15 A/px, 8 modes, object 30 x 1024 x 1024 (twisted hexagonal "
+                     "bilayer), dz 10 A, 192x192 scan, 16 positions per Adam step (forward + loss + gradient of "
+                     "all six parameters + Adam)",
+    }[workload]
+    metric = ("fwd+adjoint patterns/s (N=128, 12 slices, 6 modes)" if workload == "multislice_128"
+              else "fwd+adjoint patterns/s (N=256, 30 slices, 8 modes)")
     out = {
-        "metric": "fwd+adjoint patterns/s (N=128, 12 slices, 6 modes)",
+        "metric": metric,
         "value": round(value, 1), "unit": "patterns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "multislice_128: probe 128x128 at 0.15 A/px, 6 modes, object 12 x 640 x 640, "
-                               "dz 20 A, 128x128 scan, 64 positions per Adam step (forward + loss + gradient "
-                               "of all six parameters + Adam)",
-                   "global_batch": B, "N": w.N, "slices": w.S, "modes": w.M, "positions": n_pos},
+        "config": {"workload": desc, "global_batch": B, "N": w.N, "slices": w.S, "modes": w.M, "positions": n_pos},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

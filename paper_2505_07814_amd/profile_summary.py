@@ -16,10 +16,14 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def source_hash():
+# the sources of the multislice forward / gradient kernels and their launches
+MULTISLICE_SOURCES = ("kernels.hpp", "lines256.hpp", "ptyr.hip", "wave.hpp")
+
+
+def source_hash(files=MULTISLICE_SOURCES):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2505_07814_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in sorted(files):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
