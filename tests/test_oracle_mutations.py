@@ -83,3 +83,49 @@ def test_gradient_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(ms, "gradients", bad_gradients)
     with pytest.raises(AssertionError):
         _fd_small()
+
+
+# ---------------------------------------------------------------- conv-net oracle
+from oracle import convnet as cn              # noqa: E402
+import tests.test_oracle_convnet as cpins      # noqa: E402
+
+_conv = cn.conv3x3
+_conv_bwd = cn.conv3x3_backward
+_round = cn.round_bf16
+
+CONV_MUTANTS = {
+    "convolution instead of correlation (flipped kernel)": (
+        "conv3x3", lambda a, W, b, s: _conv(a, W[:, :, ::-1, ::-1], b, s),
+        lambda: cpins.test_conv_matches_library(1, 9, 3, 5)),
+    "stride grid starts at pixel 1": (
+        "conv3x3", lambda a, W, b, s: _conv(np.pad(a, ((0, 0), (0, 0), (0, 1), (0, 1)))[:, :, 1:, 1:], W, b, s),
+        lambda: cpins.test_conv_matches_library(2, 10, 4, 2)),
+    "input gradient with transposed taps": (
+        "conv3x3_backward",
+        lambda a, W, g, s: (_conv_bwd(a, W[:, :, ::-1, ::-1], g, s)[0],) + _conv_bwd(a, W, g, s)[1:],
+        lambda: cpins.test_conv_backward_is_adjoint(1, 8)),
+    "weight gradient with swapped tap axes": (
+        "conv3x3_backward",
+        lambda a, W, g, s: (_conv_bwd(a, W, g, s)[0], _conv_bwd(a, W, g, s)[1].transpose(0, 1, 3, 2),
+                            _conv_bwd(a, W, g, s)[2]),
+        lambda: cpins.test_conv_backward_is_adjoint(2, 9)),
+    "bf16 rounding truncates": (
+        "round_bf16",
+        lambda x: (np.asarray(x, np.float32).view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64),
+        cpins.test_round_bf16_matches_library_and_ties),
+}
+
+
+@pytest.mark.parametrize("name", list(CONV_MUTANTS))
+def test_planted_conv_mistake_is_caught(name, monkeypatch):
+    attr, bad, pin = CONV_MUTANTS[name]
+    monkeypatch.setattr(cn, attr, bad)
+    with pytest.raises(AssertionError):
+        pin()
+
+
+def test_missing_relu_mask_is_caught(monkeypatch):
+    """Back-propagating through the ReLU without its mask fails autograd parity."""
+    monkeypatch.setattr(cn.np, "where", lambda c, x, y: x)
+    with pytest.raises(AssertionError):
+        cpins.test_net_gradient_matches_autograd()
