@@ -4,9 +4,9 @@ TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
 module; only tests, the smoke check and the benchmark's CPU-baseline leg do.
 It shares no code with the HIP path.
 
-The paper itself uses a plain initial object (unit amplitude, near-zero phase;
-Sec. "Object initialization" of the reconstruction set-up) and mentions
-machine-learned direct solvers only as related work in its introduction.  The
+The paper itself uses a plain initial object (unit amplitude, near-zero random
+phase; Sec. "Preprocessing and initialization") and its introduction mentions
+machine-learned direct solvers only as related work.  The
 network here is an addition on top of the method, specified as:
 
     a_0 = log(1 + I)                      I: 9 x 64 x 64 (3 x 3 neighbourhood
@@ -134,15 +134,21 @@ def init_params(seed):
 
 def stitch(patches, centres, base):
     """Average of overlapping 32 x 32 patches placed with their centre at
-    round_half_even(centre) (rows [cy - 16, cy + 16)); pixels no patch covers
-    keep the value of `base`."""
+    round_half_even(centre) (rows [cy - 16, cy + 16)); the parts of a patch
+    outside the image are dropped; pixels no patch covers keep the value of
+    `base`."""
     img = np.array(base, np.float64)
+    H, W = img.shape
     acc = np.zeros_like(img)
     cnt = np.zeros_like(img)
     for p, (cy, cx) in zip(patches, centres):
         y0, x0 = int(np.rint(cy)) - 16, int(np.rint(cx)) - 16
-        acc[y0:y0 + 32, x0:x0 + 32] += p
-        cnt[y0:y0 + 32, x0:x0 + 32] += 1
+        for i in range(32):
+            for j in range(32):
+                y, x = y0 + i, x0 + j
+                if 0 <= y < H and 0 <= x < W:
+                    acc[y, x] += p[i, j]
+                    cnt[y, x] += 1
     m = cnt > 0
     img[m] = acc[m] / cnt[m]
     return img

@@ -75,6 +75,16 @@ def lib():
         "ptyr_step": (st, [vp, C.POINTER(Params), vp, C.c_int, vp, C.POINTER(LR), vp]),
         "ptyr_timing_enable": (st, [vp, C.c_int]),
         "ptyr_timing_read": (st, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+        # learned initial guess (include/ptyr_cnn.h)
+        "ptyr_cnn_param_count": (C.c_size_t, []),
+        "ptyr_cnn_workspace_bytes": (C.c_size_t, [C.c_int]),
+        "ptyr_cnn_create": (st, [C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "ptyr_cnn_destroy": (None, [vp]),
+        "ptyr_cnn_sync": (st, [vp]),
+        "ptyr_cnn_forward": (st, [vp, vp, vp, C.c_int, vp, C.c_int, vp]),
+        "ptyr_cnn_gradient": (st, [vp, vp, vp, C.c_int, vp, vp, C.c_int, vp, vp]),
+        "ptyr_cnn_adam": (st, [vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float]),
+        "ptyr_cnn_stitch": (st, [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -92,5 +102,8 @@ def check(status, what):
 HEADER_SYMBOLS = ["ptyr_status_str", "ptyr_check_geom", "ptyr_check_args", "ptyr_workspace_bytes",
                   "ptyr_checkpoint_plan", "ptyr_create", "ptyr_destroy", "ptyr_sync", "ptyr_forward",
                   "ptyr_loss", "ptyr_adjoint", "ptyr_step", "ptyr_timing_enable", "ptyr_timing_read"]
+
+CNN_HEADER_SYMBOLS = ["ptyr_cnn_param_count", "ptyr_cnn_workspace_bytes", "ptyr_cnn_create", "ptyr_cnn_destroy",
+                      "ptyr_cnn_sync", "ptyr_cnn_forward", "ptyr_cnn_gradient", "ptyr_cnn_adam", "ptyr_cnn_stitch"]
 
 PTYR_K_FORWARD, PTYR_K_GRADIENT = 0, 1

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "ptyr.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("ptyr.hip", "cnn.hip")]
 OUT = os.path.join(HERE, "libptyr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -20,9 +20,9 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile csrc/ptyr.hip into libptyr.so (always recompiles)."""
+    """Compile csrc/ptyr.hip and csrc/cnn.hip into libptyr.so (always recompiles)."""
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, *FLAGS, SRC, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,0 +1,333 @@
+// cnn.hpp - kernels of the learned initial guess: a 5-layer 3x3 convolutional
+// net that maps the log diffraction patterns of a 3 x 3 scan neighbourhood
+// (9 x 64 x 64) to the projected phase of the 32 x 32 patch centred on the
+// middle position.
+//
+//   layer  in          out         stride   reduction K = 9 taps x Cin (padded)
+//   0      9(16) x 64  32 x 64     1        144 -> 160
+//   1      32 x 64     32 x 32     2        288
+//   2      32 x 32     32 x 32     1        288
+//   3      32 x 32     32 x 32     1        288
+//   4      32 x 32     1(16) x 32  1        288        (no ReLU after it)
+//
+// Every convolution and both of its gradients is an implicit GEMM on the
+// gfx950 matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
+// accumulation).  Activations and back-propagated gradients are stored NHWC in
+// BF16 with channels padded to 16 / 32, so the 8 consecutive reduction elements
+// a lane feeds to the MFMA are 8 consecutive channels of one pixel: one
+// 16-byte load.  Lane i of a wave holds A[i%16][8(i/16)..+7],
+// B[8(i/16)..+7][i%16] and receives D[4(i/16)..+3][i%16].
+//
+// Parameters are one FP32 vector: per layer W[Cout_p][K_p] with reduction
+// index k = (3 u + v) * Cin_p + c for tap (u, v) and input channel c (padding
+// entries are zero and stay zero under training, their gradient being exactly
+// zero), followed by bias[Cout_p].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptyr {
+namespace cnn {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+typedef __attribute__((ext_vector_type(4))) float floatx4;
+
+constexpr int NLAYER = 5;
+constexpr int NB = 9;             // patterns per neighbourhood
+constexpr int IN = 64;            // pattern side
+constexpr int OUT = 32;           // phase patch side
+constexpr int CIN[NLAYER] = {9, 32, 32, 32, 32};
+constexpr int CINP[NLAYER] = {16, 32, 32, 32, 32};
+constexpr int COUT[NLAYER] = {32, 32, 32, 32, 1};
+constexpr int COUTP[NLAYER] = {32, 32, 32, 32, 16};
+constexpr int STRIDE[NLAYER] = {1, 2, 1, 1, 1};
+constexpr int HIN[NLAYER] = {64, 64, 32, 32, 32};
+constexpr int HOUT[NLAYER] = {64, 32, 32, 32, 32};
+
+constexpr int pad32(int x) { return (x + 31) / 32 * 32; }
+constexpr int kp(int l) { return pad32(9 * CINP[l]); }          // forward / weight-gradient reduction
+constexpr int kd(int l) { return pad32(9 * COUTP[l]); }         // input-gradient reduction
+constexpr int w_size(int l) { return COUTP[l] * kp(l); }
+constexpr int w_off(int l) { return l == 0 ? 0 : w_off(l - 1) + w_size(l - 1) + COUTP[l - 1]; }
+constexpr int b_off(int l) { return w_off(l) + w_size(l); }
+constexpr int NPARAM = b_off(NLAYER - 1) + COUTP[NLAYER - 1];
+constexpr int wt_size(int l) { return CINP[l] * kd(l); }
+constexpr int wt_off(int l) { return l == 0 ? 0 : wt_off(l - 1) + wt_size(l - 1); }
+constexpr int WT_TOTAL = wt_off(NLAYER - 1) + wt_size(NLAYER - 1);
+constexpr int WCHUNK = 512;                    // output pixels per weight-gradient partial sum
+constexpr int ERR_INDEX = 1;
+
+// per-sample element counts of the stored BF16 tensors
+constexpr int act_elems(int l) { return HIN[l] * HIN[l] * CINP[l]; }      // input of layer l
+constexpr int grad_elems(int l) { return HOUT[l] * HOUT[l] * COUTP[l]; }  // dL/dz_l
+
+__device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+    return z;
+}
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+// FP32 parameters -> BF16 W (same offsets) and, per layer, the transposed
+// BF16 weights WT_l[c][(3u+v) * Cout_p + o] = W_l[o][(3u+v) * Cin_p + c] used by
+// the input gradient (zero for reduction indices >= 9 Cout_p).
+template <int L>
+__device__ __forceinline__ void prep_wt(const float* p, __bf16* wt, int r) {
+    constexpr int cinp = CINP[L], coutp = COUTP[L], K = kp(L), KD = kd(L);
+    const int c = r / KD, kk = r % KD;
+    float w = 0.f;
+    if (kk < 9 * coutp) w = p[w_off(L) + (kk % coutp) * K + (kk / coutp) * cinp + c];
+    wt[wt_off(L) + r] = (__bf16)w;
+}
+__global__ void k_prep(const float* p, __bf16* wbf, __bf16* wt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NPARAM) wbf[i] = (__bf16)p[i];
+    if (i >= WT_TOTAL) return;
+    if (i < wt_off(1)) prep_wt<0>(p, wt, i);
+    else if (i < wt_off(2)) prep_wt<1>(p, wt, i - wt_off(1));
+    else if (i < wt_off(3)) prep_wt<2>(p, wt, i - wt_off(2));
+    else if (i < wt_off(4)) prep_wt<3>(p, wt, i - wt_off(3));
+    else prep_wt<4>(p, wt, i - wt_off(4));
+}
+
+// Gather the 9 patterns of each neighbourhood (nbr: B x 9 indices into the
+// n_pat patterns of 64 x 64) and store log(1 + max(I, 0)) as BF16 NHWC with 16
+// channels (9 used).  An index outside [0, n_pat) raises ERR_INDEX and reads
+// as an all-zero pattern.
+__global__ void k_input(const float* pat, int n_pat, const int* nbr, int B, __bf16* X0, int* err) {
+    const int n = B * IN * IN;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const int b = q / (IN * IN), yx = q % (IN * IN);
+        bf16x8 lo, hi = zero8();
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int j = nbr[b * NB + c];
+            float v = 0.f;
+            if (j >= 0 && j < n_pat) v = log1pf(fmaxf(pat[(size_t)j * IN * IN + yx], 0.f));
+            else if (yx == 0) atomicOr(err, ERR_INDEX);
+            if (c < 8) lo[c] = (__bf16)v;
+            else hi[0] = (__bf16)v;
+        }
+        bf16x8* dst = reinterpret_cast<bf16x8*>(X0 + (size_t)q * 16);
+        dst[0] = lo;
+        dst[1] = hi;
+    }
+}
+
+// Forward convolution of layer L over B samples:
+//   z[p][o] = bias[o] + sum_k W[o][k] Xcol[k][p],   Y = bf16(max(z, 0))  (L < 4)
+//   out[p] = z[p][0]                                                   (L = 4)
+// One wave per 16 output pixels and all output channels.
+template <int L>
+__global__ __launch_bounds__(256) void k_fwd(const __bf16* X, const __bf16* W, const float* bias, __bf16* Y,
+                                             float* out, int B) {
+    constexpr int cinp = CINP[L], coutp = COUTP[L], s = STRIDE[L], hin = HIN[L], hout = HOUT[L], K = kp(L);
+    constexpr int MT = coutp / 16;
+    const int lane = threadIdx.x % 64, g = lane / 16, n = lane % 16;
+    const int p0 = (blockIdx.x * 4 + threadIdx.x / 64) * 16;
+    if (p0 >= B * hout * hout) return;
+    const int p = p0 + n;
+    const int b = p / (hout * hout), yo = (p / hout) % hout, xo = p % hout;
+    floatx4 acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const int k = k0 + 8 * g;
+        bf16x8 bv = zero8();
+        if (k < 9 * cinp) {
+            const int tap = k / cinp, c0 = k % cinp;
+            const int yi = yo * s + tap / 3 - 1, xi = xo * s + tap % 3 - 1;
+            if (yi >= 0 && yi < hin && xi >= 0 && xi < hin) bv = ld8(X + (((size_t)b * hin + yi) * hin + xi) * cinp + c0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma(ld8(W + (mt * 16 + n) * K + k), bv, acc[mt]);
+    }
+    if constexpr (L < NLAYER - 1) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            bf16x4 y4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) y4[r] = (__bf16)fmaxf(acc[mt][r] + bias[mt * 16 + 4 * g + r], 0.f);
+            *reinterpret_cast<bf16x4*>(Y + (size_t)p * coutp + mt * 16 + 4 * g) = y4;
+        }
+    } else {
+        if (g == 0) out[p] = acc[0][0] + bias[0];
+    }
+}
+
+// Mean squared error over n outputs, two deterministic passes in FP64.
+__global__ __launch_bounds__(256) void k_mse_partial(const float* out, const float* target, int n, double* part) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double d = (double)out[i] - (double)target[i];
+        s += d * d;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_mse_final(const double* part, int nblk, int n, double* loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[b];
+    *loss = s / n;
+}
+
+// dL/dz_4 = bf16(2 (out - target) / n) in channel 0 of 16
+__global__ void k_mse_grad(const float* out, const float* target, int n, __bf16* G4) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        bf16x8 lo = zero8();
+        lo[0] = (__bf16)(2.0f * (out[i] - target[i]) / (float)n);
+        bf16x8* dst = reinterpret_cast<bf16x8*>(G4 + (size_t)i * 16);
+        dst[0] = lo;
+        dst[1] = zero8();
+    }
+}
+
+// Weight gradient of layer L over one chunk of WCHUNK output pixels:
+//   part[chunk][o][k] = sum_{p in chunk} G[p][o] Xcol[k][p]
+// One wave per (16 o x 16 k) tile of a chunk; the pixel sum is the MFMA reduction.
+template <int L>
+__global__ __launch_bounds__(256) void k_wgrad(const __bf16* G, const __bf16* X, float* part) {
+    constexpr int cinp = CINP[L], coutp = COUTP[L], s = STRIDE[L], hin = HIN[L], hout = HOUT[L], K = kp(L);
+    constexpr int MT = coutp / 16, NT = K / 16;
+    const int lane = threadIdx.x % 64, g = lane / 16, n = lane % 16;
+    const int tile = blockIdx.y * 4 + threadIdx.x / 64;
+    if (tile >= MT * NT) return;
+    const int mt = tile / NT, nt = tile % NT;
+    const int chunk = blockIdx.x;
+    const int o = mt * 16 + n;             // A row held by this lane
+    const int k = nt * 16 + n;             // B column held by this lane
+    const bool kreal = k < 9 * cinp;
+    const int tap = k / cinp, c = k % cinp, du = tap / 3 - 1, dv = tap % 3 - 1;
+    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int q0 = 0; q0 < WCHUNK; q0 += 32) {
+        bf16x8 av, bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int p = chunk * WCHUNK + q0 + 8 * g + e;
+            av[e] = G[(size_t)p * coutp + o];
+            const int b = p / (hout * hout), yo = (p / hout) % hout, xo = p % hout;
+            const int yi = yo * s + du, xi = xo * s + dv;
+            const bool in = kreal && yi >= 0 && yi < hin && xi >= 0 && xi < hin;
+            bv[e] = in ? X[(((size_t)b * hin + yi) * hin + xi) * cinp + c] : (__bf16)0.0f;
+        }
+        acc = mfma(av, bv, acc);
+    }
+    float* dst = part + (size_t)chunk * coutp * K;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[(mt * 16 + 4 * g + r) * K + nt * 16 + n] = acc[r];
+}
+
+// grad[i] += sum over chunks, in chunk order, of part[chunk][i]
+__global__ void k_wreduce(const float* part, int nchunk, int n, float* grad) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
+        grad[i] += s;
+    }
+}
+
+// bias gradient: grad[o] += sum_p G[p][o] (one block per o, fixed-order tree)
+__global__ __launch_bounds__(256) void k_bgrad(const __bf16* G, int P, int coutp, float* grad) {
+    __shared__ float sh[256];
+    const int o = blockIdx.x;
+    float s = 0.f;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) s += (float)G[(size_t)p * coutp + o];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[o] += sh[0];
+}
+
+// Input gradient of layer L (L >= 1) through the ReLU of layer L-1:
+//   Gprev[q][c] = bf16([X[q][c] > 0] sum_{tap, o} WT[c][tap * Cout_p + o] G[p_out(q, tap)][o])
+// where output pixel p_out = ((y + 1 - u) / s, (x + 1 - v) / s) when that is an
+// integer inside the output.  One wave per 16 input pixels and all channels.
+template <int L>
+__global__ __launch_bounds__(256) void k_dgrad(const __bf16* G, const __bf16* WT, const __bf16* X, __bf16* Gprev,
+                                               int B) {
+    constexpr int cinp = CINP[L], coutp = COUTP[L], s = STRIDE[L], hin = HIN[L], hout = HOUT[L], KD = kd(L);
+    constexpr int MT = cinp / 16;
+    const int lane = threadIdx.x % 64, g = lane / 16, n = lane % 16;
+    const int p0 = (blockIdx.x * 4 + threadIdx.x / 64) * 16;
+    if (p0 >= B * hin * hin) return;
+    const int q = p0 + n;
+    const int b = q / (hin * hin), yi = (q / hin) % hin, xi = q % hin;
+    floatx4 acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+    for (int k0 = 0; k0 < KD; k0 += 32) {
+        const int kk = k0 + 8 * g;
+        bf16x8 bv = zero8();
+        if (kk < 9 * coutp) {
+            const int tap = kk / coutp, o0 = kk % coutp;
+            const int ty = yi + 1 - tap / 3, tx = xi + 1 - tap % 3;
+            if (ty >= 0 && tx >= 0 && ty % s == 0 && tx % s == 0 && ty / s < hout && tx / s < hout)
+                bv = ld8(G + (((size_t)b * hout + ty / s) * hout + tx / s) * coutp + o0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma(ld8(WT + (mt * 16 + n) * KD + kk), bv, acc[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const size_t o = (size_t)q * cinp + mt * 16 + 4 * g;
+        const bf16x4 x4 = *reinterpret_cast<const bf16x4*>(X + o);
+        bf16x4 g4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g4[r] = (float)x4[r] > 0.f ? (__bf16)acc[mt][r] : (__bf16)0.0f;
+        *reinterpret_cast<bf16x4*>(Gprev + o) = g4;
+    }
+}
+
+// Adam on the FP32 parameter vector (PyTorch's form: bias-corrected moments,
+// eps added to the corrected square root).
+__global__ void k_adam(float* p, const float* gr, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2s) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = gr[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= (lr / bc1) * mi / (sqrtf(vi) / bc2s + eps);
+    }
+}
+
+// Average the 32 x 32 patches (P of them, centred at round_half_even(centre),
+// rows [cy - 16, cy + 16)) that cover each image pixel; uncovered pixels keep
+// their value.  One thread per pixel, patches visited in order.
+__global__ void k_stitch(const float* patches, const float* centres, int P, int H, int W, float* img) {
+    const int n = H * W;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int y = i / W, x = i % W;
+        float s = 0.f;
+        int cnt = 0;
+        for (int q = 0; q < P; ++q) {
+            const int y0 = (int)rintf(centres[2 * q]) - OUT / 2, x0 = (int)rintf(centres[2 * q + 1]) - OUT / 2;
+            if (y >= y0 && y < y0 + OUT && x >= x0 && x < x0 + OUT) {
+                s += patches[(size_t)q * OUT * OUT + (y - y0) * OUT + (x - x0)];
+                ++cnt;
+            }
+        }
+        if (cnt) img[i] = s / (float)cnt;
+    }
+}
+
+}  // namespace cnn
+}  // namespace ptyr

@@ -23,9 +23,16 @@ constexpr int LINES256 = 16;                   // lines per workgroup
 constexpr int NBLK256 = N256 / LINES256;       // line blocks per wave
 
 // lanes along the line (row passes): thread = line * 16 + lane
-struct RowGeo256 { static constexpr int NL = 256, L = 16, SB = 17, SL = 272; };
-// lanes across lines (column passes): thread = lane * 16 + line
-struct ColGeo256 { static constexpr int NL = 256, L = 16, SB = 17, SL = 274; };
+struct RowGeo256 {
+    static constexpr int NL = 256, L = 16, SB = 17, SL = 272;
+    static constexpr bool WAVE_LOCAL = true;        // the 16 lanes of a line are in one wave
+};
+// lanes across lines (column passes): thread = lane * 16 + line, so the lanes
+// of a line span all four waves and an exchange needs a workgroup barrier
+struct ColGeo256 {
+    static constexpr int NL = 256, L = 16, SB = 17, SL = 274;
+    static constexpr bool WAVE_LOCAL = false;
+};
 constexpr int LDS256 = (LINES256 - 1) * 274 + 15 * 17 + 16;
 
 struct Tables256 {

@@ -170,6 +170,7 @@ template <int N> struct WaveGeo {
     static constexpr int SL = (N == 128) ? 152 : 100;
     static constexpr int SY = N + L;
     static constexpr int LDS_SLOTS = (N - 1) * SL + 15 * SB + L;   // >= N*SY
+    static constexpr bool WAVE_LOCAL = true;      // thread = line * L + lane: a line's lanes share a wave
 };
 
 // position along the line of register r
@@ -254,6 +255,23 @@ template <int L, int SG> __device__ __forceinline__ void twiddle_pass(float2 (&v
 }
 
 // ------------------------------------------------------------ line transforms
+// Each line owns its exchange slots (l * SL .. l * SL + 15 * SB + L - 1, below
+// (l + 1) * SL).  Where the lanes of a line sit in one wave (GEO::WAVE_LOCAL:
+// thread = line * L + lane, 64 / L lines per wave) an exchange only orders the
+// wave's own LDS accesses and needs no workgroup barrier: LDS operations of one
+// wave execute in issue order, and the fences keep the compiler from moving
+// accesses across the exchange.  Code that next touches the buffer with a
+// workgroup-wide pattern (relayout, reductions) starts with a barrier.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <class GEO> __device__ __forceinline__ void exchange_sync() {
+    if constexpr (GEO::WAVE_LOCAL) wave_sync();
+    else __syncthreads();
+}
+
 // NAT -> MID, DFT of sign SG along every line.
 template <class GEO, int SG>
 __device__ __forceinline__ void nat2mid(float2 (&v)[16], float2* lds, const float4* tw, int l, int c) {
@@ -262,12 +280,12 @@ __device__ __forceinline__ void nat2mid(float2 (&v)[16], float2* lds, const floa
     twiddle_pass<L, SG>(v, tw + c);
 #pragma unroll
     for (int b = 0; b < 16; ++b) lds[slot_x<GEO>(l, b, c)] = v[b];
-    __syncthreads();
+    exchange_sync<GEO>();
 #pragma unroll
     for (int be = 0; be < G; ++be)
 #pragma unroll
         for (int a = 0; a < L; ++a) v[be * L + a] = lds[slot_x<GEO>(l, c + L * be, a)];
-    __syncthreads();
+    exchange_sync<GEO>();
 #pragma unroll
     for (int be = 0; be < G; ++be) dftL<L, SG>(&v[be * L]);
 }
@@ -282,10 +300,10 @@ __device__ __forceinline__ void mid2nat(float2 (&v)[16], float2* lds, const floa
     for (int be = 0; be < G; ++be)
 #pragma unroll
         for (int a = 0; a < L; ++a) lds[slot_x<GEO>(l, c + L * be, a)] = v[be * L + a];
-    __syncthreads();
+    exchange_sync<GEO>();
 #pragma unroll
     for (int b = 0; b < 16; ++b) v[b] = lds[slot_x<GEO>(l, b, c)];
-    __syncthreads();
+    exchange_sync<GEO>();
     twiddle_pass<L, SG>(v, tw + c);
     dft16<SG>(v);
 }
@@ -293,6 +311,7 @@ __device__ __forceinline__ void mid2nat(float2 (&v)[16], float2* lds, const floa
 // Re-distribute the field from layout (D0, K0) to (D1, K1) through LDS.
 template <int N, int D0, int K0, int D1, int K1>
 __device__ __forceinline__ void relayout(float2 (&v)[16], float2* lds, int l, int c) {
+    __syncthreads();            // other waves may still read their line-exchange slots
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         int y, x;

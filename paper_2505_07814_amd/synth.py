@@ -300,3 +300,52 @@ def small_case(N: int = 16, S: int = 3, M: int = 2, B: int = 3, H: int = 40,
     tilt = rng.uniform(-tilt_scale, tilt_scale, (B, 2))
     return Workload("small", N, S, M, B, H, W, dx, kv, dz, amp, phase, probe, pos, tilt,
                     float(np.sum(np.abs(probe) ** 2)), seed)
+
+
+# --------------------------------------------------------------------------
+# learned initial guess: neighbourhood scans of random single-slice objects
+# --------------------------------------------------------------------------
+LI_N, LI_DX, LI_KV, LI_DZ, LI_DOSE = 64, 0.2, 300.0, 10.0, 1e5
+LI_H = 144                     # object side: a 10 x 10 raster of step 8 with a 64-px window fits
+LI_SCAN = (10, 10, 8, 36, 0.3)  # ny, nx, step, origin (centre of the first window), jitter
+LI_ATOMS = 51                  # the atom density of the 40-atom 128 x 128 single-slice object
+LI_OBJECT_SEED0 = 10 ** 6      # training object i uses seed 10^6 + i
+LI_EVAL_SEED = 999             # held-out evaluation object
+
+
+def li_probe() -> np.ndarray:
+    """The single-slice optics: 64 x 64 at 0.2 A/px, 300 kV, 20 mrad, 100 A
+    defocus, 1e5 electrons per pattern; shape (1, 64, 64)."""
+    return probe_single(LI_N, LI_DX, LI_KV, 20.0, 100.0)[None] * np.sqrt(LI_DOSE)
+
+
+def li_object(seed: int):
+    """One random single-slice object for the learned initial guess and its
+    scan: (amp, phase) each (1, 144, 144) and positions (100, 2).  The scan
+    jitter uses seed + 500000 so objects and jitters never share a stream."""
+    amp, phase = random_atom_object(LI_H, LI_H, 1, LI_ATOMS, 0.3 / LI_DX, 0.5, seed)
+    ny, nx, step, origin, jitter = LI_SCAN
+    pos = raster_positions(ny, nx, step, origin, jitter, seed + 500000)
+    return amp, phase, pos
+
+
+def li_neighbourhoods(ny: int = 10, nx: int = 10):
+    """3 x 3 neighbourhoods of a row-major ny x nx raster: (nbr, centre) with
+    nbr (K, 9) raster indices in row-major (dy, dx) order and centre (K,) the
+    middle index, for the (ny-2)(nx-2) interior positions."""
+    nbr, ctr = [], []
+    for iy in range(1, ny - 1):
+        for ix in range(1, nx - 1):
+            nbr.append([(iy + a) * nx + ix + b for a in (-1, 0, 1) for b in (-1, 0, 1)])
+            ctr.append(iy * nx + ix)
+    return np.array(nbr, np.int32), np.array(ctr, np.int64)
+
+
+def li_targets(phase2d: np.ndarray, centres: np.ndarray) -> np.ndarray:
+    """True-phase crops (K, 32, 32) with rows round(cy) - 16 .. round(cy) + 15
+    (round half to even) and columns likewise."""
+    out = np.empty((len(centres), 32, 32), np.float32)
+    for q, (cy, cx) in enumerate(centres):
+        y0, x0 = int(np.rint(cy)) - 16, int(np.rint(cx)) - 16
+        out[q] = phase2d[y0:y0 + 32, x0:x0 + 32]
+    return out

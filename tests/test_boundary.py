@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2505_07814_amd import _lib as L
@@ -12,8 +13,8 @@ from paper_2505_07814_amd import _lib as L
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    src = open(os.path.join(ROOT, "include", "ptyr.h")).read()
+def header_functions(name="ptyr.h"):
+    src = open(os.path.join(ROOT, "include", name)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(ptyr_[a-z_]+)\s*\(", src)))
 
@@ -29,7 +30,9 @@ def test_library_exports_every_header_function():
     lib = L.lib()
     names = header_functions()
     assert set(names) == set(L.HEADER_SYMBOLS), names
-    for n in names:
+    cnn = header_functions("ptyr_cnn.h")
+    assert set(cnn) == set(L.CNN_HEADER_SYMBOLS), cnn
+    for n in names + cnn:
         assert hasattr(lib, n), n
 
 
@@ -102,3 +105,40 @@ def test_create_rejects_small_workspace_without_device_work():
     n = lib.ptyr_workspace_bytes(C.byref(g))
     assert lib.ptyr_create(C.byref(g), C.c_void_p(256), n - 1, None, C.byref(ctx)) == L.PTYR_E_NOMEM
     assert lib.ptyr_create(C.byref(g), None, n, None, C.byref(ctx)) == L.PTYR_E_ARG
+
+
+# ---------------------------------------------------------------- learned initial guess
+def test_cnn_param_count_and_layout():
+    from paper_2505_07814_amd import cnn
+    n = L.lib().ptyr_cnn_param_count()
+    # per layer Cout_p * K_p + Cout_p: 32*160+32, 3 x (32*288+32), 16*288+16
+    assert n == 5152 + 3 * 9248 + 4624
+    rng = np.random.default_rng(0)
+    layers = [(rng.standard_normal((co, ci, 3, 3)), rng.standard_normal(co))
+              for ci, co in zip(cnn.CHANNELS[:-1], cnn.CHANNELS[1:])]
+    v = cnn.pack_params(layers)
+    assert v.shape == (n,)
+    back = cnn.unpack_params(v)
+    for (W, b), (W2, b2) in zip(layers, back):
+        np.testing.assert_allclose(W2, W.astype(np.float32), rtol=0, atol=0)
+        np.testing.assert_allclose(b2, b.astype(np.float32), rtol=0, atol=0)
+    # W[o, c, u, v] sits at layer offset + o * K_p + (3u + v) * Cin_p + c
+    assert v[1 * 160 + (3 * 2 + 1) * 16 + 5] == np.float32(layers[0][0][1, 5, 2, 1])
+    off2 = 5152 + 9248
+    assert v[off2 + 7 * 288 + (3 * 1 + 0) * 32 + 31] == np.float32(layers[2][0][7, 31, 1, 0])
+    assert np.count_nonzero(v) == sum(W.size + b.size for W, b in layers)
+
+
+def test_cnn_workspace_and_create_errors():
+    lib = L.lib()
+    assert lib.ptyr_cnn_workspace_bytes(0) == 0
+    a, b = lib.ptyr_cnn_workspace_bytes(1), lib.ptyr_cnn_workspace_bytes(256)
+    assert 0 < a < b
+    ctx = C.c_void_p()
+    assert lib.ptyr_cnn_create(0, C.c_void_p(256), 1 << 30, None, C.byref(ctx)) == L.PTYR_E_ARG
+    assert lib.ptyr_cnn_create(4, None, 1 << 30, None, C.byref(ctx)) == L.PTYR_E_ARG
+    assert lib.ptyr_cnn_create(4, C.c_void_p(256), lib.ptyr_cnn_workspace_bytes(4) - 1, None,
+                               C.byref(ctx)) == L.PTYR_E_NOMEM
+    assert lib.ptyr_cnn_create(4, C.c_void_p(256), 1 << 30, None, None) == L.PTYR_E_ARG
+    assert lib.ptyr_cnn_forward(None, None, None, 1, None, 1, None) == L.PTYR_E_ARG
+    assert lib.ptyr_cnn_sync(None) == L.PTYR_E_ARG

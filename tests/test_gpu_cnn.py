@@ -1,0 +1,183 @@
+"""Parity of the BF16 matrix-core conv net (through the C ABI) with the FP64
+conv-net oracle evaluated at the same BF16 rounding points.
+
+Bars (derived from the arithmetic): the GPU sums BF16 products in FP32 where
+the oracle sums them in FP64, a relative difference of order 1e-6 per sum;
+a stored BF16 value differs only where that difference moves it across a
+rounding boundary (1 ulp = 2^-8 relative, rare).  Output, loss and every
+parameter-gradient block must therefore agree to relative L2 <= 1e-3 (loss
+relative <= 1e-5); they are observed far below that.  Adam and stitching
+are FP32 arithmetic on FP32 inputs: relative 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import convnet as cn
+from oracle.adam import adam_step
+from paper_2505_07814_amd import cnn as gcnn
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.ravel(np.asarray(a, np.float64)), np.ravel(np.asarray(b, np.float64))
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def T(a, dt=None):
+    a = np.ascontiguousarray(a if dt is None else np.asarray(a).astype(dt))
+    return torch.from_numpy(a).to(DEV)
+
+
+def make_case(B, n_pat, seed):
+    """Random weights with non-zero biases (mixed ReLU pattern), Poisson-like
+    count patterns with a bright disc, random neighbourhood tables with
+    repeats, targets of phase-like size."""
+    rng = np.random.default_rng(seed)
+    layers = cn.init_params(seed)
+    layers = [(W, 0.05 * rng.standard_normal(b.shape)) for W, b in layers]
+    vec = gcnn.pack_params(layers)
+    layers32 = gcnn.unpack_params(vec)          # the float32 values both sides use
+    yy, xx = np.mgrid[0:64, 0:64] - 32
+    disc = (yy ** 2 + xx ** 2 <= 13 ** 2) * 150.0 + 0.5
+    pats = rng.poisson(disc * rng.uniform(0.5, 1.5, (n_pat, 64, 64))).astype(np.float32)
+    nbr = rng.integers(0, n_pat, (B, 9)).astype(np.int32)
+    target = (0.3 * rng.standard_normal((B, 32, 32))).astype(np.float32)
+    return layers32, vec, pats, nbr, target
+
+
+@pytest.fixture(scope="module")
+def net():
+    return gcnn.ConvInit(B_max=64, device=DEV)
+
+
+@pytest.mark.parametrize("B,n_pat,seed", [(1, 9, 1), (3, 12, 2), (5, 40, 3)])
+def test_forward_matches_oracle(net, B, n_pat, seed):
+    layers, vec, pats, nbr, _ = make_case(B, n_pat, seed)
+    out = net.forward(T(vec), T(pats), T(nbr)).cpu().numpy()
+    ref = cn.forward(layers, pats[nbr], bf16=True)
+    r = rel(out, ref)
+    print(f"forward B={B}: rel-L2 {r:.2e}")
+    assert r <= 1e-3
+    # and the BF16 net is within the format's precision of the FP64 net
+    assert rel(out, cn.forward(layers, pats[nbr])) < 3e-2
+
+
+@pytest.mark.parametrize("B,n_pat,seed", [(2, 10, 4), (4, 30, 5)])
+def test_gradient_matches_oracle(net, B, n_pat, seed):
+    layers, vec, pats, nbr, target = make_case(B, n_pat, seed)
+    grad = torch.zeros(gcnn.param_count(), dtype=torch.float32, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    net.gradient(T(vec), T(pats), T(nbr), T(target), grad, loss)
+    net.sync()
+    L_ref, g_ref = cn.gradients(layers, pats[nbr], target, bf16=True)
+    g = gcnn.unpack_params(grad.cpu().numpy())
+    assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
+    for l, ((dW, db), (rW, rb)) in enumerate(zip(g, g_ref)):
+        rw, rbias = rel(dW, rW), rel(db, rb)
+        print(f"layer {l}: dW rel-L2 {rw:.2e}, db rel-L2 {rbias:.2e}")
+        assert rw <= 1e-3 and rbias <= 1e-3
+    # the padding of the packed vector receives exactly zero gradient
+    ones = [(np.ones_like(W), np.ones_like(b)) for W, b in layers]
+    padding = gcnn.pack_params(ones) == 0
+    assert padding.sum() > 0 and np.all(grad.cpu().numpy()[padding] == 0)
+
+
+def test_gradient_accumulates_and_is_deterministic(net):
+    _, vec, pats, nbr, target = make_case(6, 20, 6)
+    args = (T(vec), T(pats), T(nbr), T(target))
+    g1 = torch.zeros(gcnn.param_count(), dtype=torch.float32, device=DEV)
+    g2 = torch.zeros_like(g1)
+    net.gradient(*args, g1)
+    net.gradient(*args, g2)
+    net.gradient(*args, g2)
+    net.sync()
+    assert torch.equal(2 * g1, g2)
+
+
+def test_full_batch_sampled(net):
+    """The training launch shape (B = 64 here, the largest this context
+    takes): four sampled neighbourhoods checked against the oracle."""
+    layers, vec, pats, nbr, target = make_case(64, 200, 7)
+    out = net.forward(T(vec), T(pats), T(nbr)).cpu().numpy()
+    pick = [0, 17, 40, 63]
+    ref = cn.forward(layers, pats[nbr[pick]], bf16=True)
+    assert rel(out[pick], ref) <= 1e-3
+
+
+def test_training_batch_gradient_is_sum_of_sub_batches():
+    """At the training batch (B = 256) the gradient of the batch mean equals
+    the weighted sum of the gradients of its four 64-neighbourhood quarters
+    (the output gradient differs by the exact factor 4, so every stored BF16
+    value scales exactly; only FP32 summation order differs)."""
+    big = gcnn.ConvInit(B_max=256, device=DEV)
+    _, vec, pats, nbr, target = make_case(256, 500, 13)
+    P, V = T(pats), T(vec)
+    g = torch.zeros(gcnn.param_count(), dtype=torch.float32, device=DEV)
+    big.gradient(V, P, T(nbr), T(target), g)
+    parts = torch.zeros_like(g)
+    for q in range(4):
+        gq = torch.zeros_like(g)
+        big.gradient(V, P, T(nbr[64 * q:64 * (q + 1)]), T(target[64 * q:64 * (q + 1)]), gq)
+        parts += 0.25 * gq
+    big.sync()
+    assert rel(g.cpu().numpy(), parts.cpu().numpy()) <= 1e-5
+    # and one quarter against the oracle, sampled: the first of its 64
+    layers = gcnn.unpack_params(vec)
+    gq = torch.zeros_like(g)
+    big.gradient(V, P, T(nbr[:1]), T(target[:1]), gq)
+    big.sync()
+    _, g_ref = cn.gradients(layers, pats[nbr[:1]], target[:1], bf16=True)
+    for (dW, db), (rW, rb) in zip(gcnn.unpack_params(gq.cpu().numpy()), g_ref):
+        assert rel(dW, rW) <= 1e-3 and rel(db, rb) <= 1e-3
+
+
+def test_bad_neighbourhood_index_is_reported(net):
+    _, vec, pats, nbr, _ = make_case(2, 9, 8)
+    nbr[1, 4] = 9                                  # == n_pat: out of range
+    net.forward(T(vec), T(pats), T(nbr))
+    with pytest.raises(Exception) as e:
+        net.sync()
+    assert "PTYR_E_ARG" in str(e.value)
+    net.sync()                                     # flag cleared
+
+
+def test_batch_larger_than_context_is_rejected(net):
+    _, vec, pats, nbr, _ = make_case(65, 9, 9)
+    with pytest.raises(Exception):
+        net.forward(T(vec), T(pats), T(nbr))
+
+
+def test_adam_matches_oracle(net):
+    rng = np.random.default_rng(11)
+    n = gcnn.param_count()
+    p0 = rng.standard_normal(n).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    m0 = (0.1 * rng.standard_normal(n)).astype(np.float32)
+    v0 = (0.01 * rng.random(n)).astype(np.float32)
+    P, M, V = T(p0), T(m0), T(v0)
+    net.adam(P, T(g), M, V, step=4, lr=1e-3)
+    net.sync()
+    # the library takes beta1, beta2 as float32: give the oracle the same values
+    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))
+    rp, rm, rv = adam_step(p0.astype(np.float64), g, m0, v0, 3, 1e-3, beta1=b1, beta2=b2)
+    # the float32 result is the correctly rounded update to within 2 ulp of the parameter
+    Pg = P.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Pg - rp) <= 2 * np.spacing(np.abs(rp).astype(np.float32)) + 1e-5 * np.abs(rp - p0))
+    assert rel(M.cpu().numpy(), rm) <= 1e-6 and rel(V.cpu().numpy(), rv) <= 1e-6
+
+
+def test_stitch_matches_oracle(net):
+    rng = np.random.default_rng(12)
+    patches = rng.standard_normal((7, 32, 32)).astype(np.float32)
+    centres = np.array([[40, 40], [40, 48.5], [47.6, 40.2], [60, 70], [20, 20], [90, 95], [16.5, 99]],
+                       np.float32)
+    base = rng.standard_normal((100, 110)).astype(np.float32)
+    img = T(base.copy())
+    net.stitch(T(patches), T(centres), img)
+    net.sync()
+    ref = cn.stitch(patches, centres.astype(np.float64), base)
+    assert rel(img.cpu().numpy(), ref) <= 1e-6

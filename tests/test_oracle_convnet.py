@@ -196,3 +196,6 @@ def test_stitch():
     two = cn.stitch([np.ones((32, 32)), 3 * np.ones((32, 32))], [(40, 40), (40, 48)], base)
     assert two[40, 30] == 1.0 and two[40, 60] == 3.0 and two[40, 40] == 2.0
     assert two[10, 40] == -1.0
+    edge = cn.stitch([p], [(5, 85)], base)         # rows -11..20, cols 69..100: clipped
+    np.testing.assert_array_equal(edge[0:21, 69:90], p[11:32, 0:21])
+    assert edge[21, 70] == -1.0 and edge[5, 68] == -1.0
