@@ -27,8 +27,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t wpart_floats(int B) {
     size_t m = 0;
     for (int l = 0; l < NLAYER; ++l) {
-        const size_t nchunk = (size_t)B * HOUT[l] * HOUT[l] / WCHUNK;
-        const size_t f = nchunk * w_size(l);
+        const size_t nchunk = ((size_t)B * HOUT[l] * HOUT[l] + WCHUNK - 1) / WCHUNK;
+        const size_t f = nchunk * (w_size(l) + COUTP[l]);
         if (f > m) m = f;
     }
     return m;
@@ -76,14 +76,13 @@ void fwd_layer(ptyr_cnn* c, const float* params, int B, float* out) {
 
 template <int L>
 void bwd_layer(ptyr_cnn* c, int B, float* grad) {
-    constexpr int MT = COUTP[L] / 16, NT = kp(L) / 16;
-    const int nchunk = B * HOUT[L] * HOUT[L] / WCHUNK;
+    constexpr int MT = COUTP[L] / 16, NT = kp(L) / 16, PW = w_size(L) + COUTP[L];
+    const int nchunk = (B * HOUT[L] * HOUT[L] + WCHUNK - 1) / WCHUNK;
     hipLaunchKernelGGL(k_wgrad<L>, dim3(nchunk, (MT * NT + 3) / 4), dim3(256), 0, c->stream,
-                       at<__bf16>(c, c->G[L]), at<__bf16>(c, c->X[L]), at<float>(c, c->wpart));
-    hipLaunchKernelGGL(k_wreduce, dim3(blocks_for(w_size(L))), dim3(256), 0, c->stream, at<float>(c, c->wpart),
-                       nchunk, w_size(L), grad + w_off(L));
-    hipLaunchKernelGGL(k_bgrad, dim3(COUTP[L]), dim3(256), 0, c->stream, at<__bf16>(c, c->G[L]),
-                       B * HOUT[L] * HOUT[L], COUTP[L], grad + b_off(L));
+                       at<__bf16>(c, c->G[L]), at<__bf16>(c, c->X[L]), at<float>(c, c->wpart), B);
+    // weights and bias are contiguous in the parameter vector: one reduction
+    hipLaunchKernelGGL(k_wreduce, dim3((PW + 31) / 32), dim3(256), 0, c->stream, at<float>(c, c->wpart), nchunk, PW,
+                       grad + w_off(L));
     if constexpr (L > 0) {
         const int nblk = (B * HIN[L] * HIN[L] + 63) / 64;
         hipLaunchKernelGGL(k_dgrad<L>, dim3(nblk), dim3(256), 0, c->stream, at<__bf16>(c, c->G[L]),

@@ -55,7 +55,7 @@ constexpr int NPARAM = b_off(NLAYER - 1) + COUTP[NLAYER - 1];
 constexpr int wt_size(int l) { return CINP[l] * kd(l); }
 constexpr int wt_off(int l) { return l == 0 ? 0 : wt_off(l - 1) + wt_size(l - 1); }
 constexpr int WT_TOTAL = wt_off(NLAYER - 1) + wt_size(NLAYER - 1);
-constexpr int WCHUNK = 512;                    // output pixels per weight-gradient partial sum
+constexpr int WCHUNK = 2048;                   // output pixels per weight-gradient partial sum
 constexpr int ERR_INDEX = 1;
 
 // per-sample element counts of the stored BF16 tensors
@@ -195,13 +195,16 @@ __global__ void k_mse_grad(const float* out, const float* target, int n, __bf16*
     }
 }
 
-// Weight gradient of layer L over one chunk of WCHUNK output pixels:
-//   part[chunk][o][k] = sum_{p in chunk} G[p][o] Xcol[k][p]
-// One wave per (16 o x 16 k) tile of a chunk; the pixel sum is the MFMA reduction.
+// Weight and bias gradient of layer L over one chunk of WCHUNK output pixels:
+//   part[chunk][o * K + k] = sum_{p in chunk} G[p][o] Xcol[k][p]
+//   part[chunk][Cout_p * K + o] = sum_{p in chunk} G[p][o]        (bias)
+// One wave per (16 o x 16 k) tile of a chunk; the pixel sum is the MFMA
+// reduction.  The waves of the k = 0..15 tiles also add up their G operands
+// for the bias, in a fixed order (own pixels, then lanes 16 and 32 apart).
 template <int L>
-__global__ __launch_bounds__(256) void k_wgrad(const __bf16* G, const __bf16* X, float* part) {
+__global__ __launch_bounds__(256) void k_wgrad(const __bf16* G, const __bf16* X, float* part, int B) {
     constexpr int cinp = CINP[L], coutp = COUTP[L], s = STRIDE[L], hin = HIN[L], hout = HOUT[L], K = kp(L);
-    constexpr int MT = coutp / 16, NT = K / 16;
+    constexpr int MT = coutp / 16, NT = K / 16, PW = w_size(L) + coutp;
     const int lane = threadIdx.x % 64, g = lane / 16, n = lane % 16;
     const int tile = blockIdx.y * 4 + threadIdx.x / 64;
     if (tile >= MT * NT) return;
@@ -211,47 +214,56 @@ __global__ __launch_bounds__(256) void k_wgrad(const __bf16* G, const __bf16* X,
     const int k = nt * 16 + n;             // B column held by this lane
     const bool kreal = k < 9 * cinp;
     const int tap = k / cinp, c = k % cinp, du = tap / 3 - 1, dv = tap % 3 - 1;
+    const int P = B * hout * hout;         // the last chunk may be partial
+    const int qend = min(WCHUNK, P - chunk * WCHUNK);
     floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int q0 = 0; q0 < WCHUNK; q0 += 32) {
+    float bsum = 0.f;
+    for (int q0 = 0; q0 < qend; q0 += 32) {
         bf16x8 av, bv;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int p = chunk * WCHUNK + q0 + 8 * g + e;
-            av[e] = G[(size_t)p * coutp + o];
+            const bool pin = p < P;
+            av[e] = pin ? G[(size_t)p * coutp + o] : (__bf16)0.0f;
             const int b = p / (hout * hout), yo = (p / hout) % hout, xo = p % hout;
             const int yi = yo * s + du, xi = xo * s + dv;
-            const bool in = kreal && yi >= 0 && yi < hin && xi >= 0 && xi < hin;
+            const bool in = pin && kreal && yi >= 0 && yi < hin && xi >= 0 && xi < hin;
             bv[e] = in ? X[(((size_t)b * hin + yi) * hin + xi) * cinp + c] : (__bf16)0.0f;
         }
         acc = mfma(av, bv, acc);
+        if (nt == 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bsum += (float)av[e];
+        }
     }
-    float* dst = part + (size_t)chunk * coutp * K;
+    float* dst = part + (size_t)chunk * PW;
 #pragma unroll
     for (int r = 0; r < 4; ++r) dst[(mt * 16 + 4 * g + r) * K + nt * 16 + n] = acc[r];
-}
-
-// grad[i] += sum over chunks, in chunk order, of part[chunk][i]
-__global__ void k_wreduce(const float* part, int nchunk, int n, float* grad) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
-        grad[i] += s;
+    if (nt == 0) {
+        bsum += __shfl_xor(bsum, 16, 64);
+        bsum += __shfl_xor(bsum, 32, 64);
+        if (g == 0) dst[w_size(L) + o] = bsum;
     }
 }
 
-// bias gradient: grad[o] += sum_p G[p][o] (one block per o, fixed-order tree)
-__global__ __launch_bounds__(256) void k_bgrad(const __bf16* G, int P, int coutp, float* grad) {
-    __shared__ float sh[256];
-    const int o = blockIdx.x;
+// grad[i] += sum over chunks, in chunk order, of part[chunk][i], i < n.
+// A block covers 32 entries with 8 threads each; thread t sums the chunks
+// t, t + 8, ... and the 8 partial sums are added in thread order.
+__global__ __launch_bounds__(256) void k_wreduce(const float* part, int nchunk, int n, float* grad) {
+    __shared__ float sh[8][33];
+    const int e = threadIdx.x % 32, t = threadIdx.x / 32;
+    const int i = blockIdx.x * 32 + e;
     float s = 0.f;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) s += (float)G[(size_t)p * coutp + o];
-    sh[threadIdx.x] = s;
+    if (i < n)
+        for (int ch = t; ch < nchunk; ch += 8) s += part[(size_t)ch * n + i];
+    sh[t][e] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
+    if (t == 0 && i < n) {
+        float r = sh[0][e];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) r += sh[q][e];
+        grad[i] += r;
     }
-    if (threadIdx.x == 0) grad[o] += sh[0];
 }
 
 // Input gradient of layer L (L >= 1) through the ReLU of layer L-1:

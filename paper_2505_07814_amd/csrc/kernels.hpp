@@ -44,6 +44,7 @@ struct WaveArgs {
     int ckK;               // checkpoint spacing (CKPT)
     int nck;               // checkpoints per chain (CKPT)
     int B, M, S, H, W;
+    int chain0;            // first chain (row * M + mode) of this launch; block b handles chain0 + b
     double dx, lam;
     int global_tilt;
     float* Imode;          // B x M x N x N, zero frequency at (0, 0)
@@ -119,6 +120,16 @@ __device__ __forceinline__ void transmit(float2 (&v)[16], const float2* Os, int 
         v[r] = cmul(v[r], (base + Y::dy(r) * W)[o]);
         if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+// the object patch O_s[t + (y, x)] in layout (COL, NAT)
+template <int N>
+__device__ __forceinline__ void load_patch(float2 (&ov)[16], const float2* Os, int W, int ty, int tx, int l, int c) {
+    using Y = Lay<N, COL, NAT>;
+    const float2* base = Os + (size_t)ty * W + tx;
+    const unsigned o = Y::toff(l, c, W);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ov[r] = (base + Y::dy(r) * W)[o];
 }
 
 // phi_0 = F^-1[ Phat_m * R ] (orthonormal), leaves in (COL, NAT)
@@ -204,7 +215,7 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ Tables<N> tab;
     const int l = threadIdx.x / L, c = threadIdx.x % L;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wg = a.chain0 + xcd_remap(blockIdx.x, gridDim.x);
     const int j = wg / a.M, m = wg % a.M;
     const PosInfo pi = a.pinfo[j];
     float* Iout = a.Imode + (size_t)(j * a.M + m) * N * N;
@@ -222,9 +233,19 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     float2 v[16];
     shift_probe<N>(v, a.Phat + (size_t)m * N * N, lds, tab, l, c);
     for (int s = 0; s < a.S - 1; ++s) {
+        // the object patch is read before phi_s is written: waiting for the
+        // reads then does not also wait for those writes (one in-order
+        // counter covers both)
+        float2 ov[16];
+        load_patch<N>(ov, a.Oc + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
         if (full) wstore<N, COL, NAT>(v, sl.phi(s), N, l, c);
         else if (ckpt && s % a.ckK == 0) wstore<N, COL, NAT>(v, sl.ckpt(s / a.ckK), N, l, c);
-        slice_step<N>(v, a.Oc + (size_t)s * HW, a.W, pi.ty, pi.tx, full ? sl.spec(s + 1) : nullptr, lds, tab, l, c);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], ov[r]);
+        fft2_from_col<N>(v, lds, tab.tw, l, c);
+        apply_h<N, false>(v, tab, 1.0f / ((float)N * N), l, c);
+        if (full) wstore<N, ROW, MID>(v, sl.spec(s + 1), N, l, c);
+        ifft2_to_col<N>(v, lds, tab.tw, l, c);
     }
     const int s = a.S - 1;
     if (full) wstore<N, COL, NAT>(v, sl.phi(s), N, l, c);
@@ -273,7 +294,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ Tables<N> tab;
     const int l = threadIdx.x / L, c = threadIdx.x % L;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wg = a.chain0 + xcd_remap(blockIdx.x, gridDim.x);
     const int j = wg / a.M, m = wg % a.M;
     const PosInfo pi = a.pinfo[j];
     float* part = a.part + (size_t)(j * a.M + m) * 8;

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
     __shared__ float2 lds[LDS256];
     __shared__ Tables256 tab;
     const WaveArgs& a = P.a;
-    const int ch = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int ch = a.chain0 + blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
     const int j = ch / a.M;
     const PosInfo pi = a.pinfo[j];
     if (pi.ty < 0) return;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k256_fwd_col(Pass256 P) {
     __shared__ float2 lds[LDS256];
     __shared__ Tables256 tab;
     const WaveArgs& a = P.a;
-    const int ch = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int ch = a.chain0 + blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
     const int j = ch / a.M, m = ch % a.M;
     const PosInfo pi = a.pinfo[j];
     const int l = threadIdx.x % 16, c = threadIdx.x / 16, x = blk * LINES256 + l;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
     __shared__ float2 lds[LDS256];
     __shared__ Tables256 tab;
     const WaveArgs& a = P.a;
-    const int ch = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int ch = a.chain0 + blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
     const int j = ch / a.M, m = ch % a.M;
     const PosInfo pi = a.pinfo[j];
     const int l = threadIdx.x % 16, c = threadIdx.x / 16, x = blk * LINES256 + l;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
     __shared__ float2 lds[LDS256];
     __shared__ Tables256 tab;
     const WaveArgs& a = P.a;
-    const int ch = blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int ch = a.chain0 + blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
     const int j = ch / a.M;
     const PosInfo pi = a.pinfo[j];
     if (pi.ty < 0) return;

@@ -94,16 +94,25 @@ __device__ __forceinline__ double powp(double v, double p) {
     if (p == 0.5) return sqrt(v);
     return pow(v, p);
 }
+// v^(p-1) for v > 0
+__device__ __forceinline__ double powm1(double v, double p) {
+    if (p == 1.0) return 1.0;
+    if (p == 0.5) return 1.0 / sqrt(v);
+    return pow(v, p - 1.0);
+}
 
 // pass 1 of the loss: per-block sums of E = I_meas^p and of the residual term
+// Rows [row0, row0 + B) of a batch: Im, midx (when given) and part start at
+// that range's entries; without midx, row j of the range reads measured
+// pattern row0 + j.
 __global__ void k_loss_partial(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int NN,
-                               int kind, double p, double* part, int* err) {
+                               int kind, double p, int row0, double* part, int* err) {
     __shared__ double sh[3 * 256];
     double sE = 0.0, sR = 0.0, bad = 0.0;
     size_t n = (size_t)B * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         size_t j = e / NN, q = e % NN;
-        long row = midx ? (long)midx[j] : (long)j;
+        long row = midx ? (long)midx[j] : (long)(row0 + j);
         if (row < 0 || row >= n_meas) {
             if (q == 0) atomicOr(err, ERR_INDEX);
             continue;
@@ -164,15 +173,18 @@ __global__ void k_loss_final(const double* part, int nblk, double K, int kind, i
 }
 
 // dL/dI per value (layout of I_model) and w = 2 dL/dI for the gradient kernel
-// (zero frequency at (0, 0))
+// (zero frequency at (0, 0)).  With unscaled set, both omit the batch factor
+// c = scal[1] (which needs the whole batch's residual): the gradient kernels
+// are linear in w, and the kernels that reduce their outputs apply c.  Row
+// offsets as in k_loss_partial.
 __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int N,
-                            int kind, double p, const double* scal, float* dLdI, float* w2) {
+                            int kind, double p, int row0, const double* scal, int unscaled, float* dLdI, float* w2) {
     const int NN = N * N;
-    const double c = scal[1];
+    const double c = unscaled ? 1.0 : scal[1];
     size_t n = (size_t)B * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         size_t j = e / NN, q = e % NN;
-        long row = midx ? (long)midx[j] : (long)j;
+        long row = midx ? (long)midx[j] : (long)(row0 + j);
         const size_t e2 = j * NN + shift_index((int)q, N);
         if (row < 0 || row >= n_meas) {
             if (dLdI) dLdI[e] = 0.f;
@@ -184,10 +196,61 @@ __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, i
         double dA = kind == PTYR_LOSS_GAUSSIAN ? (A - E) * c : -(E / (A + POISSON_EPS) - 1.0) * c;
         double dI;
         if (p == 1.0) dI = dA;
-        else dI = I > 0.0 ? dA * p * pow(I, p - 1.0) : 0.0;
+        else dI = I > 0.0 ? dA * p * powm1(I, p) : 0.0;
         if (dLdI) dLdI[e] = (float)dI;
         if (w2) w2[e2] = (float)(2.0 * dI);
     }
+}
+
+// Rows [row0, row0 + nr) of a batch once their forward chains are done, in
+// one pass: the mode sum I (fftshifted, as k_modesum), per-block loss
+// partial sums (as k_loss_partial) and the gradient weights w = 2 dL/dI
+// without the batch factor (as k_loss_grad with unscaled set).  Imode, I,
+// midx and w2 start at row row0's entries.  A fixed grid and a fixed
+// element-to-block map keep the sums deterministic.
+__global__ __launch_bounds__(256) void k_loss_rows(const float* Imode, float* I, const float* Ie, const int* midx,
+                                                   int n_meas, int nr, int M, int N, int kind, double p, int row0,
+                                                   double* part, float* w2, int* err) {
+    __shared__ double sh[3 * 256];
+    const int NN = N * N;
+    double sE = 0.0, sR = 0.0, bad = 0.0;
+    const size_t n = (size_t)nr * NN;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t j = e / NN;
+        const int q = (int)(e % NN), qs = shift_index(q, N);
+        const float* src = Imode + j * M * NN + qs;
+        float sum = 0.f;
+        for (int m = 0; m < M; ++m) sum += src[(size_t)m * NN];
+        I[e] = sum;
+        const long row = midx ? (long)midx[j] : (long)(row0 + j);
+        float* w = w2 + j * NN + qs;
+        if (row < 0 || row >= n_meas) {
+            if (q == 0) atomicOr(err, ERR_INDEX);
+            *w = 0.f;
+            continue;
+        }
+        const float em = Ie[(size_t)row * NN + q];
+        const double Iv = fmax((double)sum, 0.0), Em = fmax((double)em, 0.0);
+        const double A = powp(Iv, p), E = powp(Em, p);
+        if (!isfinite(sum) || !isfinite(em)) bad += 1.0;
+        else {
+            sE += E;
+            if (kind == PTYR_LOSS_GAUSSIAN) sR += (A - E) * (A - E);
+            else sR += E * log(A + POISSON_EPS) - A;
+        }
+        const double dA = kind == PTYR_LOSS_GAUSSIAN ? (A - E) : -(E / (A + POISSON_EPS) - 1.0);
+        const double dI = p == 1.0 ? dA : (Iv > 0.0 ? dA * p * powm1(Iv, p) : 0.0);
+        *w = (float)(2.0 * dI);
+    }
+    sh[threadIdx.x] = sE; sh[256 + threadIdx.x] = sR; sh[512 + threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = sh[k * 256];
 }
 
 // Object gradient: each workgroup owns a 32 x 32 tile of one slice and sums,
@@ -200,7 +263,7 @@ __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, i
 constexpr int SCATTER_MB = 8;
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int B, int M, int S,
                                                         int N, int H, int W, const float* amp, const float* phase,
-                                                        float* g_amp, float* g_phase) {
+                                                        const double* scale, float* g_amp, float* g_phase) {
     const int ntx = (W + 31) / 32;
     const int tile = blockIdx.x, s = blockIdx.y;
     const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
@@ -238,6 +301,7 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
         }
     }
     if (!touched || y >= H) return;
+    const float sc = (float)*scale;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int x = xb + k;
@@ -246,19 +310,21 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
         float sn, cs;
         sincosf(phase[o], &sn, &cs);
         float a = amp[o];
-        float2 G = acc[k];
+        float2 G = cscale(acc[k], sc);
         if (g_amp) g_amp[o] += G.x * cs + G.y * sn;          // Re(conj(G) e^{i phi})
         if (g_phase) g_phase[o] += a * (G.y * cs - G.x * sn); // Im(G conj(a e^{i phi}))
     }
 }
 
-// sum over batch rows of the probe-spectrum gradients (fixed order)
-__global__ void k_sum_rows(const float2* src, float2* dst, int B, int M, int NN) {
+// sum over batch rows of the probe-spectrum gradients (fixed order), times
+// the batch factor
+__global__ void k_sum_rows(const float2* src, float2* dst, int B, int M, int NN, const double* scale) {
     size_t n = (size_t)M * NN;
+    const float sc = (float)*scale;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         float2 s = make_float2(0.f, 0.f);
         for (int j = 0; j < B; ++j) s = cadd(s, src[(size_t)j * n + e]);
-        dst[e] = s;
+        dst[e] = cscale(s, sc);
     }
 }
 
@@ -271,9 +337,11 @@ __global__ void k_sum_rows(const float2* src, float2* dst, int B, int M, int NN)
 // fixed order by a block tree.
 __global__ __launch_bounds__(256) void k_param_grads(const float* part, int nblk, const PosInfo* pinfo, int B,
                                                      int M, const float* tilt, int global_tilt, const float* dzp,
-                                                     double lam, float* g_pos, float* g_tilt, float* g_dz) {
+                                                     double lam, const double* scale, float* g_pos, float* g_tilt,
+                                                     float* g_dz) {
     __shared__ double sh[3][256];
     const double two_pi = 6.283185307179586;
+    const double sc = *scale;                 // batch factor of the loss gradient
     const double dz = *dzp;
     double sdz = 0.0, sty = 0.0, stx = 0.0;
     for (int j = threadIdx.x; j < B; j += blockDim.x) {
@@ -288,6 +356,7 @@ __global__ __launch_bounds__(256) void k_param_grads(const float* part, int nblk
         const float* th = global_tilt ? tilt : tilt + 2 * row;
         const double ty = tan((double)th[0]), tx = tan((double)th[1]);
         const double cy = cos((double)th[0]), cx = cos((double)th[1]);
+        k2 *= sc; kx *= sc; ky *= sc; py *= sc; px *= sc;
         sdz += -3.141592653589793 * lam * k2 + two_pi * (tx * kx + ty * ky);
         const double gy = two_pi * dz * ky / (cy * cy), gx = two_pi * dz * kx / (cx * cx);
         if (global_tilt) { sty += gy; stx += gx; }
@@ -309,16 +378,31 @@ __global__ __launch_bounds__(256) void k_param_grads(const float* part, int nblk
 
 // Adam (PyTorch's form): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
 // p -= (lr / bc1) * m / (sqrt(v) / sqrt(bc2) + eps)
-__global__ void k_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
-                       float eps, float bc1, float bc2s) {
+// All parameter blocks of a step in one launch: segment k covers elements
+// [off[k], off[k+1]) of the concatenated index range.
+constexpr int ADAM_SEGS = 6;
+struct AdamSegs {
+    float* p[ADAM_SEGS];
+    const float* g[ADAM_SEGS];
+    float* m[ADAM_SEGS];
+    float* v[ADAM_SEGS];
+    size_t off[ADAM_SEGS + 1];
+    float lr[ADAM_SEGS];
+};
+__global__ void k_adam_segs(AdamSegs a, float b1, float b2, float eps, float bc1, float bc2s) {
+    const size_t n = a.off[ADAM_SEGS];
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        float gi = g[i];
-        float mi = b1 * m[i] + (1.f - b1) * gi;
-        float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-        m[i] = mi;
-        v[i] = vi;
-        float denom = sqrtf(vi) / bc2s + eps;
-        p[i] -= (lr / bc1) * mi / denom;
+        int k = 0;
+#pragma unroll
+        for (int q = 1; q < ADAM_SEGS; ++q)
+            if (i >= a.off[q]) k = q;
+        const size_t e = i - a.off[k];
+        const float gi = a.g[k][e];
+        const float mi = b1 * a.m[k][e] + (1.f - b1) * gi;
+        const float vi = b2 * a.v[k][e] + (1.f - b2) * gi * gi;
+        a.m[k][e] = mi;
+        a.v[k][e] = vi;
+        a.p[k][e] -= (a.lr[k] / bc1) * mi / (sqrtf(vi) / bc2s + eps);
     }
 }
 
@@ -367,7 +451,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.Imode = take(B * M * NN * sizeof(float));
     L.Ibuf = take(B * NN * sizeof(float));
     L.wbuf = take(B * NN * sizeof(float));
-    L.lpart = take(3 * NPART * sizeof(double));
+    L.lpart = take(2 * 3 * NPART * sizeof(double));   // one block of NPART per row range
     L.scal = take(8 * sizeof(double));
     L.err = take(sizeof(int));
     L.store = take(B * M * (size_t)L.waves_per_chain * NN * sizeof(float2));
@@ -398,6 +482,11 @@ struct ptyr_ctx {
     char* ws;
     size_t ws_bytes;
     hipStream_t stream;
+    // second stream for the other row range of a split batch, with the
+    // fork / join events that order it against `stream` (default priority)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_join = nullptr;
+    int n_cu = 0;
     Layout L;
     int fwd_valid;   // waves / intensities of the last forward are in the workspace
     int fwd_B;
@@ -412,16 +501,17 @@ namespace {
 constexpr int MAX_TIMED = 4096;
 struct TimedLaunch {
     ptyr_ctx* c;
+    hipStream_t st;
     int slot;
-    TimedLaunch(ptyr_ctx* cc, int kind) : c(cc), slot(-1) {
+    TimedLaunch(ptyr_ctx* cc, int kind, hipStream_t s) : c(cc), st(s), slot(-1) {
         if (c->timing && c->ev_used < MAX_TIMED) {
             slot = c->ev_used++;
             c->ev_kind[slot] = kind;
-            hipEventRecord(c->ev[2 * slot], c->stream);
+            hipEventRecord(c->ev[2 * slot], st);
         }
     }
     ~TimedLaunch() {
-        if (slot >= 0) hipEventRecord(c->ev[2 * slot + 1], c->stream);
+        if (slot >= 0) hipEventRecord(c->ev[2 * slot + 1], st);
     }
 };
 }  // namespace
@@ -507,15 +597,30 @@ ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, vo
     c->L = L;
     c->fwd_valid = 0;
     c->fwd_B = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        ptyr_destroy(c);
+        return PTYR_E_DEVICE;
+    }
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, c->stream, at<float>(c, L.err), (size_t)1);
-    if (hipGetLastError() != hipSuccess) { delete c; return PTYR_E_DEVICE; }
+    if (hipGetLastError() != hipSuccess) { ptyr_destroy(c); return PTYR_E_DEVICE; }
     *out = c;
     return PTYR_OK;
 }
 
 void ptyr_destroy(ptyr_ctx* ctx) {
     if (!ctx) return;
+    if (ctx->side) hipStreamSynchronize(ctx->side);
     for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+    if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_mid) hipEventDestroy(ctx->ev_mid);
+    if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+    if (ctx->side) hipStreamDestroy(ctx->side);
     delete ctx;
 }
 
@@ -534,7 +639,8 @@ ptyr_status ptyr_timing_enable(ptyr_ctx* c, int on) {
 
 ptyr_status ptyr_timing_read(ptyr_ctx* c, int which, double* total_ms, int* launches) {
     if (!c || !total_ms || !launches) return PTYR_E_ARG;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return PTYR_E_DEVICE;
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipStreamSynchronize(c->side) != hipSuccess)
+        return PTYR_E_DEVICE;
     double tot = 0.0;
     int n = 0;
     for (int i = 0; i < c->ev_used; ++i) {
@@ -583,6 +689,7 @@ WaveArgs wave_args(ptyr_ctx* c, const float* tilt, const float* dz, int B) {
     a.ckK = c->L.ckK;
     a.nck = c->L.nck;
     a.B = B; a.M = g.M; a.S = g.S; a.H = g.H; a.W = g.W;
+    a.chain0 = 0;
     a.dx = g.dx;
     a.lam = g.lambda;
     a.global_tilt = (g.flags & PTYR_GLOBAL_TILT) ? 1 : 0;
@@ -594,16 +701,19 @@ WaveArgs wave_args(ptyr_ctx* c, const float* tilt, const float* dz, int B) {
     return a;
 }
 
-template <int N> void launch_forward(ptyr_ctx* c, const WaveArgs& a, int B) {
-    TimedLaunch t(c, PTYR_K_FORWARD);
-    hipLaunchKernelGGL(k_forward<N>, dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
+// the fused kernels over chains [c0, c0 + nc) (chain = row * M + mode) on stream st
+template <int N> void launch_forward(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
+    TimedLaunch t(c, PTYR_K_FORWARD, st);
+    a.chain0 = c0;
+    hipLaunchKernelGGL(k_forward<N>, dim3(nc), dim3(N * N / 16), 0, st, a);
 }
-template <int N> void launch_gradient(ptyr_ctx* c, const WaveArgs& a, int B) {
-    TimedLaunch t(c, PTYR_K_GRADIENT);
+template <int N> void launch_gradient(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
+    TimedLaunch t(c, PTYR_K_GRADIENT, st);
+    a.chain0 = c0;
     if (a.keep == KEEP_FULL)
-        hipLaunchKernelGGL((k_gradient<N, KEEP_FULL>), dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
+        hipLaunchKernelGGL((k_gradient<N, KEEP_FULL>), dim3(nc), dim3(N * N / 16), 0, st, a);
     else
-        hipLaunchKernelGGL((k_gradient<N, KEEP_CKPT>), dim3(B * c->g.M), dim3(N * N / 16), 0, c->stream, a);
+        hipLaunchKernelGGL((k_gradient<N, KEEP_CKPT>), dim3(nc), dim3(N * N / 16), 0, st, a);
 }
 // N = 256: forward and gradient as line passes (lines256.hpp)
 Pass256 pass256(ptyr_ctx* c, const WaveArgs& a, int s) {
@@ -613,23 +723,35 @@ Pass256 pass256(ptyr_ctx* c, const WaveArgs& a, int s) {
     P.s = s;
     return P;
 }
-void forward256(ptyr_ctx* c, const WaveArgs& a, int B) {
-    TimedLaunch t(c, PTYR_K_FORWARD);
-    const dim3 grid(B * c->g.M * NBLK256), blk(256);
-    hipLaunchKernelGGL(k256_fwd_col, grid, blk, 0, c->stream, pass256(c, a, -1));
+void forward256(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
+    TimedLaunch t(c, PTYR_K_FORWARD, st);
+    a.chain0 = c0;
+    const dim3 grid(nc * NBLK256), blk(256);
+    hipLaunchKernelGGL(k256_fwd_col, grid, blk, 0, st, pass256(c, a, -1));
     for (int s = 0; s < a.S; ++s) {
-        hipLaunchKernelGGL(k256_fwd_row, grid, blk, 0, c->stream, pass256(c, a, s));
-        hipLaunchKernelGGL(k256_fwd_col, grid, blk, 0, c->stream, pass256(c, a, s));
+        hipLaunchKernelGGL(k256_fwd_row, grid, blk, 0, st, pass256(c, a, s));
+        hipLaunchKernelGGL(k256_fwd_col, grid, blk, 0, st, pass256(c, a, s));
     }
 }
-void gradient256(ptyr_ctx* c, const WaveArgs& a, int B) {
-    TimedLaunch t(c, PTYR_K_GRADIENT);
-    const dim3 grid(B * c->g.M * NBLK256), blk(256);
-    hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, c->stream, pass256(c, a, a.S));
+void gradient256(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
+    TimedLaunch t(c, PTYR_K_GRADIENT, st);
+    a.chain0 = c0;
+    const dim3 grid(nc * NBLK256), blk(256);
+    hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, st, pass256(c, a, a.S));
     for (int s = a.S - 1; s >= 0; --s) {
-        hipLaunchKernelGGL(k256_grad_row, grid, blk, 0, c->stream, pass256(c, a, s));
-        hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, c->stream, pass256(c, a, s));
+        hipLaunchKernelGGL(k256_grad_row, grid, blk, 0, st, pass256(c, a, s));
+        hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, st, pass256(c, a, s));
     }
+}
+void forward_chains(ptyr_ctx* c, const WaveArgs& a, int c0, int nc, hipStream_t st) {
+    if (c->g.N == 64) launch_forward<64>(c, a, c0, nc, st);
+    else if (c->g.N == 128) launch_forward<128>(c, a, c0, nc, st);
+    else forward256(c, a, c0, nc, st);
+}
+void gradient_chains(ptyr_ctx* c, const WaveArgs& a, int c0, int nc, hipStream_t st) {
+    if (c->g.N == 64) launch_gradient<64>(c, a, c0, nc, st);
+    else if (c->g.N == 128) launch_gradient<128>(c, a, c0, nc, st);
+    else gradient256(c, a, c0, nc, st);
 }
 
 template <int N> void launch_probe_fft(ptyr_ctx* c, const float* probe) {
@@ -641,50 +763,98 @@ template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe) {
                        at<float2>(c, c->L.gPsum), reinterpret_cast<float2*>(g_probe));
 }
 
-ptyr_status run_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
-                        const float* tilt, const float* dz, const int* idx, int n_rows, int B) {
+// Work shared by every row of a batch: transmission of all slices, validated
+// positions, probe spectra.
+void prepare_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
+                     const int* idx, int n_rows, int B) {
     const ptyr_geom& g = c->g;
     size_t nobj = (size_t)g.S * g.H * g.W;
     hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, c->stream, amp, phase,
                        at<float2>(c, c->L.Oc), nobj);
     hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, c->stream, pos, idx, idx ? n_rows : B, B,
                        g.N, g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err));
-    WaveArgs a = wave_args(c, tilt, dz, B);
-    if (g.N == 64) { launch_probe_fft<64>(c, probe); launch_forward<64>(c, a, B); }
-    else if (g.N == 128) { launch_probe_fft<128>(c, probe); launch_forward<128>(c, a, B); }
+    if (g.N == 64) launch_probe_fft<64>(c, probe);
+    else if (g.N == 128) launch_probe_fft<128>(c, probe);
     else {
         const dim3 grid(g.M * NBLK256), blk(256);
         hipLaunchKernelGGL((k256_fft<-1, true, false>), grid, blk, 0, c->stream,
                            reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat));
         hipLaunchKernelGGL((k256_fft<-1, false, false>), grid, blk, 0, c->stream, at<float2>(c, c->L.Phat),
                            at<float2>(c, c->L.Phat));
-        forward256(c, a, B);
     }
-    size_t NN = (size_t)g.N * g.N;
-    hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)B * NN)), dim3(256), 0, c->stream,
-                       at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, g.N);
+}
+
+void modesum_rows(ptyr_ctx* c, int r0, int nr, hipStream_t st) {
+    const ptyr_geom& g = c->g;
+    const size_t NN = (size_t)g.N * g.N;
+    hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)nr * NN)), dim3(256), 0, st,
+                       at<float>(c, c->L.Imode) + (size_t)r0 * g.M * NN, at<float>(c, c->L.Ibuf) + (size_t)r0 * NN,
+                       nr, g.M, g.N);
+}
+
+ptyr_status run_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
+                        const float* tilt, const float* dz, const int* idx, int n_rows, int B) {
+    prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
+    forward_chains(c, wave_args(c, tilt, dz, B), 0, B * c->g.M, c->stream);
+    modesum_rows(c, 0, B, c->stream);
     if (hipGetLastError() != hipSuccess) return PTYR_E_DEVICE;
     c->fwd_valid = 1;
     c->fwd_B = B;
     return PTYR_OK;
 }
 
-ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* midx, int n_meas, int B,
-                     double* loss_dev, float* dLdI, float* w2) {
+// Mode sum, loss partial sums (into partial-sum range `slot` of NPART
+// blocks, so that the final pass adds ranges in a fixed order) and unscaled
+// gradient weights of rows [r0, r0 + nr).  nm: measured patterns addressable
+// through midx, or the batch size without it.
+void loss_rows(ptyr_ctx* c, const float* Ie, const int* midx, int nm, int r0, int nr, int slot, hipStream_t st) {
     const ptyr_geom& g = c->g;
-    int NN = g.N * g.N;
-    size_t n = (size_t)B * NN;
-    int nblk = std::min(NPART, grid_for(n));
-    const int nm = midx ? n_meas : B;
-    hipLaunchKernelGGL(k_loss_partial, dim3(nblk), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, g.loss_kind,
-                       g.loss_p, at<double>(c, c->L.lpart), at<int>(c, c->L.err));
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, c->stream, at<double>(c, c->L.lpart), nblk, (double)n,
+    const size_t NN = (size_t)g.N * g.N;
+    hipLaunchKernelGGL(k_loss_rows, dim3(NPART), dim3(256), 0, st, at<float>(c, c->L.Imode) + (size_t)r0 * g.M * NN,
+                       at<float>(c, c->L.Ibuf) + (size_t)r0 * NN, Ie, midx ? midx + r0 : nullptr, nm, nr, g.M, g.N,
+                       g.loss_kind, g.loss_p, r0, at<double>(c, c->L.lpart) + 3 * (size_t)slot * NPART,
+                       at<float>(c, c->L.wbuf) + (size_t)r0 * NN, at<int>(c, c->L.err));
+}
+
+void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev) {
+    const ptyr_geom& g = c->g;
+    const double n = (double)B * g.N * g.N;
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, c->stream, at<double>(c, c->L.lpart), nslots * NPART, n,
                        g.loss_kind, (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
                        at<int>(c, c->L.err));
-    if (dLdI || w2)
+}
+
+ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* midx, int n_meas, int B,
+                     double* loss_dev, float* dLdI) {
+    const ptyr_geom& g = c->g;
+    const int NN = g.N * g.N;
+    const size_t n = (size_t)B * NN;
+    const int nm = midx ? n_meas : B;
+    hipLaunchKernelGGL(k_loss_partial, dim3(NPART), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, g.loss_kind,
+                       g.loss_p, 0, at<double>(c, c->L.lpart), at<int>(c, c->L.err));
+    loss_final(c, 1, B, loss_dev);
+    if (dLdI)
         hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, g.N,
-                           g.loss_kind, g.loss_p, at<double>(c, c->L.scal), dLdI, w2);
+                           g.loss_kind, g.loss_p, 0, at<double>(c, c->L.scal), 0, dLdI, nullptr);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
+}
+
+// A batch of more chains (one workgroup each, one workgroup per compute unit)
+// than the chip has compute units would leave part of the chip idle in the
+// second round of each fused kernel.  It runs instead as: forward of the
+// first n_cu chains (every compute unit busy); forward of the remaining
+// chains on the side stream, which takes compute units as the first forward
+// ends; meanwhile the loss of the rows wholly in the first range and the
+// gradient of as many of their chains as there are compute units left over;
+// on the side stream, once the second forward is done, the loss of the
+// remaining rows and the gradient of all remaining chains.  Small kernels are
+// issued only when compute units are free, so they are not queued behind
+// pending workgroups.
+// Returns the size of the first forward range (0: no split).
+int split_chains(const ptyr_ctx* c, int B) {
+    const ptyr_geom& g = c->g;
+    if (g.N > 128 || c->n_cu <= 0 || B * g.M <= c->n_cu) return 0;
+    return c->n_cu / g.M >= 1 ? c->n_cu : 0;
 }
 
 ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
@@ -692,30 +862,51 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
                         const float* I_meas, float* g_amp, float* g_phase, float* g_probe, float* g_pos,
                         float* g_tilt, float* g_dz, double* loss_dev, unsigned flags) {
     const ptyr_geom& g = c->g;
-    ptyr_status st;
-    if (!(flags & PTYR_REUSE_FORWARD) || !c->fwd_valid || c->fwd_B != B) {
-        st = run_forward(c, amp, phase, probe, pos, tilt, dz, idx, n_rows, B);
-        if (st != PTYR_OK) return st;
+    const int M = g.M, nm = idx ? n_rows : B, BM = B * M;
+    const bool reuse = (flags & PTYR_REUSE_FORWARD) && c->fwd_valid && c->fwd_B == B;
+    if (!reuse) prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
+    const WaveArgs a = wave_args(c, tilt, dz, B);
+    const int nA = reuse ? 0 : split_chains(c, B);
+    if (nA) {
+        const int rA = nA / M;                                     // rows complete after the first forward
+        const int g1 = std::min(rA * M, std::max(0, c->n_cu - (BM - nA)));   // early gradient chains
+        if (hipEventRecord(c->ev_fork, c->stream) != hipSuccess ||
+            hipStreamWaitEvent(c->side, c->ev_fork, 0) != hipSuccess)
+            return PTYR_E_DEVICE;
+        forward_chains(c, a, 0, nA, c->stream);
+        forward_chains(c, a, nA, BM - nA, c->side);
+        loss_rows(c, I_meas, idx, nm, 0, rA, 0, c->stream);
+        // the side stream continues with the remaining rows once the first
+        // range's forward and loss are done (its rows' weights are read by
+        // the remaining gradient chains of the first range)
+        if (hipEventRecord(c->ev_mid, c->stream) != hipSuccess ||
+            hipStreamWaitEvent(c->side, c->ev_mid, 0) != hipSuccess)
+            return PTYR_E_DEVICE;
+        if (g1 > 0) gradient_chains(c, a, 0, g1, c->stream);
+        loss_rows(c, I_meas, idx, nm, rA, B - rA, 1, c->side);
+        gradient_chains(c, a, g1, BM - g1, c->side);
+        if (hipEventRecord(c->ev_join, c->side) != hipSuccess ||
+            hipStreamWaitEvent(c->stream, c->ev_join, 0) != hipSuccess)
+            return PTYR_E_DEVICE;
     } else {
-        size_t NN = (size_t)g.N * g.N;
-        hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)B * NN)), dim3(256), 0, c->stream,
-                           at<float>(c, c->L.Imode), at<float>(c, c->L.Ibuf), B, g.M, g.N);
+        if (!reuse) forward_chains(c, a, 0, BM, c->stream);
+        loss_rows(c, I_meas, idx, nm, 0, B, 0, c->stream);
+        gradient_chains(c, a, 0, BM, c->stream);
     }
-    st = run_loss(c, at<float>(c, c->L.Ibuf), I_meas, idx, n_rows, B, loss_dev, nullptr, at<float>(c, c->L.wbuf));
-    if (st != PTYR_OK) return st;
-    WaveArgs a = wave_args(c, tilt, dz, B);
-    if (g.N == 64) launch_gradient<64>(c, a, B);
-    else if (g.N == 128) launch_gradient<128>(c, a, B);
-    else gradient256(c, a, B);
+    c->fwd_valid = 1;
+    c->fwd_B = B;
+    loss_final(c, nA ? 2 : 1, B, loss_dev);
+    const double* scale = at<double>(c, c->L.scal) + 1;     // the batch factor of w
     if (g_amp || g_phase) {
         int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
         hipLaunchKernelGGL(k_scatter_object, dim3(ntiles, g.S), dim3(256), 0, c->stream, at<float2>(c, c->L.gO),
-                           at<PosInfo>(c, c->L.pinfo), B, g.M, g.S, g.N, g.H, g.W, amp, phase, g_amp, g_phase);
+                           at<PosInfo>(c, c->L.pinfo), B, g.M, g.S, g.N, g.H, g.W, amp, phase, scale, g_amp,
+                           g_phase);
     }
     if (g_probe) {
         int NN = g.N * g.N;
         hipLaunchKernelGGL(k_sum_rows, dim3(grid_for((size_t)g.M * NN)), dim3(256), 0, c->stream,
-                           at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B, g.M, NN);
+                           at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B, g.M, NN, scale);
         if (g.N == 64) launch_probe_ifft_acc<64>(c, g_probe);
         else if (g.N == 128) launch_probe_ifft_acc<128>(c, g_probe);
         else {
@@ -729,7 +920,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     if (g_pos || g_tilt || g_dz)
         hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(256), 0, c->stream, at<float>(c, c->L.part),
                            g.N == 256 ? NBLK256 : 1, at<PosInfo>(c, c->L.pinfo), B, g.M, tilt, a.global_tilt, dz,
-                           g.lambda, g_pos, g_tilt, g_dz);
+                           g.lambda, scale, g_pos, g_tilt, g_dz);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
 
@@ -737,14 +928,6 @@ void zero(ptyr_ctx* c, float* p, size_t n) {
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(256), 0, c->stream, p, n);
 }
 
-void adam(ptyr_ctx* c, float* p, const float* g, float* m, float* v, size_t n, float lr, const ptyr_lr* h,
-          int64_t t) {
-    if (lr == 0.f || n == 0) return;
-    double bc1 = 1.0 - pow((double)h->beta1, (double)t);
-    double bc2 = 1.0 - pow((double)h->beta2, (double)t);
-    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, c->stream, p, g, m, v, n, lr, h->beta1, h->beta2,
-                       h->eps, (float)bc1, (float)sqrt(bc2));
-}
 
 }  // namespace
 
@@ -773,7 +956,7 @@ ptyr_status ptyr_loss(ptyr_ctx* c, const float* I_model, const float* I_meas, co
     if (st != PTYR_OK) return st;
     if (!I_model || !I_meas || !loss_dev) return PTYR_E_ARG;
     if (meas_idx && n_meas < 1) return PTYR_E_ARG;
-    return run_loss(c, I_model, I_meas, meas_idx, n_meas, B, loss_dev, dLdI, nullptr);
+    return run_loss(c, I_model, I_meas, meas_idx, n_meas, B, loss_dev, dLdI);
 }
 
 ptyr_status ptyr_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
@@ -816,23 +999,34 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
     float* gdz = at<float>(c, c->L.gdz);
     float* gpos = at<float>(c, c->L.gpos);
     float* gtilt = at<float>(c, c->L.gtilt);
-    zero(c, gamp, nobj);
-    zero(c, gphase, nobj);
-    zero(c, gprobe, nprb);
-    zero(c, gdz, 1);
-    zero(c, gpos, npos);
-    zero(c, gtilt, ntilt);
+    // the six gradient buffers are consecutive in the workspace: one clear
+    zero(c, gamp, (size_t)(reinterpret_cast<char*>(gtilt + ntilt) - reinterpret_cast<char*>(gamp)) / sizeof(float));
     st = run_adjoint(c, p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz, idx, p->n_pos, B, I_meas_all,
                      rates[0] > 0.f ? gamp : nullptr, rates[1] > 0.f ? gphase : nullptr,
                      rates[2] > 0.f ? gprobe : nullptr, gpos, gtilt, gdz, loss_dev, 0);
     if (st != PTYR_OK) return st;
     const int64_t t = p->step + 1;
-    adam(c, p->amp, gamp, p->m_amp, p->v_amp, nobj, rates[0], lr, t);
-    adam(c, p->phase, gphase, p->m_phase, p->v_phase, nobj, rates[1], lr, t);
-    adam(c, p->probe, gprobe, p->m_probe, p->v_probe, nprb, rates[2], lr, t);
-    adam(c, p->pos, gpos, p->m_pos, p->v_pos, npos, rates[3], lr, t);
-    adam(c, p->tilt, gtilt, p->m_tilt, p->v_tilt, ntilt, rates[4], lr, t);
-    adam(c, p->dz, gdz, p->m_dz, p->v_dz, 1, rates[5], lr, t);
+    {
+        AdamSegs A;
+        float* const params[6] = {p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz};
+        const float* const grads[6] = {gamp, gphase, gprobe, gpos, gtilt, gdz};
+        const size_t sizes[6] = {nobj, nobj, nprb, npos, ntilt, 1};
+        A.off[0] = 0;
+        for (int k = 0; k < 6; ++k) {
+            const bool on = rates[k] > 0.f;          // a zero rate leaves the parameter and its moments alone
+            A.p[k] = params[k];
+            A.g[k] = grads[k];
+            A.m[k] = mv[k][0];
+            A.v[k] = mv[k][1];
+            A.lr[k] = rates[k];
+            A.off[k + 1] = A.off[k] + (on ? sizes[k] : 0);
+        }
+        const double bc1 = 1.0 - pow((double)lr->beta1, (double)t);
+        const double bc2 = 1.0 - pow((double)lr->beta2, (double)t);
+        if (A.off[6] > 0)
+            hipLaunchKernelGGL(k_adam_segs, dim3(grid_for(A.off[6])), dim3(256), 0, c->stream, A, lr->beta1,
+                               lr->beta2, lr->eps, (float)bc1, (float)sqrt(bc2));
+    }
     p->step = t;
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
