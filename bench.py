@@ -37,6 +37,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3          # MI355X: 256 CU x 2.4 GHz x 128 FP32 FMA/clk x 2
 PEAK_FP32_UNPACKED_TFLOPS = 78.6         # the same without packed FP32 (disabled in this build)
+PEAK_HBM_GBS = 8000.0                    # MI355X HBM3E
 WORKLOAD = "multislice_128"
 
 
@@ -44,6 +45,22 @@ def fft_flops(N):
     """Nominal flops of one N x N complex 2-D FFT: 5 N^2 log2(N^2)."""
     import math
     return 5.0 * N * N * math.log2(N * N)
+
+
+def line_pass_bytes(w, B):
+    """Algorithmic HBM bytes per step of the N=256 line passes (one wave =
+    N*N complex64).  Forward, per chain: shifted probe (read the spectrum,
+    write the wave) 2 waves; per slice a row pass (read wave, keep phi, write
+    wave) and a column pass (read wave, keep Y, write wave) 6 waves, the last
+    column pass writing the far field and the mode intensity instead (2.5);
+    so 6S + 1.5 waves.  Gradient, per chain: 7S + 1.5 waves (the column pass
+    also reads Y, the row pass reads phi and writes the patch gradient).
+    Object patches are read once per batch row and slice."""
+    wave = w.N * w.N * 8
+    chains = B * w.M
+    patches = B * w.S * wave
+    return {"forward": chains * (6 * w.S + 1.5) * wave + patches,
+            "gradient": chains * (7 * w.S + 1.5) * wave + patches}
 
 
 def read_traffic(kernel, workload):
@@ -235,20 +252,34 @@ def main():
     # durations overstates the time each used and `achieved` is a lower bound.
     per_launch = {k: (v[0] / v[1] if v[1] else float("nan")) for k, v in kt.items()}
     dom = max(per_launch, key=lambda k: kt[k][0])
-    flops_step = B * w.M * 2 * w.S * fft_flops(w.N)     # nominal FFT flops of either fused kernel per step
     launches = kt[dom][1]
-    flops_launch = flops_step * args.steps / launches
-    achieved = flops_step * args.steps / (kt[dom][0] * 1e-3) / 1e12
-    roofline = {
-        "bound": "alu", "kernel": f"k_{dom}<{w.N}>" if w.N < 256 else f"{dom} line passes (N=256)", "achieved": round(achieved, 3),
-        "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-        "traffic": read_traffic(dom, workload),
-        "launch_ms": round(per_launch[dom], 4),
-        "launches_per_step": launches / args.steps,
-        "flops_per_launch": flops_launch,
-        "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
-        "other_kernel_ms": {k: round(v, 4) for k, v in per_launch.items() if k != dom},
-    }
+    if w.N < 256:
+        # wave-resident chains: bound by the FFT arithmetic
+        flops_step = B * w.M * 2 * w.S * fft_flops(w.N)     # nominal FFT flops of either fused kernel per step
+        achieved = flops_step * args.steps / (kt[dom][0] * 1e-3) / 1e12
+        roofline = {
+            "bound": "alu", "kernel": f"k_{dom}<{w.N}>", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+            "traffic": read_traffic(dom, workload),
+            "launch_ms": round(per_launch[dom], 4),
+            "launches_per_step": launches / args.steps,
+            "flops_per_launch": flops_step * args.steps / launches,
+            "peak_without_packed_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+            "other_kernel_ms": {k: round(v, 4) for k, v in per_launch.items() if k != dom},
+        }
+    else:
+        # line passes: every pass reads and writes the chain's wave through HBM
+        by = line_pass_bytes(w, B)[dom]
+        achieved = by * args.steps / (kt[dom][0] * 1e-3) / 1e9
+        roofline = {
+            "bound": "hbm", "kernel": f"{dom} line passes (N=256)", "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": read_traffic(dom, workload),
+            "launch_ms": round(per_launch[dom], 4),
+            "launches_per_step": launches / args.steps,
+            "bytes_per_launch": by * args.steps / launches,
+            "other_kernel_ms": {k: round(v, 4) for k, v in per_launch.items() if k != dom},
+        }
     desc = {
         "multislice_128": "multislice_128: probe 128x128 at 0.15 A/px, 6 modes, object 12 x 640 x 640, dz 20 A, "
                           "128x128 scan, 64 positions per Adam step (forward + loss + gradient of all six "

@@ -77,7 +77,7 @@ template <int N> struct Slots {
 // Per-workgroup LDS tables: twiddles and the separable propagator factors.
 template <int N> struct Tables {
     float4 tw[N];          // twiddles, b-major: tw[b*L + c] = exp(-2 pi i c b / N)
-    float4 hy[N], hx[N];   // propagator factors along y and x (unscaled)
+    float4 hy[N], hx[N];   // propagator factors along y (times 1/N^2) and x
     float2 ry[N], rx[N];   // shift ramp factors exp(-2 pi i q_n dr_y), exp(-2 pi i q_n dr_x)
 };
 
@@ -100,7 +100,10 @@ __device__ __forceinline__ void build_tables(Tables<N>& t, const WaveArgs& a, co
         sincos(ph, &s, &c);
         float4 w = unit_pair(c, s);
         if (which == 0) t.tw[n] = w;
-        else if (which == 1) t.hy[n] = w;
+        else if (which == 1) {   // the 1/N^2 of the two unnormalised transforms rides on h_y (exact: 2^-k)
+            const float sc = 1.0f / ((float)N * N);
+            t.hy[n] = make_float4(w.x * sc, w.y * sc, w.z * sc, w.w * sc);
+        }
         else if (which == 2) t.hx[n] = w;
         else if (which == 3) t.ry[n] = make_float2(w.x, w.y);
         else t.rx[n] = make_float2(w.x, w.y);
@@ -161,13 +164,14 @@ __device__ __forceinline__ void ifft2_to_col(float2 (&v)[16], float2* lds, const
     mid2nat<WaveGeo<N>, +1>(v, lds, tw, l, c);
 }
 
-// Multiply a (ROW, MID) spectrum by H (or conj(H)) and a scale.
+// Multiply a (ROW, MID) spectrum by H / N^2 (or conj(H) / N^2); the table h_y
+// carries the 1/N^2.
 template <int N, bool CONJ>
-__device__ __forceinline__ void apply_h(float2 (&v)[16], const Tables<N>& t, float scale, int l, int c) {
+__device__ __forceinline__ void apply_h(float2 (&v)[16], const Tables<N>& t, int l, int c) {
     const float4 hy = t.hy[l];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        v[r] = cscale(tmul<CONJ>(tmul<CONJ>(v[r], hy), t.hx[line_pos<N, MID>(c, r)]), scale);
+        v[r] = tmul<CONJ>(tmul<CONJ>(v[r], hy), t.hx[line_pos<N, MID>(c, r)]);
         if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -180,7 +184,7 @@ __device__ __forceinline__ void slice_step(float2 (&v)[16], const float2* Os, in
                                            float2* lds, const Tables<N>& t, int l, int c) {
     transmit<N>(v, Os, W, ty, tx, l, c);
     fft2_from_col<N>(v, lds, t.tw, l, c);
-    apply_h<N, false>(v, t, 1.0f / ((float)N * N), l, c);
+    apply_h<N, false>(v, t, l, c);
     if (spec) wstore<N, ROW, MID>(v, spec, N, l, c);
     ifft2_to_col<N>(v, lds, t.tw, l, c);
 }
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], ov[r]);
         fft2_from_col<N>(v, lds, tab.tw, l, c);
-        apply_h<N, false>(v, tab, 1.0f / ((float)N * N), l, c);
+        apply_h<N, false>(v, tab, l, c);
         if (full) wstore<N, ROW, MID>(v, sl.spec(s + 1), N, l, c);
         ifft2_to_col<N>(v, lds, tab.tw, l, c);
     }
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
             acc_ky = fmaf(e, ky, acc_ky);
             if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
-        apply_h<N, true>(g, tab, inv_n2, l, c);                               // conj(H) G^ / N^2
+        apply_h<N, true>(g, tab, l, c);                                       // conj(H) G^ / N^2
         ifft2_to_col<N>(g, lds, tab.tw, l, c);                                // G_chi_{s-1}
     }
     slice_back(0);

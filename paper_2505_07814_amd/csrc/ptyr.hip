@@ -257,8 +257,9 @@ __global__ __launch_bounds__(256) void k_loss_rows(const float* Imode, float* I,
 // in batch order, the patch gradients of every (position, mode) covering it;
 // then applies the chain rule to amplitude and phase (O = a exp(i phase)):
 //   g_a += Re(conj(G) exp(i phase)),  g_phase += Im(G conj(O)).
-// A thread owns 4 consecutive pixels of a tile row; the loads of up to
-// MB modes of one position are issued together before they are added (in
+// A thread owns one column of the tile and four rows 8 apart, so each load
+// instruction reads two whole 256-byte tile rows of a patch; the loads of up
+// to MB modes of one position are issued together before they are added (in
 // mode order), to keep enough bytes in flight per workgroup.
 constexpr int SCATTER_MB = 8;
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int B, int M, int S,
@@ -267,10 +268,10 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
     const int ntx = (W + 31) / 32;
     const int tile = blockIdx.x, s = blockIdx.y;
     const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
-    const int ly = threadIdx.x / 8, lx = (threadIdx.x % 8) * 4;
-    const int y = y0 + ly, xb = x0 + lx;
+    const int x = x0 + (int)threadIdx.x % 32, yb = y0 + (int)threadIdx.x / 32;
     float2 acc[4];
-    for (int k = 0; k < 4; ++k) acc[k] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = make_float2(0.f, 0.f);
     bool touched = false;
     const size_t NN = (size_t)N * N;
     for (int j = 0; j < B; ++j) {
@@ -278,39 +279,38 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
         if (pi.ty < 0) continue;
         if (pi.ty >= y0 + 32 || pi.ty + N <= y0 || pi.tx >= x0 + 32 || pi.tx + N <= x0) continue;
         touched = true;
-        const int py = y - pi.ty, px0 = xb - pi.tx;
-        if (py < 0 || py >= N) continue;
-        const bool all4 = px0 >= 0 && px0 + 3 < N;
+        const int px = x - pi.tx;
+        const bool xin = px >= 0 && px < N;
         for (int m0 = 0; m0 < M; m0 += SCATTER_MB) {
             float2 buf[SCATTER_MB][4];
 #pragma unroll
             for (int mm = 0; mm < SCATTER_MB; ++mm) {
                 const int m = m0 + mm;
-                const float2* src = gO + ((size_t)(j * M + m) * S + s) * NN + (size_t)py * N;
+                const float2* src = gO + ((size_t)(j * M + m) * S + s) * NN + px;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int px = px0 + k;
-                    const bool in = m < M && (all4 || (px >= 0 && px < N));
-                    buf[mm][k] = in ? src[px] : make_float2(0.f, 0.f);
+                for (int i = 0; i < 4; ++i) {
+                    const int py = yb + 8 * i - pi.ty;
+                    const bool in = m < M && xin && py >= 0 && py < N;
+                    buf[mm][i] = in ? src[(size_t)py * N] : make_float2(0.f, 0.f);
                 }
             }
 #pragma unroll
             for (int mm = 0; mm < SCATTER_MB; ++mm)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k] = cadd(acc[k], buf[mm][k]);
+                for (int i = 0; i < 4; ++i) acc[i] = cadd(acc[i], buf[mm][i]);
         }
     }
-    if (!touched || y >= H) return;
+    if (!touched || x >= W) return;
     const float sc = (float)*scale;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int x = xb + k;
-        if (x >= W) continue;
+    for (int i = 0; i < 4; ++i) {
+        const int y = yb + 8 * i;
+        if (y >= H) continue;
         size_t o = ((size_t)s * H + y) * W + x;
         float sn, cs;
         sincosf(phase[o], &sn, &cs);
         float a = amp[o];
-        float2 G = cscale(acc[k], sc);
+        float2 G = cscale(acc[i], sc);
         if (g_amp) g_amp[o] += G.x * cs + G.y * sn;          // Re(conj(G) e^{i phi})
         if (g_phase) g_phase[o] += a * (G.y * cs - G.x * sn); // Im(G conj(a e^{i phi}))
     }
@@ -323,7 +323,15 @@ __global__ void k_sum_rows(const float2* src, float2* dst, int B, int M, int NN,
     const float sc = (float)*scale;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         float2 s = make_float2(0.f, 0.f);
-        for (int j = 0; j < B; ++j) s = cadd(s, src[(size_t)j * n + e]);
+        int j = 0;
+        for (; j + 8 <= B; j += 8) {         // eight loads in flight, added in row order
+            float2 t[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t[q] = src[(size_t)(j + q) * n + e];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s = cadd(s, t[q]);
+        }
+        for (; j < B; ++j) s = cadd(s, src[(size_t)j * n + e]);
         dst[e] = cscale(s, sc);
     }
 }

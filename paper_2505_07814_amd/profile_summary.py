@@ -6,7 +6,12 @@ measured in the same run, and written with the hash of the kernel sources
 so that bench.py can tell whether they still describe the current kernels.
 
 usage: python -m paper_2505_07814_amd.profile_summary FETCH_CSV WRITE_CSV
-           KERNEL_SUBSTRING OUT_TXT COMMAND...
+           KERNELS OUT_TXT [--launches K] COMMAND...
+
+KERNELS is a comma-separated list of kernel-name substrings.  Without
+--launches the figure is the average per matching dispatch; with it, the
+total over all matching dispatches divided by K (for a timed unit made of
+several dispatches, such as the N=256 line passes of one gradient).
 """
 import csv
 import hashlib
@@ -40,8 +45,15 @@ def per_kernel(path, counter):
 
 
 def main(argv):
-    fetch_csv, write_csv, kname, out_txt = argv[:4]
-    cmd = " ".join(argv[4:])
+    fetch_csv, write_csv, knames, out_txt = argv[:4]
+    rest = argv[4:]
+    launches = None
+    if rest and rest[0] == "--launches":
+        launches = int(rest[1])
+        rest = rest[2:]
+    cmd = " ".join(rest)
+    keys = [k for k in knames.split(",") if k]
+    kname = knames
     fetch = per_kernel(fetch_csv, "FETCH_SIZE")
     write = per_kernel(write_csv, "WRITE_SIZE")
     copy_f = [v for k, v in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower()]
@@ -51,15 +63,15 @@ def main(argv):
     known = 512.0 * 1024                                  # KiB read and written by one copy
     kf = known / big_f if big_f else float("nan")
     kw = known / big_w if big_w else float("nan")
-    kf_vals = [v for k, vals in fetch.items() if kname in k for v in vals]
-    kw_vals = [v for k, vals in write.items() if kname in k for v in vals]
-    af = sum(kf_vals) / len(kf_vals)
-    aw = sum(kw_vals) / len(kw_vals)
+    kf_vals = [v for k, vals in fetch.items() if any(q in k for q in keys) for v in vals]
+    kw_vals = [v for k, vals in write.items() if any(q in k for q in keys) for v in vals]
+    af = sum(kf_vals) / (launches or len(kf_vals))
+    aw = sum(kw_vals) / (launches or len(kw_vals))
     hbm = (af * kf + aw * kw) * 1024
     lines = [
         f"# HBM traffic of {kname} (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)",
         f"# command: {cmd}",
-        f"# dispatches: fetch {len(kf_vals)}, write {len(kw_vals)}",
+        f"# dispatches: fetch {len(kf_vals)}, write {len(kw_vals)}" + (f", per timed launch of {len(kf_vals) // launches}" if launches else ""),
         f"# copy calibration (512 MiB device copy): FETCH_SIZE {big_f:.0f} KiB, WRITE_SIZE {big_w:.0f} KiB",
         f"fetch_kib_per_launch = {af:.1f}",
         f"write_kib_per_launch = {aw:.1f}",
