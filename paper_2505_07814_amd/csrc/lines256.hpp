@@ -118,8 +118,13 @@ __global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
     const int l = threadIdx.x / 16, c = threadIdx.x % 16, y = blk * LINES256 + l;
     build256<1>(tab, a, pi, blk * LINES256);
     float2* w = P.wave + (size_t)ch * N256 * N256;
-    float2 v[16];
+    float2 v[16], ov[16];
     rows_load(v, w, y, c);
+    // the object patch is read now, so that its latency overlaps the line DFT
+    // (three workgroups per CU by LDS leave room for the extra registers)
+    const float2* Os = a.Oc + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ov[r] = Os[c + 16 * r];
     if (P.s == 0) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], tab.r[c + 16 * r]);
@@ -128,9 +133,8 @@ __global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
     const Slots<N256> sl(a, ch);
     if (sl.base && a.keep == KEEP_FULL) rows_store(v, sl.phi(P.s), y, c);
     else if (sl.base && a.ckK <= a.S && P.s % a.ckK == 0) rows_store(v, sl.ckpt(P.s / a.ckK), y, c);
-    const float2* Os = a.Oc + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], Os[c + 16 * r]);
+    for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], ov[r]);
     nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
     rows_store(v, w, y, c);
 }
@@ -224,17 +228,18 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
         return;
     }
     cols_load(v, w, x, c);
+    float2 yv_[16];                      // Y'_s, read now so that its latency overlaps the DFT
+    if (P.s > 0) cols_load(yv_, sl.spec(P.s), x, c);
     nat2mid<ColGeo256, -1>(v, lds, tab.tw, l, c);                       // G^ (raw), (k_y, k_x)
     const float dk = (float)(1.0 / (N256 * a.dx));
     const float kx = sfreq<N256>(x) * dk;
     float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     if (P.s > 0) {
-        const float2* Y = sl.spec(P.s);
         const float4 hx = tab.hl[l];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int ky_i = c + 16 * r;
-            const float2 yv = Y[ky_i * N256 + x];
+            const float2 yv = yv_[r];
             const float e = v[r].y * yv.x - v[r].x * yv.y;               // Im(G^ conj(Y))
             const float ky = sfreq<N256>(ky_i) * dk;
             acc[0] = fmaf(e, kx * kx + ky * ky, acc[0]);
@@ -280,17 +285,21 @@ __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
     build256<1>(tab, a, pi, blk * LINES256);
     const Slots<N256> sl(a, ch);
     float2* w = P.wave + (size_t)ch * N256 * N256;
-    float2 v[16];
+    float2 v[16], ph[16], ov[16];
     rows_load(v, w, y, c);
-    mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                      // G_chi_s (space)
-    const float2* phi = sl.phi(P.s) + y * N256;
-    float2* go = a.gO + (((size_t)ch * a.S + P.s) * N256 + y) * N256;
+    // phi_s and the object patch are read now, so that their latency
+    // overlaps the line DFT
+    rows_load(ph, sl.phi(P.s), y, c);
     const float2* Os = a.Oc + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ov[r] = Os[c + 16 * r];
+    mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                      // G_chi_s (space)
+    float2* go = a.gO + (((size_t)ch * a.S + P.s) * N256 + y) * N256;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int xx = c + 16 * r;
-        go[xx] = cmulc(v[r], phi[xx]);                                    // conj(phi) G_chi
-        v[r] = cmulc(v[r], Os[xx]);                                       // conj(O) G_chi
+        go[xx] = cmulc(v[r], ph[r]);                                      // conj(phi) G_chi
+        v[r] = cmulc(v[r], ov[r]);                                        // conj(O) G_chi
     }
     nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
     rows_store(v, w, y, c);

@@ -169,6 +169,29 @@ def test_gradient_parity_multislice_128():
     _check_grads(c, c.engine())
 
 
+def test_gradient_parity_multislice_128_full_batch():
+    """The benchmark batch (64 rows x 6 modes = 384 chains, more than the 256
+    compute units): the step runs as two chain ranges on two streams, with the
+    loss batch factor applied at the reductions."""
+    print("gradient multislice_128 B=64 (two chain ranges)", flush=True)
+    c = Case(synth.workload("multislice_128", scan=64))
+    _check_grads(c, c.engine())
+
+
+def test_gradient_parity_uneven_chain_split():
+    """270 chains: a first range of 256, then 14 more chains of which the
+    first 4 belong to the last row of the first range's forward."""
+    print("gradient N=64 S=3 M=3 B=90 (uneven split)", flush=True)
+    w = synth.small_case(N=64, S=3, M=3, B=90, H=64 + 60, W=64 + 70, seed=31)
+    c = Case(w)
+    g1 = _check_grads(c, c.engine())
+    eng = c.engine()
+    g2 = eng.adjoint(*c.gpu_args(), T(c.meas))[1]
+    eng.sync()
+    for k in g1:
+        assert torch.equal(g1[k], g2[k]), k        # the two-stream schedule is deterministic
+
+
 def test_recompute_equals_stored_waves():
     print("recompute vs store", flush=True)
     c = Case(synth.workload("diffcheck_64"))
