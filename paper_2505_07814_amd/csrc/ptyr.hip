@@ -254,7 +254,8 @@ __global__ __launch_bounds__(256) void k_loss_rows(const float* Imode, float* I,
 }
 
 // Object gradient: each workgroup owns a 32 x 32 tile of one slice and sums,
-// in batch order, the patch gradients of every (position, mode) covering it;
+// in batch order, the patch gradients of every (position, mode) of batch rows
+// [j0, j1) covering it;
 // then applies the chain rule to amplitude and phase (O = a exp(i phase)):
 //   g_a += Re(conj(G) exp(i phase)),  g_phase += Im(G conj(O)).
 // A thread owns one column of the tile and four rows 8 apart, so each load
@@ -262,9 +263,10 @@ __global__ __launch_bounds__(256) void k_loss_rows(const float* Imode, float* I,
 // to MB modes of one position are issued together before they are added (in
 // mode order), to keep enough bytes in flight per workgroup.
 constexpr int SCATTER_MB = 8;
-__global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int B, int M, int S,
-                                                        int N, int H, int W, const float* amp, const float* phase,
-                                                        const double* scale, float* g_amp, float* g_phase) {
+__global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int j0, int j1, int M,
+                                                        int S, int N, int H, int W, const float* amp,
+                                                        const float* phase, const double* scale, float* g_amp,
+                                                        float* g_phase) {
     const int ntx = (W + 31) / 32;
     const int tile = blockIdx.x, s = blockIdx.y;
     const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
     for (int i = 0; i < 4; ++i) acc[i] = make_float2(0.f, 0.f);
     bool touched = false;
     const size_t NN = (size_t)N * N;
-    for (int j = 0; j < B; ++j) {
+    for (int j = j0; j < j1; ++j) {
         const PosInfo pi = pinfo[j];
         if (pi.ty < 0) continue;
         if (pi.ty >= y0 + 32 || pi.ty + N <= y0 || pi.tx >= x0 + 32 || pi.tx + N <= x0) continue;
@@ -493,7 +495,7 @@ struct ptyr_ctx {
     // second stream for the other row range of a split batch, with the
     // fork / join events that order it against `stream` (default priority)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_loss = nullptr, ev_join = nullptr;
     int n_cu = 0;
     Layout L;
     int fwd_valid;   // waves / intensities of the last forward are in the workspace
@@ -611,6 +613,7 @@ ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, vo
         hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_loss, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         ptyr_destroy(c);
         return PTYR_E_DEVICE;
@@ -627,6 +630,7 @@ void ptyr_destroy(ptyr_ctx* ctx) {
     for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
     if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_mid) hipEventDestroy(ctx->ev_mid);
+    if (ctx->ev_loss) hipEventDestroy(ctx->ev_loss);
     if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
     if (ctx->side) hipStreamDestroy(ctx->side);
     delete ctx;
@@ -766,8 +770,8 @@ template <int N> void launch_probe_fft(ptyr_ctx* c, const float* probe) {
     hipLaunchKernelGGL((k_fft2<N, -1, false>), dim3(c->g.M), dim3(N * N / 16), 0, c->stream,
                        reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat));
 }
-template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe) {
-    hipLaunchKernelGGL((k_fft2<N, +1, true>), dim3(c->g.M), dim3(N * N / 16), 0, c->stream,
+template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe, hipStream_t st) {
+    hipLaunchKernelGGL((k_fft2<N, +1, true>), dim3(c->g.M), dim3(N * N / 16), 0, st,
                        at<float2>(c, c->L.gPsum), reinterpret_cast<float2*>(g_probe));
 }
 
@@ -874,6 +878,16 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     const bool reuse = (flags & PTYR_REUSE_FORWARD) && c->fwd_valid && c->fwd_B == B;
     if (!reuse) prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
     const WaveArgs a = wave_args(c, tilt, dz, B);
+    const double* scale = at<double>(c, c->L.scal) + 1;     // the batch factor of w (after loss_final)
+    // object-gradient scatter of batch rows [j0, j1) on the main stream
+    auto scatter = [&](int j0, int j1) {
+        if (!(g_amp || g_phase)) return;
+        const int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
+        hipLaunchKernelGGL(k_scatter_object, dim3(ntiles, g.S), dim3(256), 0, c->stream, at<float2>(c, c->L.gO),
+                           at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W, amp, phase, scale, g_amp,
+                           g_phase);
+    };
+    int scattered = 0;                                       // rows already scattered
     const int nA = reuse ? 0 : split_chains(c, B);
     if (nA) {
         const int rA = nA / M;                                     // rows complete after the first forward
@@ -892,7 +906,18 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
             return PTYR_E_DEVICE;
         if (g1 > 0) gradient_chains(c, a, 0, g1, c->stream);
         loss_rows(c, I_meas, idx, nm, rA, B - rA, 1, c->side);
+        if (hipEventRecord(c->ev_loss, c->side) != hipSuccess) return PTYR_E_DEVICE;
         gradient_chains(c, a, g1, BM - g1, c->side);
+        // rows whose chains all ran in the first gradient launch are scattered
+        // while the side stream's gradient still runs (its last round leaves
+        // compute units free); the batch factor needs both loss ranges
+        const int r1 = g1 / M;
+        if (r1 > 0) {
+            if (hipStreamWaitEvent(c->stream, c->ev_loss, 0) != hipSuccess) return PTYR_E_DEVICE;
+            loss_final(c, 2, B, loss_dev);
+            scatter(0, r1);
+            scattered = r1;
+        }
         if (hipEventRecord(c->ev_join, c->side) != hipSuccess ||
             hipStreamWaitEvent(c->stream, c->ev_join, 0) != hipSuccess)
             return PTYR_E_DEVICE;
@@ -903,20 +928,14 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     }
     c->fwd_valid = 1;
     c->fwd_B = B;
-    loss_final(c, nA ? 2 : 1, B, loss_dev);
-    const double* scale = at<double>(c, c->L.scal) + 1;     // the batch factor of w
-    if (g_amp || g_phase) {
-        int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
-        hipLaunchKernelGGL(k_scatter_object, dim3(ntiles, g.S), dim3(256), 0, c->stream, at<float2>(c, c->L.gO),
-                           at<PosInfo>(c, c->L.pinfo), B, g.M, g.S, g.N, g.H, g.W, amp, phase, scale, g_amp,
-                           g_phase);
-    }
+    if (!scattered) loss_final(c, nA ? 2 : 1, B, loss_dev);
+    scatter(scattered, B);
     if (g_probe) {
         int NN = g.N * g.N;
         hipLaunchKernelGGL(k_sum_rows, dim3(grid_for((size_t)g.M * NN)), dim3(256), 0, c->stream,
                            at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B, g.M, NN, scale);
-        if (g.N == 64) launch_probe_ifft_acc<64>(c, g_probe);
-        else if (g.N == 128) launch_probe_ifft_acc<128>(c, g_probe);
+        if (g.N == 64) launch_probe_ifft_acc<64>(c, g_probe, c->stream);
+        else if (g.N == 128) launch_probe_ifft_acc<128>(c, g_probe, c->stream);
         else {
             const dim3 grid(g.M * NBLK256), blk(256);
             hipLaunchKernelGGL((k256_fft<+1, true, false>), grid, blk, 0, c->stream, at<float2>(c, c->L.gPsum),
