@@ -162,6 +162,58 @@ def learned_init_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def sweep_bench(args):
+    """Throughput of the full step around the N=128 point, one axis at a
+    time: batch B, probe modes M (the first M of the six), slices S (the
+    first S of the twelve, or the twelve twice for 24).  Timing only: the
+    measured patterns are those of the 12-slice, 6-mode object for every
+    shape."""
+    import numpy as np
+    import torch
+
+    from paper_2505_07814_amd import synth
+    from paper_2505_07814_amd.ptyr import AdamState, Engine
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.workload("multislice_128", scan=8192)
+    lam = synth.wavelength_A(w.kv)
+    n_pos = w.pos.shape[0]
+    T = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a if dt is None else a.astype(dt))).to(dev)
+    meas = torch.poisson(torch.full((n_pos, w.N, w.N), 60.0, device=dev))
+    amp0, ph0 = synth.plain_init(w.S, w.H, w.W, w.seed_base + 5)
+    lr = dict(amp=5e-4, phase=5e-4, probe=1e-4, pos=1e-3, tilt=1e-5, dz=1e-2)
+    points = [(64, 6, 12)] + [(b, 6, 12) for b in (16, 32, 128, 256)] + [(64, m, 12) for m in (1, 3)] + \
+             [(64, 6, s) for s in (1, 6, 24)]
+    rows = []
+    for B, M, S in points:
+        reps = (S + 11) // 12
+        amp = np.concatenate([amp0] * reps)[:S]
+        ph = np.concatenate([ph0] * reps)[:S]
+        eng = Engine(w.N, M, S, w.H, w.W, B, w.dx, lam, n_scan=n_pos, device=dev)
+        st = AdamState(T(amp, np.float32), T(ph, np.float32), T(w.probe[:M], np.complex64), T(w.pos, np.float32),
+                       T(np.zeros_like(w.pos), np.float32), T(np.array([w.dz], np.float32)))
+        perm = np.random.default_rng(7).permutation(n_pos)
+        batches = [torch.tensor(perm[i * B:(i + 1) * B], dtype=torch.int32, device=dev) for i in range(n_pos // B)]
+        steps = max(8, min(64, 4096 // B))
+        for i in range(4):
+            eng.step(st, batches[i % len(batches)], meas, lr)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(steps):
+            eng.step(st, batches[(4 + i) % len(batches)], meas, lr)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        rows.append({"B": B, "M": M, "S": S, "ms_per_step": round(ms, 4), "patterns_per_s": round(B / ms * 1e3, 1),
+                     "chain_slices_per_s": round(B * M * S / ms * 1e3, 1)})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        del eng, st
+    print(json.dumps({"metric": "fwd+adjoint patterns/s sweep around N=128, 12 slices, 6 modes, B=64",
+                      "unit": "patterns/s", "n_gpus": 1, "data": "synthetic (timing only)", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +225,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--positions", type=int, default=0,
                     help="use only the first P scan positions (profiling runs; 0 = all)")
+    ap.add_argument("--sweep", action="store_true", help="time the step over B, M and S around the N=128 point")
     ap.add_argument("--learned-init", action="store_true",
                     help="measure wall time to 0.02 rad RMS phase error, learned vs plain initial guess")
     ap.add_argument("--objects", type=int, default=3125, help="training objects for --learned-init (64 pairs each)")
@@ -187,6 +240,8 @@ def main():
         sys.exit(2)
     if args.learned_init:
         return learned_init_bench(args)
+    if args.sweep:
+        return sweep_bench(args)
 
     import numpy as np
     import torch
