@@ -355,12 +355,23 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
         }
         const float2* Os = a.Oc + (size_t)s * HW + (size_t)pi.ty * a.W + pi.tx;
         float2* go = a.gO + ((size_t)(j * a.M + m) * a.S + s) * N * N;
+        // The reads of each half are issued before its writes: the
+        // patch-gradient writes could alias the reads as far as the compiler
+        // knows, so interleaved they would serialise every read behind a full
+        // wait; two halves keep the registers in flight at 32.
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float2 ph = (phi_s + YC::dy(r) * N)[oN];
-            (go + YC::dy(r) * N)[oN] = cmulc(g[r], ph);                       // conj(phi) G_chi
-            g[r] = cmulc(g[r], (Os + YC::dy(r) * a.W)[oW]);                    // G_phi = conj(O) G_chi
-            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        for (int h = 0; h < 16; h += 8) {
+            float2 ph[8], ov[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                ph[r] = (phi_s + YC::dy(h + r) * N)[oN];
+                ov[r] = (Os + YC::dy(h + r) * a.W)[oW];
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                (go + YC::dy(h + r) * N)[oN] = cmulc(g[h + r], ph[r]);        // conj(phi) G_chi
+                g[h + r] = cmulc(g[h + r], ov[r]);                             // G_phi = conj(O) G_chi
+            }
         }
         fft2_from_col<N>(g, lds, tab.tw, l, c);                               // G^ = F_raw G_phi
         return Y_s;
@@ -372,15 +383,25 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     for (int s = a.S - 1; s >= 1; --s) {
         const float2* Y_s = slice_back(s);
         // dL/d(dz, th) += sum_k dPhi/dt(k) Im(G^ conj(Y)), Y = F phi_s (raw G^ x Y')
+        // Y is read in two batches of eight; the per-register k_x are
+        // recomputed each slice (the opaque copy of the lane index keeps the
+        // compiler from hoisting all sixteen out of the loop into spills)
+        int cc = c;
+        asm volatile("" : "+v"(cc));
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float2 y = (Y_s + YR::dx(r))[oM];
-            const float e = g[r].y * y.x - g[r].x * y.y;
-            const float kx = sfreq<N>(line_pos<N, MID>(c, r)) * dk;
-            acc_k2 = fmaf(e, kx * kx + ky * ky, acc_k2);
-            acc_kx = fmaf(e, kx, acc_kx);
-            acc_ky = fmaf(e, ky, acc_ky);
-            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        for (int h = 0; h < 16; h += 8) {
+            float2 yv[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) yv[r] = (Y_s + YR::dx(h + r))[oM];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const float2 y = yv[r];
+                const float e = g[h + r].y * y.x - g[h + r].x * y.y;
+                const float kx = sfreq<N>(line_pos<N, MID>(cc, h + r)) * dk;
+                acc_k2 = fmaf(e, kx * kx + ky * ky, acc_k2);
+                acc_kx = fmaf(e, kx, acc_kx);
+                acc_ky = fmaf(e, ky, acc_ky);
+            }
         }
         apply_h<N, true>(g, tab, l, c);                                       // conj(H) G^ / N^2
         ifft2_to_col<N>(g, lds, tab.tw, l, c);                                // G_chi_{s-1}
