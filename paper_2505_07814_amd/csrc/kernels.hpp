@@ -212,8 +212,11 @@ __device__ __forceinline__ void block_sum(float (&x)[NV], float* red) {
 }
 
 // ------------------------------------------------------------------ kernels
-// Forward: one workgroup per (batch row j, probe mode m).
-template <int N>
+// Forward: one workgroup per (batch row j, probe mode m).  KEEP (the wave
+// store plan) is a template parameter so that the hot loop has no
+// data-dependent branch around its writes: at such a merge the compiler's
+// wait for the object-patch reads would also wait for the writes.
+template <int N, int KEEP>
 __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     constexpr int L = N / 16;
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
@@ -230,8 +233,8 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     const float* th = a.global_tilt ? a.tilt : a.tilt + 2 * pi.row;
     build_tables<N>(tab, a, pi, th[0], th[1], *a.dz);
     const Slots<N> sl(a, j * a.M + m);
-    const bool full = sl.base && a.keep == KEEP_FULL;
-    const bool ckpt = sl.base && a.keep == KEEP_CKPT && a.ckK <= a.S;
+    constexpr bool full = KEEP == KEEP_FULL;            // the store is always in the workspace
+    const bool ckpt = KEEP == KEEP_CKPT && a.ckK <= a.S;
     const size_t HW = (size_t)a.H * a.W;
 
     float2 v[16];
@@ -242,10 +245,14 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
         // counter covers both)
         float2 ov[16];
         load_patch<N>(ov, a.Oc + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
+        // chi_s is formed before phi_s is written: waiting for the patch then
+        // cannot wait for those (conditional) writes as well
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ov[r] = cmul(v[r], ov[r]);
         if (full) wstore<N, COL, NAT>(v, sl.phi(s), N, l, c);
         else if (ckpt && s % a.ckK == 0) wstore<N, COL, NAT>(v, sl.ckpt(s / a.ckK), N, l, c);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], ov[r]);
+        for (int r = 0; r < 16; ++r) v[r] = ov[r];
         fft2_from_col<N>(v, lds, tab.tw, l, c);
         apply_h<N, false>(v, tab, l, c);
         if (full) wstore<N, ROW, MID>(v, sl.spec(s + 1), N, l, c);

@@ -717,7 +717,10 @@ WaveArgs wave_args(ptyr_ctx* c, const float* tilt, const float* dz, int B) {
 template <int N> void launch_forward(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
     TimedLaunch t(c, PTYR_K_FORWARD, st);
     a.chain0 = c0;
-    hipLaunchKernelGGL(k_forward<N>, dim3(nc), dim3(N * N / 16), 0, st, a);
+    if (a.keep == KEEP_FULL)
+        hipLaunchKernelGGL((k_forward<N, KEEP_FULL>), dim3(nc), dim3(N * N / 16), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_forward<N, KEEP_CKPT>), dim3(nc), dim3(N * N / 16), 0, st, a);
 }
 template <int N> void launch_gradient(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
     TimedLaunch t(c, PTYR_K_GRADIENT, st);
