@@ -133,11 +133,17 @@ size_t ptyr_workspace_bytes(const ptyr_geom* g);
  * gradient recomputes from the probe (O(S^2) slice steps). */
 ptyr_status ptyr_checkpoint_plan(const ptyr_geom* g, int* stride);
 
-/* Bind a context to a workspace (device, caller-owned, >= ptyr_workspace_bytes)
- * and a stream (hipStream_t as void*; NULL = the default stream).  The
- * context stores pointers only. */
+/* Bind a context to a workspace (device, caller-owned, >= ptyr_workspace_bytes,
+ * 256-byte aligned) and a stream (hipStream_t as void*; NULL = the default
+ * stream), on the current device.  Besides pointers the context owns one
+ * extra stream of default priority and four events: a batch with more
+ * (row, mode) chains than the device has compute units runs part of its
+ * chains on that stream, joined back to the caller's stream before
+ * ptyr_adjoint / ptyr_step return, so callers only ever order work against
+ * their own stream.  PTYR_E_DEVICE if the stream or events cannot be made. */
 ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes,
                         void* stream, ptyr_ctx** out);
+/* Release the context, its stream and events (waits for the stream's work). */
 void ptyr_destroy(ptyr_ctx* ctx);
 
 /* Wait for the context's stream and report the first asynchronous error:

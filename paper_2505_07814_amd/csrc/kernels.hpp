@@ -390,25 +390,22 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     for (int s = a.S - 1; s >= 1; --s) {
         const float2* Y_s = slice_back(s);
         // dL/d(dz, th) += sum_k dPhi/dt(k) Im(G^ conj(Y)), Y = F phi_s (raw G^ x Y')
-        // Y is read in two batches of eight; the per-register k_x are
-        // recomputed each slice (the opaque copy of the lane index keeps the
-        // compiler from hoisting all sixteen out of the loop into spills)
+        // Y is read in one batch; the per-register k_x are recomputed each
+        // slice (the opaque copy of the lane index keeps the compiler from
+        // hoisting all sixteen out of the loop into spills)
         int cc = c;
         asm volatile("" : "+v"(cc));
+        float2 yv[16];
 #pragma unroll
-        for (int h = 0; h < 16; h += 8) {
-            float2 yv[8];
+        for (int r = 0; r < 16; ++r) yv[r] = (Y_s + YR::dx(r))[oM];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) yv[r] = (Y_s + YR::dx(h + r))[oM];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const float2 y = yv[r];
-                const float e = g[h + r].y * y.x - g[h + r].x * y.y;
-                const float kx = sfreq<N>(line_pos<N, MID>(cc, h + r)) * dk;
-                acc_k2 = fmaf(e, kx * kx + ky * ky, acc_k2);
-                acc_kx = fmaf(e, kx, acc_kx);
-                acc_ky = fmaf(e, ky, acc_ky);
-            }
+        for (int r = 0; r < 16; ++r) {
+            const float2 y = yv[r];
+            const float e = g[r].y * y.x - g[r].x * y.y;
+            const float kx = sfreq<N>(line_pos<N, MID>(cc, r)) * dk;
+            acc_k2 = fmaf(e, kx * kx + ky * ky, acc_k2);
+            acc_kx = fmaf(e, kx, acc_kx);
+            acc_ky = fmaf(e, ky, acc_ky);
         }
         apply_h<N, true>(g, tab, l, c);                                       // conj(H) G^ / N^2
         ifft2_to_col<N>(g, lds, tab.tw, l, c);                                // G_chi_{s-1}

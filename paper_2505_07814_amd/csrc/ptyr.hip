@@ -102,17 +102,15 @@ __device__ __forceinline__ double powm1(double v, double p) {
 }
 
 // pass 1 of the loss: per-block sums of E = I_meas^p and of the residual term
-// Rows [row0, row0 + B) of a batch: Im, midx (when given) and part start at
-// that range's entries; without midx, row j of the range reads measured
-// pattern row0 + j.
+// (ptyr_loss; inside the step k_loss_rows does this per row range)
 __global__ void k_loss_partial(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int NN,
-                               int kind, double p, int row0, double* part, int* err) {
+                               int kind, double p, double* part, int* err) {
     __shared__ double sh[3 * 256];
     double sE = 0.0, sR = 0.0, bad = 0.0;
     size_t n = (size_t)B * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         size_t j = e / NN, q = e % NN;
-        long row = midx ? (long)midx[j] : (long)(row0 + j);
+        long row = midx ? (long)midx[j] : (long)j;
         if (row < 0 || row >= n_meas) {
             if (q == 0) atomicOr(err, ERR_INDEX);
             continue;
@@ -172,23 +170,17 @@ __global__ void k_loss_final(const double* part, int nblk, double K, int kind, i
     }
 }
 
-// dL/dI per value (layout of I_model) and w = 2 dL/dI for the gradient kernel
-// (zero frequency at (0, 0)).  With unscaled set, both omit the batch factor
-// c = scal[1] (which needs the whole batch's residual): the gradient kernels
-// are linear in w, and the kernels that reduce their outputs apply c.  Row
-// offsets as in k_loss_partial.
+// dL/dI per value, in the layout of I_model (ptyr_loss)
 __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int N,
-                            int kind, double p, int row0, const double* scal, int unscaled, float* dLdI, float* w2) {
+                            int kind, double p, const double* scal, float* dLdI) {
     const int NN = N * N;
-    const double c = unscaled ? 1.0 : scal[1];
+    const double c = scal[1];
     size_t n = (size_t)B * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         size_t j = e / NN, q = e % NN;
-        long row = midx ? (long)midx[j] : (long)(row0 + j);
-        const size_t e2 = j * NN + shift_index((int)q, N);
+        long row = midx ? (long)midx[j] : (long)j;
         if (row < 0 || row >= n_meas) {
-            if (dLdI) dLdI[e] = 0.f;
-            if (w2) w2[e2] = 0.f;
+            dLdI[e] = 0.f;
             continue;
         }
         double I = fmax((double)Im[e], 0.0), Em = fmax((double)Ie[(size_t)row * NN + q], 0.0);
@@ -197,8 +189,7 @@ __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, i
         double dI;
         if (p == 1.0) dI = dA;
         else dI = I > 0.0 ? dA * p * powm1(I, p) : 0.0;
-        if (dLdI) dLdI[e] = (float)dI;
-        if (w2) w2[e2] = (float)(2.0 * dI);
+        dLdI[e] = (float)dI;
     }
 }
 
@@ -846,11 +837,11 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
     const size_t n = (size_t)B * NN;
     const int nm = midx ? n_meas : B;
     hipLaunchKernelGGL(k_loss_partial, dim3(NPART), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, g.loss_kind,
-                       g.loss_p, 0, at<double>(c, c->L.lpart), at<int>(c, c->L.err));
+                       g.loss_p, at<double>(c, c->L.lpart), at<int>(c, c->L.err));
     loss_final(c, 1, B, loss_dev);
     if (dLdI)
         hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, g.N,
-                           g.loss_kind, g.loss_p, 0, at<double>(c, c->L.scal), 0, dLdI, nullptr);
+                           g.loss_kind, g.loss_p, at<double>(c, c->L.scal), dLdI);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
 
