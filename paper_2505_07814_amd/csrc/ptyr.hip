@@ -486,7 +486,7 @@ struct ptyr_ctx {
     // second stream for the other row range of a split batch, with the
     // fork / join events that order it against `stream` (default priority)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_loss = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_a1 = nullptr, ev_loss = nullptr, ev_join = nullptr;
     int n_cu = 0;
     Layout L;
     int fwd_valid;   // waves / intensities of the last forward are in the workspace
@@ -605,6 +605,7 @@ ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, vo
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_loss, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_a1, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         ptyr_destroy(c);
         return PTYR_E_DEVICE;
@@ -622,6 +623,7 @@ void ptyr_destroy(ptyr_ctx* ctx) {
     if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_mid) hipEventDestroy(ctx->ev_mid);
     if (ctx->ev_loss) hipEventDestroy(ctx->ev_loss);
+    if (ctx->ev_a1) hipEventDestroy(ctx->ev_a1);
     if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
     if (ctx->side) hipStreamDestroy(ctx->side);
     delete ctx;
@@ -822,10 +824,10 @@ void loss_rows(ptyr_ctx* c, const float* Ie, const int* midx, int nm, int r0, in
                        at<float>(c, c->L.wbuf) + (size_t)r0 * NN, at<int>(c, c->L.err));
 }
 
-void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev) {
+void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev, hipStream_t st) {
     const ptyr_geom& g = c->g;
     const double n = (double)B * g.N * g.N;
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, c->stream, at<double>(c, c->L.lpart), nslots * NPART, n,
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, at<double>(c, c->L.lpart), nslots * NPART, n,
                        g.loss_kind, (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
                        at<int>(c, c->L.err));
 }
@@ -838,7 +840,7 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
     const int nm = midx ? n_meas : B;
     hipLaunchKernelGGL(k_loss_partial, dim3(NPART), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, g.loss_kind,
                        g.loss_p, at<double>(c, c->L.lpart), at<int>(c, c->L.err));
-    loss_final(c, 1, B, loss_dev);
+    loss_final(c, 1, B, loss_dev, c->stream);
     if (dLdI)
         hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, g.N,
                            g.loss_kind, g.loss_p, at<double>(c, c->L.scal), dLdI);
@@ -847,16 +849,17 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
 
 // A batch of more chains (one workgroup each, one workgroup per compute unit)
 // than the chip has compute units would leave part of the chip idle in the
-// second round of each fused kernel.  It runs instead as: forward of the
-// first n_cu chains (every compute unit busy); forward of the remaining
-// chains on the side stream, which takes compute units as the first forward
-// ends; meanwhile the loss of the rows wholly in the first range and the
-// gradient of as many of their chains as there are compute units left over;
-// on the side stream, once the second forward is done, the loss of the
-// remaining rows and the gradient of all remaining chains.  Small kernels are
-// issued only when compute units are free, so they are not queued behind
-// pending workgroups.
-// Returns the size of the first forward range (0: no split).
+// second round of each fused kernel.  It runs instead on two streams:
+//   main: forward of chains [0, n_cu) (every compute unit busy); loss of the
+//         rows wholly inside that range; gradient of as many of their chains
+//         as compute units are left over (g1); later the gradient of chains
+//         [n_cu, B*M) and the scatter of the remaining rows.
+//   side: forward of chains [n_cu, B*M) as compute units free up; loss of the
+//         remaining rows; gradient of chains [g1, n_cu); then the batch
+//         factor and the object scatter of the first range's rows, in the
+//         compute units the main stream's last gradient launch leaves free.
+// Small kernels are issued only when compute units are free, so they are not
+// queued behind pending workgroups.  Returns n_cu (0: no split).
 int split_chains(const ptyr_ctx* c, int B) {
     const ptyr_geom& g = c->g;
     if (g.N > 128 || c->n_cu <= 0 || B * g.M <= c->n_cu) return 0;
@@ -873,11 +876,11 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     if (!reuse) prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
     const WaveArgs a = wave_args(c, tilt, dz, B);
     const double* scale = at<double>(c, c->L.scal) + 1;     // the batch factor of w (after loss_final)
-    // object-gradient scatter of batch rows [j0, j1) on the main stream
-    auto scatter = [&](int j0, int j1) {
-        if (!(g_amp || g_phase)) return;
+    // object-gradient scatter of batch rows [j0, j1) on stream st
+    auto scatter = [&](int j0, int j1, hipStream_t st) {
+        if (!(g_amp || g_phase) || j1 <= j0) return;
         const int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
-        hipLaunchKernelGGL(k_scatter_object, dim3(ntiles, g.S), dim3(256), 0, c->stream, at<float2>(c, c->L.gO),
+        hipLaunchKernelGGL(k_scatter_object, dim3(ntiles, g.S), dim3(256), 0, st, at<float2>(c, c->L.gO),
                            at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W, amp, phase, scale, g_amp,
                            g_phase);
     };
@@ -899,22 +902,25 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
             hipStreamWaitEvent(c->side, c->ev_mid, 0) != hipSuccess)
             return PTYR_E_DEVICE;
         if (g1 > 0) gradient_chains(c, a, 0, g1, c->stream);
+        if (hipEventRecord(c->ev_a1, c->stream) != hipSuccess) return PTYR_E_DEVICE;
         loss_rows(c, I_meas, idx, nm, rA, B - rA, 1, c->side);
-        if (hipEventRecord(c->ev_loss, c->side) != hipSuccess) return PTYR_E_DEVICE;
-        gradient_chains(c, a, g1, BM - g1, c->side);
-        // rows whose chains all ran in the first gradient launch are scattered
-        // while the side stream's gradient still runs (its last round leaves
-        // compute units free); the batch factor needs both loss ranges
-        const int r1 = g1 / M;
-        if (r1 > 0) {
-            if (hipStreamWaitEvent(c->stream, c->ev_loss, 0) != hipSuccess) return PTYR_E_DEVICE;
-            loss_final(c, 2, B, loss_dev);
-            scatter(0, r1);
-            scattered = r1;
-        }
-        if (hipEventRecord(c->ev_join, c->side) != hipSuccess ||
-            hipStreamWaitEvent(c->stream, c->ev_join, 0) != hipSuccess)
+        if (hipEventRecord(c->ev_loss, c->side) != hipSuccess ||
+            hipStreamWaitEvent(c->stream, c->ev_loss, 0) != hipSuccess)
             return PTYR_E_DEVICE;
+        // side: the first range's remaining gradient chains, then (the batch
+        // factor needing both loss ranges, and the first gradient launch being
+        // done) the scatter of the first range's complete rows, which runs in
+        // the compute units the main stream's last gradient launch leaves free
+        if (nA > g1) gradient_chains(c, a, g1, nA - g1, c->side);
+        if (hipStreamWaitEvent(c->side, c->ev_a1, 0) != hipSuccess) return PTYR_E_DEVICE;
+        loss_final(c, 2, B, loss_dev, c->side);
+        scatter(0, rA, c->side);
+        if (hipEventRecord(c->ev_join, c->side) != hipSuccess) return PTYR_E_DEVICE;
+        // main: the second range's gradient chains, then the remaining rows
+        gradient_chains(c, a, nA, BM - nA, c->stream);
+        if (hipStreamWaitEvent(c->stream, c->ev_join, 0) != hipSuccess) return PTYR_E_DEVICE;
+        scatter(rA, B, c->stream);
+        scattered = B;
     } else {
         if (!reuse) forward_chains(c, a, 0, BM, c->stream);
         loss_rows(c, I_meas, idx, nm, 0, B, 0, c->stream);
@@ -922,8 +928,10 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     }
     c->fwd_valid = 1;
     c->fwd_B = B;
-    if (!scattered) loss_final(c, nA ? 2 : 1, B, loss_dev);
-    scatter(scattered, B);
+    if (!scattered) {
+        loss_final(c, 1, B, loss_dev, c->stream);
+        scatter(0, B, c->stream);
+    }
     if (g_probe) {
         int NN = g.N * g.N;
         hipLaunchKernelGGL(k_sum_rows, dim3(grid_for((size_t)g.M * NN)), dim3(256), 0, c->stream,
