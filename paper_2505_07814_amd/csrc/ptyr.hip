@@ -380,15 +380,18 @@ __global__ __launch_bounds__(256) void k_param_grads(const float* part, int nblk
 // Adam (PyTorch's form): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
 // p -= (lr / bc1) * m / (sqrt(v) / sqrt(bc2) + eps)
 // All parameter blocks of a step in one launch: segment k covers elements
-// [off[k], off[k+1]) of the concatenated index range.
+// [off[k], off[k+1]) of the concatenated index range.  Each gradient entry
+// is cleared once read, so the step's gradient buffers start the next step
+// at zero; a segment with upd = 0 (learning rate 0) is only cleared.
 constexpr int ADAM_SEGS = 6;
 struct AdamSegs {
     float* p[ADAM_SEGS];
-    const float* g[ADAM_SEGS];
+    float* g[ADAM_SEGS];
     float* m[ADAM_SEGS];
     float* v[ADAM_SEGS];
     size_t off[ADAM_SEGS + 1];
     float lr[ADAM_SEGS];
+    int upd[ADAM_SEGS];
 };
 __global__ void k_adam_segs(AdamSegs a, float b1, float b2, float eps, float bc1, float bc2s) {
     const size_t n = a.off[ADAM_SEGS];
@@ -399,6 +402,8 @@ __global__ void k_adam_segs(AdamSegs a, float b1, float b2, float eps, float bc1
             if (i >= a.off[q]) k = q;
         const size_t e = i - a.off[k];
         const float gi = a.g[k][e];
+        a.g[k][e] = 0.f;
+        if (!a.upd[k]) continue;
         const float mi = b1 * a.m[k][e] + (1.f - b1) * gi;
         const float vi = b2 * a.v[k][e] + (1.f - b2) * gi * gi;
         a.m[k][e] = mi;
@@ -491,6 +496,7 @@ struct ptyr_ctx {
     Layout L;
     int fwd_valid;   // waves / intensities of the last forward are in the workspace
     int fwd_B;
+    int step_grads_clear = 0;   // ptyr_step's gradient buffers are all zero
     // instrumentation: event pairs around the fused kernels
     int timing = 0;
     std::vector<hipEvent_t> ev;      // 2 per launch
@@ -1028,8 +1034,13 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
     float* gdz = at<float>(c, c->L.gdz);
     float* gpos = at<float>(c, c->L.gpos);
     float* gtilt = at<float>(c, c->L.gtilt);
-    // the six gradient buffers are consecutive in the workspace: one clear
-    zero(c, gamp, (size_t)(reinterpret_cast<char*>(gtilt + ntilt) - reinterpret_cast<char*>(gamp)) / sizeof(float));
+    // The six gradient buffers are consecutive in the workspace; they are
+    // cleared once here and afterwards by each step's Adam as it reads them
+    // (an interrupted step leaves them to be cleared again).
+    if (!c->step_grads_clear)
+        zero(c, gamp, (size_t)(reinterpret_cast<char*>(at<float>(c, c->L.gtilt) + std::max(g.n_scan, 1) * 2) -
+                               reinterpret_cast<char*>(gamp)) / sizeof(float));
+    c->step_grads_clear = 0;
     st = run_adjoint(c, p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz, idx, p->n_pos, B, I_meas_all,
                      rates[0] > 0.f ? gamp : nullptr, rates[1] > 0.f ? gphase : nullptr,
                      rates[2] > 0.f ? gprobe : nullptr, gpos, gtilt, gdz, loss_dev, 0);
@@ -1038,23 +1049,28 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
     {
         AdamSegs A;
         float* const params[6] = {p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz};
-        const float* const grads[6] = {gamp, gphase, gprobe, gpos, gtilt, gdz};
+        float* const grads[6] = {gamp, gphase, gprobe, gpos, gtilt, gdz};
         const size_t sizes[6] = {nobj, nobj, nprb, npos, ntilt, 1};
         A.off[0] = 0;
         for (int k = 0; k < 6; ++k) {
-            const bool on = rates[k] > 0.f;          // a zero rate leaves the parameter and its moments alone
+            // a zero rate leaves the parameter and its moments alone; the
+            // object and probe gradients are then not even accumulated, the
+            // position / tilt / dz ones are and only need clearing
+            const bool on = rates[k] > 0.f;
             A.p[k] = params[k];
             A.g[k] = grads[k];
             A.m[k] = mv[k][0];
             A.v[k] = mv[k][1];
             A.lr[k] = rates[k];
-            A.off[k + 1] = A.off[k] + (on ? sizes[k] : 0);
+            A.upd[k] = on ? 1 : 0;
+            A.off[k + 1] = A.off[k] + ((on || k >= 3) ? sizes[k] : 0);
         }
         const double bc1 = 1.0 - pow((double)lr->beta1, (double)t);
         const double bc2 = 1.0 - pow((double)lr->beta2, (double)t);
         if (A.off[6] > 0)
             hipLaunchKernelGGL(k_adam_segs, dim3(grid_for(A.off[6])), dim3(256), 0, c->stream, A, lr->beta1,
                                lr->beta2, lr->eps, (float)bc1, (float)sqrt(bc2));
+        c->step_grads_clear = 1;
     }
     p->step = t;
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
