@@ -6,12 +6,15 @@ measured in the same run, and written with the hash of the kernel sources
 so that bench.py can tell whether they still describe the current kernels.
 
 usage: python -m paper_2505_07814_amd.profile_summary FETCH_CSV WRITE_CSV
-           KERNELS OUT_TXT [--launches K] COMMAND...
+           KERNELS OUT_TXT [--launches K] [--grids G1,G2,...] COMMAND...
 
 KERNELS is a comma-separated list of kernel-name substrings.  Without
 --launches the figure is the average per matching dispatch; with it, the
 total over all matching dispatches divided by K (for a timed unit made of
-several dispatches, such as the N=256 line passes of one gradient).
+several dispatches, such as the N=256 line passes of one gradient).  With
+--grids only dispatches of those grid sizes (work-items) count, which keeps
+the launches of a timed step apart from other launches of the same kernel in
+the profiled run (such as data generation).
 """
 import csv
 import hashlib
@@ -34,11 +37,15 @@ def source_hash(files=MULTISLICE_SOURCES):
     return h.hexdigest()[:16]
 
 
-def per_kernel(path, counter):
-    """{kernel name: [values of counter per dispatch]}"""
+def per_kernel(path, counter, grids=None):
+    """{kernel name: [values of counter per dispatch]}; with `grids`, the
+    copy kernels and the dispatches of those grid sizes only"""
     out = {}
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name") != counter:
+            continue
+        name = r["Kernel_Name"].lower()
+        if grids and r.get("Grid_Size") not in grids and "copy" not in name and "elementwise" not in name:
             continue
         out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return out
@@ -48,14 +55,18 @@ def main(argv):
     fetch_csv, write_csv, knames, out_txt = argv[:4]
     rest = argv[4:]
     launches = None
-    if rest and rest[0] == "--launches":
-        launches = int(rest[1])
+    grids = None
+    while rest and rest[0] in ("--launches", "--grids"):
+        if rest[0] == "--launches":
+            launches = int(rest[1])
+        else:
+            grids = {g for g in rest[1].split(",") if g}
         rest = rest[2:]
     cmd = " ".join(rest)
     keys = [k for k in knames.split(",") if k]
     kname = knames
-    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
-    write = per_kernel(write_csv, "WRITE_SIZE")
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE", grids)
+    write = per_kernel(write_csv, "WRITE_SIZE", grids)
     copy_f = [v for k, v in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower()]
     copy_w = [v for k, v in write.items() if "copy" in k.lower() or "elementwise" in k.lower()]
     big_f = max((x for vals in copy_f for x in vals), default=0.0)
@@ -71,6 +82,7 @@ def main(argv):
     lines = [
         f"# HBM traffic of {kname} (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)",
         f"# command: {cmd}",
+    ] + ([f"# dispatches of grid sizes {','.join(sorted(grids, key=int))} only"] if grids else []) + [
         f"# dispatches: fetch {len(kf_vals)}, write {len(kw_vals)}" + (f", per timed launch of {len(kf_vals) // launches}" if launches else ""),
         f"# copy calibration (512 MiB device copy): FETCH_SIZE {big_f:.0f} KiB, WRITE_SIZE {big_w:.0f} KiB",
         f"fetch_kib_per_launch = {af:.1f}",
