@@ -244,6 +244,25 @@ __global__ __launch_bounds__(256) void k_loss_rows(const float* Imode, float* I,
         for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = sh[k * 256];
 }
 
+// One Adam update of a parameter element (Kingma & Ba, Alg. 1 with the bias
+// corrections folded into the step: bc1 = 1 - b1^t, bc2s = sqrt(1 - b2^t)).
+__device__ __forceinline__ void adam_elem(float& p, float& m, float& v, float g, float lr, float b1, float b2,
+                                          float eps, float bc1, float bc2s) {
+    const float mi = b1 * m + (1.f - b1) * g;
+    const float vi = b2 * v + (1.f - b2) * g * g;
+    m = mi;
+    v = vi;
+    p -= (lr / bc1) * mi / (sqrtf(vi) / bc2s + eps);
+}
+
+// Adam of the object, fused into the last scatter of a step: the parameter
+// whose gradient buffer is non-null is updated and its buffer cleared.
+struct ObjAdam {
+    float *amp, *phase;                     // the parameters (read, then updated in place)
+    float *m_amp, *v_amp, *m_phase, *v_phase;
+    float lr_amp, lr_phase, b1, b2, eps, bc1, bc2s;
+};
+
 // Object gradient: each workgroup owns a 32 x 32 tile of one slice and sums,
 // in batch order, the patch gradients of every (position, mode) of batch rows
 // [j0, j1) covering it;
@@ -252,12 +271,15 @@ __global__ __launch_bounds__(256) void k_loss_rows(const float* Imode, float* I,
 // A thread owns one column of the tile and four rows 8 apart, so each load
 // instruction reads two whole 256-byte tile rows of a patch; the loads of up
 // to MB modes of one position are issued together before they are added (in
-// mode order), to keep enough bytes in flight per workgroup.
+// mode order), to keep enough bytes in flight per workgroup.  FUSE: the
+// launch also takes every pixel's complete gradient (buffer + this sum)
+// through Adam (ObjAdam) and clears the buffer, untouched tiles included.
 constexpr int SCATTER_MB = 8;
+template <bool FUSE>
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int j0, int j1, int M,
                                                         int S, int N, int H, int W, const float* amp,
                                                         const float* phase, const double* scale, float* g_amp,
-                                                        float* g_phase) {
+                                                        float* g_phase, ObjAdam ad) {
     const int ntx = (W + 31) / 32;
     const int tile = blockIdx.x, s = blockIdx.y;
     const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
@@ -293,19 +315,38 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
                 for (int i = 0; i < 4; ++i) acc[i] = cadd(acc[i], buf[mm][i]);
         }
     }
-    if (!touched || x >= W) return;
+    if ((!FUSE && !touched) || x >= W) return;
     const float sc = (float)*scale;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = yb + 8 * i;
         if (y >= H) continue;
         size_t o = ((size_t)s * H + y) * W + x;
-        float sn, cs;
-        sincosf(phase[o], &sn, &cs);
-        float a = amp[o];
-        float2 G = cscale(acc[i], sc);
-        if (g_amp) g_amp[o] += G.x * cs + G.y * sn;          // Re(conj(G) e^{i phi})
-        if (g_phase) g_phase[o] += a * (G.y * cs - G.x * sn); // Im(G conj(a e^{i phi}))
+        float ga = 0.f, gp = 0.f;
+        if (!FUSE || touched) {
+            float sn, cs;
+            sincosf(phase[o], &sn, &cs);
+            float a = amp[o];
+            float2 G = cscale(acc[i], sc);
+            ga = G.x * cs + G.y * sn;              // Re(conj(G) e^{i phi})
+            gp = a * (G.y * cs - G.x * sn);        // Im(G conj(a e^{i phi}))
+        }
+        if constexpr (!FUSE) {
+            if (g_amp) g_amp[o] += ga;
+            if (g_phase) g_phase[o] += gp;
+        } else {
+            if (g_amp) {
+                const float gi = g_amp[o] + ga;
+                g_amp[o] = 0.f;
+                adam_elem(ad.amp[o], ad.m_amp[o], ad.v_amp[o], gi, ad.lr_amp, ad.b1, ad.b2, ad.eps, ad.bc1, ad.bc2s);
+            }
+            if (g_phase) {
+                const float gi = g_phase[o] + gp;
+                g_phase[o] = 0.f;
+                adam_elem(ad.phase[o], ad.m_phase[o], ad.v_phase[o], gi, ad.lr_phase, ad.b1, ad.b2, ad.eps, ad.bc1,
+                          ad.bc2s);
+            }
+        }
     }
 }
 
@@ -404,11 +445,7 @@ __global__ void k_adam_segs(AdamSegs a, float b1, float b2, float eps, float bc1
         const float gi = a.g[k][e];
         a.g[k][e] = 0.f;
         if (!a.upd[k]) continue;
-        const float mi = b1 * a.m[k][e] + (1.f - b1) * gi;
-        const float vi = b2 * a.v[k][e] + (1.f - b2) * gi * gi;
-        a.m[k][e] = mi;
-        a.v[k][e] = vi;
-        a.p[k][e] -= (a.lr[k] / bc1) * mi / (sqrtf(vi) / bc2s + eps);
+        adam_elem(a.p[k][e], a.m[k][e], a.v[k][e], gi, a.lr[k], b1, b2, eps, bc1, bc2s);
     }
 }
 
@@ -491,7 +528,8 @@ struct ptyr_ctx {
     // second stream for the other row range of a split batch, with the
     // fork / join events that order it against `stream` (default priority)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_a1 = nullptr, ev_loss = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_a1 = nullptr, ev_loss = nullptr, ev_gdone = nullptr,
+               ev_red = nullptr, ev_join = nullptr;
     int n_cu = 0;
     Layout L;
     int fwd_valid;   // waves / intensities of the last forward are in the workspace
@@ -612,6 +650,8 @@ ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, vo
         hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_loss, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_a1, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_gdone, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_red, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         ptyr_destroy(c);
         return PTYR_E_DEVICE;
@@ -630,6 +670,8 @@ void ptyr_destroy(ptyr_ctx* ctx) {
     if (ctx->ev_mid) hipEventDestroy(ctx->ev_mid);
     if (ctx->ev_loss) hipEventDestroy(ctx->ev_loss);
     if (ctx->ev_a1) hipEventDestroy(ctx->ev_a1);
+    if (ctx->ev_gdone) hipEventDestroy(ctx->ev_gdone);
+    if (ctx->ev_red) hipEventDestroy(ctx->ev_red);
     if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
     if (ctx->side) hipStreamDestroy(ctx->side);
     delete ctx;
@@ -768,8 +810,8 @@ void gradient_chains(ptyr_ctx* c, const WaveArgs& a, int c0, int nc, hipStream_t
     else gradient256(c, a, c0, nc, st);
 }
 
-template <int N> void launch_probe_fft(ptyr_ctx* c, const float* probe) {
-    hipLaunchKernelGGL((k_fft2<N, -1, false>), dim3(c->g.M), dim3(N * N / 16), 0, c->stream,
+template <int N> void launch_probe_fft(ptyr_ctx* c, const float* probe, hipStream_t st) {
+    hipLaunchKernelGGL((k_fft2<N, -1, false>), dim3(c->g.M), dim3(N * N / 16), 0, st,
                        reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat));
 }
 template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe, hipStream_t st) {
@@ -781,19 +823,20 @@ template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe, hipStre
 // positions, probe spectra.
 void prepare_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
                      const int* idx, int n_rows, int B) {
+    const hipStream_t st = c->stream;
     const ptyr_geom& g = c->g;
     size_t nobj = (size_t)g.S * g.H * g.W;
-    hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, c->stream, amp, phase,
+    hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, st, amp, phase,
                        at<float2>(c, c->L.Oc), nobj);
-    hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, c->stream, pos, idx, idx ? n_rows : B, B,
-                       g.N, g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err));
-    if (g.N == 64) launch_probe_fft<64>(c, probe);
-    else if (g.N == 128) launch_probe_fft<128>(c, probe);
+    hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, st, pos, idx, idx ? n_rows : B, B, g.N, g.H,
+                       g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err));
+    if (g.N == 64) launch_probe_fft<64>(c, probe, st);
+    else if (g.N == 128) launch_probe_fft<128>(c, probe, st);
     else {
         const dim3 grid(g.M * NBLK256), blk(256);
-        hipLaunchKernelGGL((k256_fft<-1, true, false>), grid, blk, 0, c->stream,
-                           reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat));
-        hipLaunchKernelGGL((k256_fft<-1, false, false>), grid, blk, 0, c->stream, at<float2>(c, c->L.Phat),
+        hipLaunchKernelGGL((k256_fft<-1, true, false>), grid, blk, 0, st, reinterpret_cast<const float2*>(probe),
+                           at<float2>(c, c->L.Phat));
+        hipLaunchKernelGGL((k256_fft<-1, false, false>), grid, blk, 0, st, at<float2>(c, c->L.Phat),
                            at<float2>(c, c->L.Phat));
     }
 }
@@ -875,23 +918,52 @@ int split_chains(const ptyr_ctx* c, int B) {
 ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
                         const float* tilt, const float* dz, const int* idx, int n_rows, int B,
                         const float* I_meas, float* g_amp, float* g_phase, float* g_probe, float* g_pos,
-                        float* g_tilt, float* g_dz, double* loss_dev, unsigned flags) {
+                        float* g_tilt, float* g_dz, double* loss_dev, unsigned flags,
+                        const ObjAdam* fuse = nullptr) {
     const ptyr_geom& g = c->g;
     const int M = g.M, nm = idx ? n_rows : B, BM = B * M;
     const bool reuse = (flags & PTYR_REUSE_FORWARD) && c->fwd_valid && c->fwd_B == B;
+    const int nA = reuse ? 0 : split_chains(c, B);
     if (!reuse) prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
     const WaveArgs a = wave_args(c, tilt, dz, B);
     const double* scale = at<double>(c, c->L.scal) + 1;     // the batch factor of w (after loss_final)
-    // object-gradient scatter of batch rows [j0, j1) on stream st
-    auto scatter = [&](int j0, int j1, hipStream_t st) {
-        if (!(g_amp || g_phase) || j1 <= j0) return;
+    // object-gradient scatter of batch rows [j0, j1) on stream st; `last`
+    // (the batch's final scatter) runs the fused object Adam when asked
+    auto scatter = [&](int j0, int j1, hipStream_t st, bool last) {
+        if (!(g_amp || g_phase)) return;
         const int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
-        hipLaunchKernelGGL(k_scatter_object, dim3(ntiles, g.S), dim3(256), 0, st, at<float2>(c, c->L.gO),
-                           at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W, amp, phase, scale, g_amp,
-                           g_phase);
+        if (last && fuse) {
+            hipLaunchKernelGGL(k_scatter_object<true>, dim3(ntiles, g.S), dim3(256), 0, st, at<float2>(c, c->L.gO),
+                               at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W, amp, phase, scale,
+                               g_amp, g_phase, *fuse);
+        } else if (j1 > j0) {
+            hipLaunchKernelGGL(k_scatter_object<false>, dim3(ntiles, g.S), dim3(256), 0, st,
+                               at<float2>(c, c->L.gO), at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W,
+                               amp, phase, scale, g_amp, g_phase, ObjAdam{});
+        }
+    };
+    // probe-spectrum sum and inverse transform, position / tilt / dz partials
+    auto reductions = [&](hipStream_t st) {
+        if (g_probe) {
+            int NN = g.N * g.N;
+            hipLaunchKernelGGL(k_sum_rows, dim3(grid_for((size_t)g.M * NN)), dim3(256), 0, st,
+                               at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B, g.M, NN, scale);
+            if (g.N == 64) launch_probe_ifft_acc<64>(c, g_probe, st);
+            else if (g.N == 128) launch_probe_ifft_acc<128>(c, g_probe, st);
+            else {
+                const dim3 grid(g.M * NBLK256), blk(256);
+                hipLaunchKernelGGL((k256_fft<+1, true, false>), grid, blk, 0, st, at<float2>(c, c->L.gPsum),
+                                   at<float2>(c, c->L.gPsum));
+                hipLaunchKernelGGL((k256_fft<+1, false, true>), grid, blk, 0, st, at<float2>(c, c->L.gPsum),
+                                   reinterpret_cast<float2*>(g_probe));
+            }
+        }
+        if (g_pos || g_tilt || g_dz)
+            hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(256), 0, st, at<float>(c, c->L.part),
+                               g.N == 256 ? NBLK256 : 1, at<PosInfo>(c, c->L.pinfo), B, g.M, tilt, a.global_tilt, dz,
+                               g.lambda, scale, g_pos, g_tilt, g_dz);
     };
     int scattered = 0;                                       // rows already scattered
-    const int nA = reuse ? 0 : split_chains(c, B);
     if (nA) {
         const int rA = nA / M;                                     // rows complete after the first forward
         const int g1 = std::min(rA * M, std::max(0, c->n_cu - (BM - nA)));   // early gradient chains
@@ -920,12 +992,20 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         if (nA > g1) gradient_chains(c, a, g1, nA - g1, c->side);
         if (hipStreamWaitEvent(c->side, c->ev_a1, 0) != hipSuccess) return PTYR_E_DEVICE;
         loss_final(c, 2, B, loss_dev, c->side);
-        scatter(0, rA, c->side);
+        scatter(0, rA, c->side, false);
         if (hipEventRecord(c->ev_join, c->side) != hipSuccess) return PTYR_E_DEVICE;
-        // main: the second range's gradient chains, then the remaining rows
+        // main: the second range's gradient chains, then the remaining rows'
+        // scatter; the side stream meanwhile runs the probe / parameter
+        // reductions, which need every chain
         gradient_chains(c, a, nA, BM - nA, c->stream);
+        if (hipEventRecord(c->ev_gdone, c->stream) != hipSuccess ||
+            hipStreamWaitEvent(c->side, c->ev_gdone, 0) != hipSuccess)
+            return PTYR_E_DEVICE;
+        reductions(c->side);
+        if (hipEventRecord(c->ev_red, c->side) != hipSuccess) return PTYR_E_DEVICE;
         if (hipStreamWaitEvent(c->stream, c->ev_join, 0) != hipSuccess) return PTYR_E_DEVICE;
-        scatter(rA, B, c->stream);
+        scatter(rA, B, c->stream, true);
+        if (hipStreamWaitEvent(c->stream, c->ev_red, 0) != hipSuccess) return PTYR_E_DEVICE;
         scattered = B;
     } else {
         if (!reuse) forward_chains(c, a, 0, BM, c->stream);
@@ -936,26 +1016,9 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     c->fwd_B = B;
     if (!scattered) {
         loss_final(c, 1, B, loss_dev, c->stream);
-        scatter(0, B, c->stream);
+        reductions(c->stream);
+        scatter(0, B, c->stream, true);
     }
-    if (g_probe) {
-        int NN = g.N * g.N;
-        hipLaunchKernelGGL(k_sum_rows, dim3(grid_for((size_t)g.M * NN)), dim3(256), 0, c->stream,
-                           at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B, g.M, NN, scale);
-        if (g.N == 64) launch_probe_ifft_acc<64>(c, g_probe, c->stream);
-        else if (g.N == 128) launch_probe_ifft_acc<128>(c, g_probe, c->stream);
-        else {
-            const dim3 grid(g.M * NBLK256), blk(256);
-            hipLaunchKernelGGL((k256_fft<+1, true, false>), grid, blk, 0, c->stream, at<float2>(c, c->L.gPsum),
-                               at<float2>(c, c->L.gPsum));
-            hipLaunchKernelGGL((k256_fft<+1, false, true>), grid, blk, 0, c->stream, at<float2>(c, c->L.gPsum),
-                               reinterpret_cast<float2*>(g_probe));
-        }
-    }
-    if (g_pos || g_tilt || g_dz)
-        hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(256), 0, c->stream, at<float>(c, c->L.part),
-                           g.N == 256 ? NBLK256 : 1, at<PosInfo>(c, c->L.pinfo), B, g.M, tilt, a.global_tilt, dz,
-                           g.lambda, scale, g_pos, g_tilt, g_dz);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
 
@@ -1041,11 +1104,17 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
         zero(c, gamp, (size_t)(reinterpret_cast<char*>(at<float>(c, c->L.gtilt) + std::max(g.n_scan, 1) * 2) -
                                reinterpret_cast<char*>(gamp)) / sizeof(float));
     c->step_grads_clear = 0;
+    const int64_t t = p->step + 1;
+    const double bc1 = 1.0 - pow((double)lr->beta1, (double)t);
+    const double bc2 = 1.0 - pow((double)lr->beta2, (double)t);
+    // the object's Adam runs inside the batch's last object scatter
+    const ObjAdam oa{p->amp,     p->phase,  p->m_amp,   p->v_amp,  p->m_phase,    p->v_phase,
+                     rates[0],   rates[1],  lr->beta1,  lr->beta2, lr->eps,       (float)bc1,
+                     (float)sqrt(bc2)};
     st = run_adjoint(c, p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz, idx, p->n_pos, B, I_meas_all,
                      rates[0] > 0.f ? gamp : nullptr, rates[1] > 0.f ? gphase : nullptr,
-                     rates[2] > 0.f ? gprobe : nullptr, gpos, gtilt, gdz, loss_dev, 0);
+                     rates[2] > 0.f ? gprobe : nullptr, gpos, gtilt, gdz, loss_dev, 0, &oa);
     if (st != PTYR_OK) return st;
-    const int64_t t = p->step + 1;
     {
         AdamSegs A;
         float* const params[6] = {p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz};
@@ -1055,8 +1124,9 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
         for (int k = 0; k < 6; ++k) {
             // a zero rate leaves the parameter and its moments alone; the
             // object and probe gradients are then not even accumulated, the
-            // position / tilt / dz ones are and only need clearing
-            const bool on = rates[k] > 0.f;
+            // position / tilt / dz ones are and only need clearing.  The
+            // object (k < 2) was updated by the fused scatter.
+            const bool on = rates[k] > 0.f && k >= 2;
             A.p[k] = params[k];
             A.g[k] = grads[k];
             A.m[k] = mv[k][0];
@@ -1065,8 +1135,6 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
             A.upd[k] = on ? 1 : 0;
             A.off[k + 1] = A.off[k] + ((on || k >= 3) ? sizes[k] : 0);
         }
-        const double bc1 = 1.0 - pow((double)lr->beta1, (double)t);
-        const double bc2 = 1.0 - pow((double)lr->beta2, (double)t);
         if (A.off[6] > 0)
             hipLaunchKernelGGL(k_adam_segs, dim3(grid_for(A.off[6])), dim3(256), 0, c->stream, A, lr->beta1,
                                lr->beta2, lr->eps, (float)bc1, (float)sqrt(bc2));

@@ -312,6 +312,57 @@ def test_adam_step_parity():
         assert err < 1e-3, (k, err)
 
 
+@pytest.mark.parametrize("which", ["all", "phase_only"])
+def test_step_split_batch_matches_adjoint_then_adam(which):
+    """ptyr_step on a batch of more chains than compute units (two-stream
+    schedule, the object's Adam fused into the batch's last scatter) equals
+    ptyr_adjoint's gradients of the same batch followed by Adam in float64,
+    over two steps (the second also shows that the first left its gradient
+    buffers cleared).  The gradients are the same kernels' in the same order,
+    so the parameters differ only by the float32 Adam arithmetic and the
+    rounding of the updated parameter."""
+    from paper_2505_07814_amd.ptyr import AdamState, Engine
+    print(f"step N=64 S=3 M=3 B=90 ({which})", flush=True)
+    w = synth.small_case(N=64, S=3, M=3, B=90, H=64 + 60, W=64 + 70, seed=31)
+    c = Case(w)
+    lr = dict(amp=1e-3, phase=2e-3, probe=1e-2, pos=1e-2, tilt=1e-4, dz=1e-1)
+    if which == "phase_only":
+        lr = dict(amp=0.0, phase=2e-3, probe=0.0, pos=0.0, tilt=0.0, dz=0.0)
+    eng = Engine(64, 3, 3, w.H, w.W, 90, w.dx, c.lam, device=DEV, n_scan=90)
+    ref_eng = c.engine()
+    st = AdamState(*[t.clone() for t in c.gpu_args()])
+    meas = T(c.meas)
+    b1, b2, eps = float(np.float32(0.9)), float(np.float32(0.999)), float(np.float32(1e-8))
+    for t, order in enumerate([np.arange(90), np.arange(90)[::-1].copy()]):
+        idx = torch.tensor(order, dtype=torch.int32, device=DEV)
+        before = {k: getattr(st, k).clone() for k in st.NAMES}
+        m0 = {k: st.m[k].clone() for k in st.NAMES}
+        v0 = {k: st.v[k].clone() for k in st.NAMES}
+        eng.step(st, idx, meas, lr)
+        _, g = ref_eng.adjoint(*[before[k] for k in st.NAMES], meas, idx=idx)
+        eng.sync()
+        ref_eng.sync()
+        for k in st.NAMES:
+            p0 = before[k].cpu().numpy()
+            got = getattr(st, k).cpu().numpy()
+            if lr[k] == 0:
+                assert np.array_equal(got, p0), k
+                continue
+            f64 = lambda x: np.asarray(x, np.complex128 if np.iscomplexobj(x) else np.float64)
+            rp, _, _ = adam_step(f64(p0), f64(g[k].cpu().numpy()), f64(m0[k].cpu().numpy()),
+                                 f64(v0[k].cpu().numpy()), t, lr[k], beta1=b1, beta2=b2, eps=eps)
+            # the float32 parameter is the reference update rounded, to 2 ulp
+            # (an update of 1e-3 on a parameter near 1 is itself only held to
+            # ~6e-5 relative by float32)
+            got_r = got.view(np.float32) if np.iscomplexobj(got) else got
+            p0_r = p0.view(np.float32) if np.iscomplexobj(p0) else p0
+            rp_r = np.stack([rp.real, rp.imag], -1).ravel() if np.iscomplexobj(rp) else np.ravel(rp)
+            d = np.abs(np.ravel(got_r).astype(np.float64) - rp_r)
+            tol = 2 * np.spacing(np.abs(rp_r).astype(np.float32)) + 1e-5 * np.abs(rp_r - np.ravel(p0_r))
+            print(f"step {t + 1} {k}: max |P - P_ref| / tol {np.max(d / tol):.2f}", flush=True)
+            assert np.all(d <= tol), (t, k, float(np.max(d / tol)))
+
+
 def test_autograd_function_matches_adjoint():
     from paper_2505_07814_amd.ptyr import multislice_loss
     c = Case(small(64, 3, 2, 4, 27))
