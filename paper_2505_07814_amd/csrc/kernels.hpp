@@ -212,6 +212,15 @@ __device__ __forceinline__ void block_sum(float (&x)[NV], float* red) {
 }
 
 // ------------------------------------------------------------------ kernels
+// LDS slots the forward declares.  At N = 128 it uses half of the compute
+// unit's 160 KiB but reserves all of it: small kernels launched beside the
+// forward (the loss rows of the first chain range) then run on free compute
+// units instead of sharing the forward's, where they would stretch out
+// behind its waves (measured: 67 -> 28 us for those loss rows).
+template <int N> constexpr int fwd_lds_slots() {
+    return N == 128 ? (int)((160 * 1024 - sizeof(Tables<N>)) / sizeof(float2)) : WaveGeo<N>::LDS_SLOTS;
+}
+
 // Forward: one workgroup per (batch row j, probe mode m).  KEEP (the wave
 // store plan) is a template parameter so that the hot loop has no
 // data-dependent branch around its writes: at such a merge the compiler's
@@ -219,7 +228,7 @@ __device__ __forceinline__ void block_sum(float (&x)[NV], float* red) {
 template <int N, int KEEP>
 __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     constexpr int L = N / 16;
-    __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
+    __shared__ float2 lds[fwd_lds_slots<N>()];
     __shared__ Tables<N> tab;
     const int l = threadIdx.x / L, c = threadIdx.x % L;
     const int wg = a.chain0 + xcd_remap(blockIdx.x, gridDim.x);

@@ -529,7 +529,7 @@ struct ptyr_ctx {
     // fork / join events that order it against `stream` (default priority)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_a1 = nullptr, ev_loss = nullptr, ev_gdone = nullptr,
-               ev_red = nullptr, ev_join = nullptr;
+               ev_join = nullptr;
     int n_cu = 0;
     Layout L;
     int fwd_valid;   // waves / intensities of the last forward are in the workspace
@@ -651,7 +651,6 @@ ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, vo
         hipEventCreateWithFlags(&c->ev_loss, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_a1, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_gdone, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_red, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         ptyr_destroy(c);
         return PTYR_E_DEVICE;
@@ -671,7 +670,6 @@ void ptyr_destroy(ptyr_ctx* ctx) {
     if (ctx->ev_loss) hipEventDestroy(ctx->ev_loss);
     if (ctx->ev_a1) hipEventDestroy(ctx->ev_a1);
     if (ctx->ev_gdone) hipEventDestroy(ctx->ev_gdone);
-    if (ctx->ev_red) hipEventDestroy(ctx->ev_red);
     if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
     if (ctx->side) hipStreamDestroy(ctx->side);
     delete ctx;
@@ -993,19 +991,21 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         if (hipStreamWaitEvent(c->side, c->ev_a1, 0) != hipSuccess) return PTYR_E_DEVICE;
         loss_final(c, 2, B, loss_dev, c->side);
         scatter(0, rA, c->side, false);
-        if (hipEventRecord(c->ev_join, c->side) != hipSuccess) return PTYR_E_DEVICE;
-        // main: the second range's gradient chains, then the remaining rows'
-        // scatter; the side stream meanwhile runs the probe / parameter
-        // reductions, which need every chain
+        // main: the second range's gradient chains, then the probe /
+        // parameter reductions, which need every chain; the side stream
+        // meanwhile scatters the remaining rows.  (The reductions' probe
+        // transform needs whole compute units: issued first, on the stream
+        // that is already running, it gets them before the scatter fills
+        // the chip.)
         gradient_chains(c, a, nA, BM - nA, c->stream);
         if (hipEventRecord(c->ev_gdone, c->stream) != hipSuccess ||
             hipStreamWaitEvent(c->side, c->ev_gdone, 0) != hipSuccess)
             return PTYR_E_DEVICE;
-        reductions(c->side);
-        if (hipEventRecord(c->ev_red, c->side) != hipSuccess) return PTYR_E_DEVICE;
-        if (hipStreamWaitEvent(c->stream, c->ev_join, 0) != hipSuccess) return PTYR_E_DEVICE;
-        scatter(rA, B, c->stream, true);
-        if (hipStreamWaitEvent(c->stream, c->ev_red, 0) != hipSuccess) return PTYR_E_DEVICE;
+        reductions(c->stream);
+        scatter(rA, B, c->side, true);
+        if (hipEventRecord(c->ev_join, c->side) != hipSuccess ||
+            hipStreamWaitEvent(c->stream, c->ev_join, 0) != hipSuccess)
+            return PTYR_E_DEVICE;
         scattered = B;
     } else {
         if (!reuse) forward_chains(c, a, 0, BM, c->stream);
