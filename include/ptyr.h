@@ -136,7 +136,7 @@ ptyr_status ptyr_checkpoint_plan(const ptyr_geom* g, int* stride);
 /* Bind a context to a workspace (device, caller-owned, >= ptyr_workspace_bytes,
  * 256-byte aligned) and a stream (hipStream_t as void*; NULL = the default
  * stream), on the current device.  Besides pointers the context owns one
- * extra stream of default priority and six events: a batch with more
+ * extra stream of default priority and seven events: a batch with more
  * (row, mode) chains than the device has compute units runs part of its
  * chains on that stream, joined back to the caller's stream before
  * ptyr_adjoint / ptyr_step return, so callers only ever order work against

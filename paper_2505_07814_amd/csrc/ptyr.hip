@@ -528,8 +528,8 @@ struct ptyr_ctx {
     // second stream for the other row range of a split batch, with the
     // fork / join events that order it against `stream` (default priority)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_a1 = nullptr, ev_loss = nullptr, ev_gdone = nullptr,
-               ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_a1 = nullptr, ev_loss = nullptr, ev_sgrad = nullptr,
+               ev_gdone = nullptr, ev_join = nullptr;
     int n_cu = 0;
     Layout L;
     int fwd_valid;   // waves / intensities of the last forward are in the workspace
@@ -650,6 +650,7 @@ ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, vo
         hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_loss, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_a1, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_sgrad, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_gdone, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         ptyr_destroy(c);
@@ -669,6 +670,7 @@ void ptyr_destroy(ptyr_ctx* ctx) {
     if (ctx->ev_mid) hipEventDestroy(ctx->ev_mid);
     if (ctx->ev_loss) hipEventDestroy(ctx->ev_loss);
     if (ctx->ev_a1) hipEventDestroy(ctx->ev_a1);
+    if (ctx->ev_sgrad) hipEventDestroy(ctx->ev_sgrad);
     if (ctx->ev_gdone) hipEventDestroy(ctx->ev_gdone);
     if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
     if (ctx->side) hipStreamDestroy(ctx->side);
@@ -990,16 +992,18 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         if (nA > g1) gradient_chains(c, a, g1, nA - g1, c->side);
         if (hipStreamWaitEvent(c->side, c->ev_a1, 0) != hipSuccess) return PTYR_E_DEVICE;
         loss_final(c, 2, B, loss_dev, c->side);
+        if (hipEventRecord(c->ev_sgrad, c->side) != hipSuccess) return PTYR_E_DEVICE;
         scatter(0, rA, c->side, false);
-        // main: the second range's gradient chains, then the probe /
-        // parameter reductions, which need every chain; the side stream
-        // meanwhile scatters the remaining rows.  (The reductions' probe
-        // transform needs whole compute units: issued first, on the stream
-        // that is already running, it gets them before the scatter fills
-        // the chip.)
+        // main: the second range's gradient chains, then (with the side
+        // stream's chains and the batch factor done) the probe / parameter
+        // reductions, which need every chain; the side stream meanwhile
+        // scatters the remaining rows.  (The reductions' probe transform
+        // needs whole compute units: issued first, on the stream that is
+        // already running, it gets them before the scatter fills the chip.)
         gradient_chains(c, a, nA, BM - nA, c->stream);
         if (hipEventRecord(c->ev_gdone, c->stream) != hipSuccess ||
-            hipStreamWaitEvent(c->side, c->ev_gdone, 0) != hipSuccess)
+            hipStreamWaitEvent(c->side, c->ev_gdone, 0) != hipSuccess ||
+            hipStreamWaitEvent(c->stream, c->ev_sgrad, 0) != hipSuccess)
             return PTYR_E_DEVICE;
         reductions(c->stream);
         scatter(rA, B, c->side, true);
