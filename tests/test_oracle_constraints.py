@@ -1,0 +1,175 @@
+"""Pins of the FP64 constraints oracle (r_z filter, positivity, probe-mode
+orthogonalisation) against a library routine, closed forms and invariants,
+and planted mistakes in it that those pins must catch."""
+import math
+
+import numpy as np
+import pytest
+from scipy.ndimage import gaussian_filter1d
+
+from oracle import constraints as oc
+
+
+def _vol(S=12, H=5, W=6, seed=0):
+    return np.random.default_rng(seed).standard_normal((S, H, W))
+
+
+# ------------------------------------------------------------ r_z filter
+@pytest.mark.parametrize("S,sigma", [(12, 0.6), (12, 1.0), (12, 1.3), (30, 2.5), (12, 7.0), (2, 1.0), (1, 1.5)])
+def test_rz_matches_library_gaussian_filter(S, sigma):
+    """scipy's gaussian_filter1d with mode='reflect' (mirror about the outer
+    sample faces) and the same radius is the same convolution, including
+    kernels wider than the stack (repeated mirroring)."""
+    v = _vol(S)
+    R = int(math.ceil(4 * sigma))
+    ref = gaussian_filter1d(v, sigma, axis=0, mode="reflect", radius=R)
+    assert np.max(np.abs(oc.rz_filter(v, sigma) - ref)) < 1e-13
+
+
+def test_rz_impulse_response_is_the_normalised_gaussian():
+    S, sigma = 41, 1.7
+    v = np.zeros((S, 1, 1))
+    v[20] = 1.0
+    out = oc.rz_filter(v, sigma)[:, 0, 0]
+    R = int(math.ceil(4 * sigma))
+    k = np.arange(-R, R + 1)
+    g = np.exp(-k ** 2 / (2 * sigma ** 2))
+    assert np.allclose(out[20 - R:20 + R + 1], g / g.sum(), atol=1e-15)
+    assert np.all(out[:20 - R] == 0) and np.all(out[20 + R + 1:] == 0)
+
+
+def test_rz_keeps_constants_and_mean_and_is_linear():
+    v, u = _vol(9, seed=1), _vol(9, seed=2)
+    assert np.allclose(oc.rz_filter(np.full((9, 2, 3), 2.5), 1.2), 2.5, atol=1e-14)
+    assert np.allclose(oc.rz_filter(2 * v - u, 0.9), 2 * oc.rz_filter(v, 0.9) - oc.rz_filter(u, 0.9), atol=1e-13)
+    # mirrored ends: the filter is doubly stochastic, so the depth mean is kept
+    assert np.allclose(oc.rz_filter(v, 1.1).mean(0), v.mean(0), atol=1e-13)
+
+
+def test_rz_does_not_mix_top_and_bottom():
+    """Unlike a periodic (Fourier) depth filter, a feature in the first slice
+    never reaches the last one when the stack is deeper than the kernel."""
+    v = np.zeros((20, 1, 1))
+    v[0] = 1.0
+    out = oc.rz_filter(v, 1.0)[:, 0, 0]
+    assert out[-1] == 0.0 and out[0] > 0.3
+    # and the first slice's weight comes back from the mirror: sum is kept
+    assert abs(out.sum() - 1.0) < 1e-14
+
+
+def test_rz_zero_sigma_is_identity():
+    v = _vol(5)
+    assert np.array_equal(oc.rz_filter(v, 0.0), v)
+
+
+def test_positivity_clips_only_negatives():
+    p = np.array([-1.0, -0.0, 0.0, 1e-9, 0.3])
+    assert np.array_equal(oc.positivity(p), [0.0, 0.0, 0.0, 1e-9, 0.3])
+
+
+# ------------------------------------------------------------ probe orthogonalisation
+def _probe(M=3, N=8, seed=3):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((M, N, N)) + 1j * rng.standard_normal((M, N, N))
+
+
+def test_orthogonalised_modes_are_orthogonal_power_ordered_and_keep_the_incoherent_sum():
+    P = _probe(4)
+    Q, lam = oc.probe_orthogonalize(P)
+    G = oc.probe_overlap(Q)
+    assert np.max(np.abs(G - np.diag(np.diag(G)))) < 1e-10 * np.max(np.abs(G))
+    assert np.allclose(np.diag(G).real, lam) and np.all(np.diff(lam) <= 0)
+    assert np.allclose((np.abs(Q) ** 2).sum(0), (np.abs(P) ** 2).sum(0), rtol=1e-12)
+    # the mutual intensity rho(r, r') = sum_k Q_k(r) conj(Q_k(r')) is the same
+    Pf, Qf = P.reshape(4, -1), Q.reshape(4, -1)
+    assert np.allclose(Qf.T @ np.conj(Qf), Pf.T @ np.conj(Pf), atol=1e-10)
+
+
+def test_two_mode_powers_match_the_closed_form():
+    """Eigenvalues of [[a, b], [conj b, d]]: (a+d)/2 +- sqrt(((a-d)/2)^2 + |b|^2)."""
+    P = _probe(2, seed=5)
+    a = np.vdot(P[0], P[0]).real
+    d = np.vdot(P[1], P[1]).real
+    b = np.vdot(P[0], P[1])
+    r = math.sqrt(((a - d) / 2) ** 2 + abs(b) ** 2)
+    _, lam = oc.probe_orthogonalize(P)
+    assert np.allclose(lam, [(a + d) / 2 + r, (a + d) / 2 - r], rtol=1e-12)
+
+
+def test_orthogonal_input_is_only_reordered():
+    """Modes that are already orthogonal with distinct powers come back
+    sorted by power, each up to a unit phase factor."""
+    N = 8
+    y, x = np.mgrid[0:N, 0:N] - (N - 1) / 2            # symmetric grid
+    g = np.exp(-(x ** 2 + y ** 2) / 8.0)
+    P = np.stack([0.5 * g, 2.0 * x * g, 1.0 * y * g]).astype(np.complex128)     # distinct parities
+    Q, lam = oc.probe_orthogonalize(P)
+    for k, m in enumerate([1, 2, 0]):                  # powers: x g (4x), y g, 0.5 g
+        c = np.vdot(P[m], Q[k]) / np.vdot(P[m], P[m])
+        assert abs(abs(c) - 1) < 1e-12
+        assert np.allclose(Q[k], c * P[m], atol=1e-12)
+
+
+def test_apply_order_blur_then_clip():
+    amp, ph = _vol(6, seed=7), _vol(6, seed=8)
+    P = _probe(2)
+    a2, p2, P2 = oc.apply(amp, ph, P, rz_sigma=1.0, phase_positive=True, probe_orthogonal=False)
+    assert np.array_equal(p2, np.maximum(oc.rz_filter(ph, 1.0), 0))
+    assert np.array_equal(a2, oc.rz_filter(amp, 1.0)) and np.array_equal(P2, P)
+
+
+# ------------------------------------------------------------ planted mistakes
+def _rz_pins():
+    for S, sigma in [(12, 1.0), (12, 7.0), (2, 1.0)]:
+        test_rz_matches_library_gaussian_filter(S, sigma)
+    test_rz_does_not_mix_top_and_bottom()
+    test_rz_keeps_constants_and_mean_and_is_linear()
+
+
+def _orth_pins():
+    test_orthogonalised_modes_are_orthogonal_power_ordered_and_keep_the_incoherent_sum()
+    test_two_mode_powers_match_the_closed_form()
+    test_orthogonal_input_is_only_reordered()
+
+
+MUTANTS = {
+    "periodic depth boundary": ("mirror_index", lambda i, S: i % S, _rz_pins),
+    "mirror about the outer sample instead of its face": (
+        "mirror_index", lambda i, S: 0 if S == 1 else (lambda j: j if j < S else 2 * S - 2 - j)(i % (2 * S - 2)),
+        _rz_pins),
+    "taps not normalised": (
+        "gaussian_taps",
+        lambda sigma, truncate=4.0: np.exp(-np.arange(-math.ceil(truncate * sigma), math.ceil(truncate * sigma) + 1)
+                                           ** 2 / (2.0 * sigma * sigma)) if sigma > 0 else np.ones(1),
+        _rz_pins),
+    "sigma used as variance": (
+        "gaussian_taps",
+        lambda sigma, truncate=4.0: (lambda w: w / w.sum())(
+            np.exp(-np.arange(-math.ceil(truncate * sigma), math.ceil(truncate * sigma) + 1) ** 2 / (2.0 * sigma)))
+        if sigma > 0 else np.ones(1),
+        _rz_pins),
+    "overlap not conjugated": (
+        "probe_overlap", lambda probe: (lambda P: P @ P.T)(np.asarray(probe).reshape(probe.shape[0], -1)), _orth_pins),
+}
+
+
+@pytest.mark.parametrize("name", list(MUTANTS))
+def test_planted_constraint_mistake_is_caught(name, monkeypatch):
+    attr, bad, pin = MUTANTS[name]
+    monkeypatch.setattr(oc, attr, bad)
+    with pytest.raises(AssertionError):
+        pin()
+
+
+def test_mixing_with_the_wrong_side_of_the_eigenvectors_is_caught(monkeypatch):
+    """Q = V^H P instead of V^T P (the conjugate mixing)."""
+    def bad(probe):
+        A = oc.probe_overlap(probe)
+        lam, V = np.linalg.eigh(A)
+        order = np.argsort(lam)[::-1]
+        lam, V = lam[order], V[:, order]
+        P = np.asarray(probe, np.complex128).reshape(probe.shape[0], -1)
+        return (np.conj(V).T @ P).reshape(probe.shape), lam
+    monkeypatch.setattr(oc, "probe_orthogonalize", bad)
+    with pytest.raises(AssertionError):
+        _orth_pins()
