@@ -200,6 +200,36 @@ ptyr_status ptyr_adjoint(ptyr_ctx* ctx, const float* amp, const float* phase,
 ptyr_status ptyr_step(ptyr_ctx* ctx, ptyr_params* p, const int* idx, int B,
                       const float* I_meas_all, const ptyr_lr* lr, double* loss_dev);
 
+/* Per-iteration constraints on the object and probe (Sec. "Physical
+ * constraints"), applied by ptyr_constrain after a gradient step, in this
+ * order:
+ *  rz_sigma > 0: the r_z filter (Sec. "Real-space depth regularization"): the
+ *    amplitude and the phase are each convolved along the slice axis with a
+ *    Gaussian of standard deviation rz_sigma slices, truncated at
+ *    |k| <= ceil(4 rz_sigma) and normalised to sum 1; the stack is mirrored
+ *    about its outer slice faces, so the first and last slices never mix.
+ *    0 < rz_sigma <= 16, S <= 256.
+ *  phase_positive: negative phase is set to 0 (Sec. "Positivity and
+ *    sparsity").
+ *  probe_orthogonal: the M probe modes are replaced by the eigenvectors of
+ *    their overlap matrix A[m][n] = sum_r conj(P_m(r)) P_n(r), in order of
+ *    decreasing power (after Thibault & Menzel 2013); each new mode's phase
+ *    factor makes its largest mixing coefficient real and positive.  The
+ *    incoherent sum of |P_m|^2, and so every model intensity, is unchanged.
+ *    M <= 24. */
+typedef struct {
+    float rz_sigma;           /* r_z filter width in slices; 0 = off */
+    int phase_positive;       /* clip negative object phase to 0 */
+    int probe_orthogonal;     /* orthogonalise the probe modes */
+} ptyr_constraints;
+
+/* Apply the constraints in place on the context's stream: amp, phase
+ * (S x H x W), probe (M x N x N complex); the pointer of a constraint that is
+ * off may be NULL.  PTYR_E_ARG for rz_sigma outside [0, 16], S > 256 with the
+ * r_z filter, M > 24 with probe_orthogonal, or a needed NULL pointer. */
+ptyr_status ptyr_constrain(ptyr_ctx* ctx, float* amp, float* phase, float* probe,
+                           const ptyr_constraints* cfg);
+
 /* Instrumentation (not part of the method): when enabled, the context brackets
  * each launch of its fused wave kernels with HIP events on its stream.
  * kernel ids: PTYR_K_FORWARD (the multislice forward kernel) and

@@ -91,7 +91,7 @@ def apply(amp, phase, probe, rz_sigma=0.0, phase_positive=False, probe_orthogona
     and phase), positivity, probe orthogonalisation."""
     amp = np.asarray(amp, np.float64)
     phase = np.asarray(phase, np.float64)
-    probe = np.asarray(probe, np.complex128)
+    probe = None if probe is None else np.asarray(probe, np.complex128)
     if rz_sigma > 0:
         amp = rz_filter(amp, rz_sigma)
         phase = rz_filter(phase, rz_sigma)

@@ -39,6 +39,10 @@ class LR(C.Structure):
                                          "beta1", "beta2", "eps")]
 
 
+class Constraints(C.Structure):
+    _fields_ = [("rz_sigma", C.c_float), ("phase_positive", C.c_int), ("probe_orthogonal", C.c_int)]
+
+
 class PtyrError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
@@ -73,6 +77,7 @@ def lib():
         "ptyr_adjoint": (st, [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, vp,
                               vp, vp, vp, vp, vp, vp, vp, C.c_uint]),
         "ptyr_step": (st, [vp, C.POINTER(Params), vp, C.c_int, vp, C.POINTER(LR), vp]),
+        "ptyr_constrain": (st, [vp, vp, vp, vp, C.POINTER(Constraints)]),
         "ptyr_timing_enable": (st, [vp, C.c_int]),
         "ptyr_timing_read": (st, [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
         # learned initial guess (include/ptyr_cnn.h)
@@ -101,7 +106,8 @@ def check(status, what):
 
 HEADER_SYMBOLS = ["ptyr_status_str", "ptyr_check_geom", "ptyr_check_args", "ptyr_workspace_bytes",
                   "ptyr_checkpoint_plan", "ptyr_create", "ptyr_destroy", "ptyr_sync", "ptyr_forward",
-                  "ptyr_loss", "ptyr_adjoint", "ptyr_step", "ptyr_timing_enable", "ptyr_timing_read"]
+                  "ptyr_loss", "ptyr_adjoint", "ptyr_step", "ptyr_constrain", "ptyr_timing_enable",
+                  "ptyr_timing_read"]
 
 CNN_HEADER_SYMBOLS = ["ptyr_cnn_param_count", "ptyr_cnn_workspace_bytes", "ptyr_cnn_create", "ptyr_cnn_destroy",
                       "ptyr_cnn_sync", "ptyr_cnn_forward", "ptyr_cnn_gradient", "ptyr_cnn_adam", "ptyr_cnn_stitch"]

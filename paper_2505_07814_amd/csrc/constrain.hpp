@@ -1,0 +1,219 @@
+// constrain.hpp - per-iteration constraints on the object and probe (the
+// paper's Sec. "Physical constraints"): the r_z depth filter with phase
+// positivity, and probe-mode orthogonalisation.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ptyr {
+
+constexpr int RZ_MAX_R = 64;        // largest tap radius (rz_sigma <= 16)
+constexpr int RZ_PIX = 64;          // pixels per workgroup of the depth filter
+constexpr int ORTH_MAX_M = 24;      // most probe modes the orthogonalisation takes
+constexpr int RZ_MAX_S = 256;       // deepest stack the depth filter takes (S * RZ_PIX floats of LDS)
+
+struct RzTaps {
+    float w[2 * RZ_MAX_R + 1];      // normalised taps w[k + R], k = -R..R
+    int R;
+};
+
+// index i of a stack of S slices extended by mirroring about its outer faces
+__device__ __forceinline__ int mirror_slice(int i, int S) {
+    if (S == 1) return 0;
+    const int period = 2 * S;
+    i %= period;
+    if (i < 0) i += period;
+    return i < S ? i : period - 1 - i;
+}
+
+// r_z filter of one field (S x HW, in place), then optionally max(., 0).
+// A workgroup owns RZ_PIX consecutive pixels for all S slices: it stages
+// their columns in LDS (coalesced rows of RZ_PIX floats), convolves along
+// depth and writes them back.  Dynamic LDS: S * RZ_PIX floats.
+__global__ __launch_bounds__(256) void k_rz_filter(float* v, int S, size_t HW, RzTaps taps, int positive) {
+    extern __shared__ float col[];                 // col[s * RZ_PIX + p]
+    const size_t p0 = (size_t)blockIdx.x * RZ_PIX;
+    const int p = threadIdx.x % RZ_PIX, q = threadIdx.x / RZ_PIX, nq = blockDim.x / RZ_PIX;
+    const bool in = p0 + p < HW;
+    for (int s = q; s < S; s += nq) col[s * RZ_PIX + p] = in ? v[(size_t)s * HW + p0 + p] : 0.f;
+    __syncthreads();
+    if (!in) return;
+    const int R = taps.R;
+    for (int s = q; s < S; s += nq) {
+        float acc = 0.f;
+        for (int k = -R; k <= R; ++k) acc = fmaf(taps.w[k + R], col[mirror_slice(s + k, S) * RZ_PIX + p], acc);
+        v[(size_t)s * HW + p0 + p] = positive ? fmaxf(acc, 0.f) : acc;
+    }
+}
+
+// phase positivity alone (elementwise)
+__global__ void k_clip_negative(float* v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        v[i] = fmaxf(v[i], 0.f);
+}
+
+// ------------------------------------------------------------ probe modes
+struct cd {
+    double re, im;
+};
+__device__ __forceinline__ cd cd_mul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd cd_conj(cd a) { return {a.re, -a.im}; }
+__device__ __forceinline__ cd cd_add(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd cd_scale(cd a, double s) { return {a.re * s, a.im * s}; }
+
+// Overlap matrix A[m][n] = sum_r conj(P_m(r)) P_n(r), one workgroup per pair
+// m <= n, summed in double in a fixed order; A is M x M row-major.
+__global__ __launch_bounds__(256) void k_probe_gram(const float2* P, int M, int NN, cd* A) {
+    int pair = blockIdx.x, m = 0;
+    while (pair >= M - m) { pair -= M - m; ++m; }
+    const int n = m + pair;
+    const float2* a = P + (size_t)m * NN;
+    const float2* b = P + (size_t)n * NN;
+    double re = 0.0, im = 0.0;
+    for (int r = threadIdx.x; r < NN; r += blockDim.x) {
+        const float2 x = a[r], y = b[r];
+        re += (double)x.x * y.x + (double)x.y * y.y;       // conj(x) y
+        im += (double)x.x * y.y - (double)x.y * y.x;
+    }
+    __shared__ double sr[256], si[256];
+    sr[threadIdx.x] = re;
+    si[threadIdx.x] = im;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sr[threadIdx.x] += sr[threadIdx.x + o];
+            si[threadIdx.x] += si[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        A[m * M + n] = {sr[0], m == n ? 0.0 : si[0]};
+        A[n * M + m] = {sr[0], m == n ? 0.0 : -si[0]};
+    }
+}
+
+// Eigenvectors of the Hermitian overlap matrix by cyclic complex Jacobi
+// rotations in double (one workgroup, thread k owning row / column k), then
+// ordered by decreasing eigenvalue; each eigenvector is scaled by a unit
+// phase so that its largest-magnitude entry (first of equals) is real and
+// positive.  Writes V (M x M, column k = mode k's mixing coefficients) as
+// float pairs and the eigenvalues.
+__global__ __launch_bounds__(64) void k_probe_eig(const cd* Ain, int M, float2* Vout, double* lam_out) {
+    __shared__ cd A[ORTH_MAX_M * ORTH_MAX_M], V[ORTH_MAX_M * ORTH_MAX_M];
+    __shared__ double lam[ORTH_MAX_M];
+    __shared__ int order[ORTH_MAX_M];
+    __shared__ double off;
+    const int k = threadIdx.x;
+    for (int i = k; i < M * M; i += blockDim.x) {
+        A[i] = Ain[i];
+        V[i] = {(i / M) == (i % M) ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    double scale = 0.0;
+    for (int i = 0; i < M; ++i) scale += A[i * M + i].re;
+    const double tol = 1e-28 * scale * scale;     // off-diagonal norm 1e-14 of the trace
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        if (k == 0) {
+            double s = 0.0;
+            for (int i = 0; i < M; ++i)
+                for (int j = 0; j < M; ++j)
+                    if (i != j) s += A[i * M + j].re * A[i * M + j].re + A[i * M + j].im * A[i * M + j].im;
+            off = s;
+        }
+        __syncthreads();
+        if (off <= tol) break;
+        for (int p = 0; p < M - 1; ++p)
+            for (int q = p + 1; q < M; ++q) {
+                const cd apq = A[p * M + q];
+                const double mag = sqrt(apq.re * apq.re + apq.im * apq.im);
+                if (mag == 0.0) continue;                       // uniform: every thread reads the same value
+                // U = D P: D_qq = exp(-i alpha) makes the (p, q) entry real
+                // (alpha = arg a_pq), P the real Jacobi rotation that zeroes it
+                const cd e = {apq.re / mag, -apq.im / mag};     // exp(-i alpha)
+                const double zeta = (A[q * M + q].re - A[p * M + p].re) / (2.0 * mag);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(zeta * zeta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                __syncthreads();
+                // columns p, q of A U and of V U (thread k: row k)
+                if (k < M) {
+                    const cd akp = A[k * M + p], akq = cd_mul(A[k * M + q], e);
+                    A[k * M + p] = {c * akp.re - s * akq.re, c * akp.im - s * akq.im};
+                    A[k * M + q] = {s * akp.re + c * akq.re, s * akp.im + c * akq.im};
+                    const cd vkp = V[k * M + p], vkq = cd_mul(V[k * M + q], e);
+                    V[k * M + p] = {c * vkp.re - s * vkq.re, c * vkp.im - s * vkq.im};
+                    V[k * M + q] = {s * vkp.re + c * vkq.re, s * vkp.im + c * vkq.im};
+                }
+                __syncthreads();
+                // rows p, q of U^H (A U) (thread k: column k)
+                if (k < M) {
+                    const cd bpk = A[p * M + k], bqk = cd_mul(A[q * M + k], cd_conj(e));
+                    A[p * M + k] = {c * bpk.re - s * bqk.re, c * bpk.im - s * bqk.im};
+                    A[q * M + k] = {s * bpk.re + c * bqk.re, s * bpk.im + c * bqk.im};
+                }
+                __syncthreads();
+                if (k == 0) {
+                    A[p * M + q] = {0.0, 0.0};
+                    A[q * M + p] = {0.0, 0.0};
+                    A[p * M + p].im = 0.0;
+                    A[q * M + q].im = 0.0;
+                }
+                __syncthreads();
+            }
+    }
+    if (k == 0) {
+        for (int i = 0; i < M; ++i) {
+            lam[i] = A[i * M + i].re;
+            order[i] = i;
+        }
+        for (int i = 0; i < M; ++i)                       // selection sort, decreasing; stable for ties
+            for (int j = i + 1; j < M; ++j)
+                if (lam[order[j]] > lam[order[i]]) {
+                    const int tmp = order[i];
+                    order[i] = order[j];
+                    order[j] = tmp;
+                }
+    }
+    __syncthreads();
+    if (k < M) {                                          // thread k: output column k
+        const int src = order[k];
+        int best = 0;
+        double bm = -1.0;
+        for (int m = 0; m < M; ++m) {
+            const cd x = V[m * M + src];
+            const double a = x.re * x.re + x.im * x.im;
+            if (a > bm) { bm = a; best = m; }
+        }
+        const cd x = V[best * M + src];
+        const double r = sqrt(x.re * x.re + x.im * x.im);
+        const cd ph = r > 0 ? cd{x.re / r, -x.im / r} : cd{1.0, 0.0};
+        for (int m = 0; m < M; ++m) {
+            const cd y = cd_mul(V[m * M + src], ph);
+            Vout[m * M + k] = make_float2((float)y.re, (float)y.im);
+        }
+        lam_out[k] = lam[src];
+    }
+}
+
+// Q_k(r) = sum_m V[m][k] P_m(r), in place: a workgroup stages the M values of
+// its 256 pixels in LDS before writing.  Dynamic LDS: M * 256 float2 + M^2 float2.
+__global__ __launch_bounds__(256) void k_probe_mix(float2* P, int M, int NN, const float2* V) {
+    extern __shared__ float2 sm[];
+    float2* vals = sm;                        // vals[m * 256 + t]
+    float2* Vs = sm + (size_t)M * 256;
+    const int t = threadIdx.x;
+    const int r = blockIdx.x * 256 + t;
+    for (int i = t; i < M * M; i += 256) Vs[i] = V[i];
+    for (int m = 0; m < M; ++m) vals[m * 256 + t] = r < NN ? P[(size_t)m * NN + r] : make_float2(0.f, 0.f);
+    __syncthreads();
+    if (r >= NN) return;
+    for (int kk = 0; kk < M; ++kk) {
+        float re = 0.f, im = 0.f;
+        for (int m = 0; m < M; ++m) {
+            const float2 v = Vs[m * M + kk], p = vals[m * 256 + t];
+            re = fmaf(v.x, p.x, fmaf(-v.y, p.y, re));
+            im = fmaf(v.x, p.y, fmaf(v.y, p.x, im));
+        }
+        P[(size_t)kk * NN + r] = make_float2(re, im);
+    }
+}
+
+}  // namespace ptyr

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/ptyr.h"
+#include "constrain.hpp"
 #include "kernels.hpp"
 #include "lines256.hpp"
 
@@ -454,7 +455,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, err, store, gO, gPhat, gPsum, part, gamp, gphase,
-        gprobe, gdz, gpos, gtilt, wave, total;
+        gprobe, gdz, gpos, gtilt, wave, cons, total;
     int keep, ckK, nck, waves_per_chain;
 };
 
@@ -509,6 +510,9 @@ Layout make_layout(const ptyr_geom* g) {
     L.gpos = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
     L.gtilt = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
     L.wave = take(g->N == 256 ? B * M * NN * sizeof(float2) : 0);
+    // probe orthogonalisation: overlap matrix (double complex), mixing
+    // matrix (float complex), eigenvalues
+    L.cons = take((size_t)ORTH_MAX_M * ORTH_MAX_M * (sizeof(cd) + sizeof(float2)) + ORTH_MAX_M * sizeof(double));
     L.total = o;
     return L;
 }
@@ -1073,6 +1077,48 @@ ptyr_status ptyr_adjoint(ptyr_ctx* c, const float* amp, const float* phase, cons
     if (idx && n_rows < 1) return PTYR_E_ARG;
     return run_adjoint(c, amp, phase, probe, pos, tilt, dz, idx, n_rows, B, I_meas, g_amp, g_phase, g_probe, g_pos,
                        g_tilt, g_dz, loss_dev, flags);
+}
+
+ptyr_status ptyr_constrain(ptyr_ctx* c, float* amp, float* phase, float* probe, const ptyr_constraints* cfg) {
+    if (!c || !cfg) return PTYR_E_ARG;
+    const ptyr_geom& g = c->g;
+    const bool rz = cfg->rz_sigma > 0.f;
+    if (!(cfg->rz_sigma >= 0.f && cfg->rz_sigma <= 16.f)) return PTYR_E_ARG;
+    if (rz && (!amp || !phase || g.S > RZ_MAX_S)) return PTYR_E_ARG;
+    if (cfg->phase_positive && !phase) return PTYR_E_ARG;
+    if (cfg->probe_orthogonal && (!probe || g.M > ORTH_MAX_M)) return PTYR_E_ARG;
+    const hipStream_t st = c->stream;
+    const size_t HW = (size_t)g.H * g.W;
+    if (rz && g.S > 1) {
+        // taps in double, normalised, then rounded (the same on every call)
+        RzTaps t;
+        t.R = (int)ceil(4.0 * (double)cfg->rz_sigma);
+        double w[2 * RZ_MAX_R + 1], sum = 0.0;
+        for (int k = -t.R; k <= t.R; ++k) {
+            w[k + t.R] = exp(-(double)k * k / (2.0 * (double)cfg->rz_sigma * cfg->rz_sigma));
+            sum += w[k + t.R];
+        }
+        for (int k = 0; k <= 2 * t.R; ++k) t.w[k] = (float)(w[k] / sum);
+        const dim3 grid((unsigned)((HW + RZ_PIX - 1) / RZ_PIX));
+        const size_t lds = (size_t)g.S * RZ_PIX * sizeof(float);
+        hipLaunchKernelGGL(k_rz_filter, grid, dim3(256), lds, st, amp, g.S, HW, t, 0);
+        hipLaunchKernelGGL(k_rz_filter, grid, dim3(256), lds, st, phase, g.S, HW, t, cfg->phase_positive ? 1 : 0);
+    } else if (cfg->phase_positive) {
+        hipLaunchKernelGGL(k_clip_negative, dim3(grid_for((size_t)g.S * HW)), dim3(256), 0, st, phase,
+                           (size_t)g.S * HW);
+    }
+    if (cfg->probe_orthogonal && g.M > 1) {
+        const int M = g.M, NN = g.N * g.N;
+        cd* A = at<cd>(c, c->L.cons);
+        float2* V = reinterpret_cast<float2*>(A + ORTH_MAX_M * ORTH_MAX_M);
+        double* lam = reinterpret_cast<double*>(V + ORTH_MAX_M * ORTH_MAX_M);
+        float2* P = reinterpret_cast<float2*>(probe);
+        hipLaunchKernelGGL(k_probe_gram, dim3(M * (M + 1) / 2), dim3(256), 0, st, P, M, NN, A);
+        hipLaunchKernelGGL(k_probe_eig, dim3(1), dim3(64), 0, st, A, M, V, lam);
+        const size_t lds = ((size_t)M * 256 + (size_t)M * M) * sizeof(float2);
+        hipLaunchKernelGGL(k_probe_mix, dim3((NN + 255) / 256), dim3(256), lds, st, P, M, NN, V);
+    }
+    return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
 
 ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const float* I_meas_all,

@@ -142,3 +142,11 @@ def test_cnn_workspace_and_create_errors():
     assert lib.ptyr_cnn_create(4, C.c_void_p(256), 1 << 30, None, None) == L.PTYR_E_ARG
     assert lib.ptyr_cnn_forward(None, None, None, 1, None, 1, None) == L.PTYR_E_ARG
     assert lib.ptyr_cnn_sync(None) == L.PTYR_E_ARG
+
+
+def test_constrain_rejects_a_null_context():
+    from paper_2505_07814_amd import _lib as L
+    import ctypes as C
+    cfg = L.Constraints(1.0, 1, 0)
+    assert L.lib().ptyr_constrain(None, None, None, None, C.byref(cfg)) == L.PTYR_E_ARG
+    assert L.lib().ptyr_constrain(None, None, None, None, None) == L.PTYR_E_ARG

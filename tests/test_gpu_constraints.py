@@ -1,0 +1,172 @@
+"""Parity of ptyr_constrain (r_z depth filter, phase positivity, probe-mode
+orthogonalisation) with the FP64 constraints oracle.
+
+Bars (derived from the arithmetic): the depth filter is a convex combination
+of 2R+1 float values with float taps (each rounded to 2^-24 relative) summed
+in float, so each output is within (2R+2) 2^-24 max|v| of the exact value;
+clipping is exact.  The orthogonalised modes are sums of M float products of
+a double-precision eigenvector with the float input (relative error ~M 2^-24)
+and the eigenvectors of well-separated powers are stable, so each mode must
+match the oracle's to relative L2 <= 1e-5 up to its (arbitrary) unit phase.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import constraints as oc
+from paper_2505_07814_amd import _lib as L
+from paper_2505_07814_amd.ptyr import Engine
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def T(a, dt=None):
+    a = np.ascontiguousarray(a if dt is None else np.asarray(a).astype(dt))
+    return torch.from_numpy(a).to(DEV)
+
+
+def engine(S, H, W, N=64, M=1):
+    return Engine(N, M, S, H, W, 1, 0.2, 0.02, device=DEV)
+
+
+def rz_bound(sigma, v):
+    R = int(math.ceil(4 * sigma))
+    return (2 * R + 2) * 2.0 ** -24 * float(np.max(np.abs(v)))
+
+
+@pytest.mark.parametrize("S,sigma", [(12, 0.6), (12, 1.0), (30, 2.5), (12, 7.0), (2, 1.0), (1, 1.5)])
+def test_rz_filter_matches_oracle(S, sigma):
+    print(f"rz filter S={S} sigma={sigma}", flush=True)
+    H, W = 70, 67                                   # HW not a multiple of the 64-pixel workgroup
+    rng = np.random.default_rng(S * 100 + int(10 * sigma))
+    amp = rng.uniform(0.5, 1.5, (S, H, W)).astype(np.float32)
+    ph = rng.uniform(-0.5, 1.0, (S, H, W)).astype(np.float32)
+    eng = engine(S, H, W)
+    a, p = T(amp), T(ph)
+    eng.constrain(a, p, rz_sigma=sigma, phase_positive=True)
+    eng.sync()
+    ra, rp, _ = oc.apply(amp, ph, None, rz_sigma=sigma, phase_positive=True)
+    ea = np.max(np.abs(a.cpu().numpy() - ra))
+    ep = np.max(np.abs(p.cpu().numpy() - rp))
+    print(f"max |err| amp {ea:.2e} phase {ep:.2e} (bound {rz_bound(sigma, amp):.2e})", flush=True)
+    assert ea <= rz_bound(sigma, amp) and ep <= rz_bound(sigma, ph)
+    got = p.cpu().numpy()
+    assert np.all(got >= 0)
+    # clipping decides exactly where the filtered value is clearly negative
+    assert np.all(got[rp == 0] <= rz_bound(sigma, ph))
+
+
+def test_clip_alone_is_exact():
+    rng = np.random.default_rng(3)
+    ph = rng.standard_normal((3, 70, 75)).astype(np.float32)
+    eng = engine(3, 70, 75)
+    p = T(ph)
+    eng.constrain(phase=p, phase_positive=True)
+    eng.sync()
+    assert np.array_equal(p.cpu().numpy(), np.maximum(ph, 0))
+
+
+def test_rz_filter_full_object_sampled():
+    """The 12 x 640 x 640 object of the N=128 workload: 4000 sampled pixel
+    columns against the oracle, and the depth mean of every column kept (the
+    mirrored filter is doubly stochastic)."""
+    S, H = 12, 640
+    rng = np.random.default_rng(11)
+    ph = rng.uniform(-0.2, 1.0, (S, H, H)).astype(np.float32)
+    eng = engine(S, H, H, N=128, M=1)
+    p = T(ph)
+    eng.constrain(phase=p, amp=T(np.ones((S, H, H), np.float32)), rz_sigma=1.0)
+    eng.sync()
+    got = p.cpu().numpy()
+    idx = rng.integers(0, H * H, 4000)
+    cols = ph.reshape(S, -1)[:, idx]
+    ref = oc.rz_filter(cols[:, :, None], 1.0)[:, :, 0]
+    assert np.max(np.abs(got.reshape(S, -1)[:, idx] - ref)) <= rz_bound(1.0, ph)
+    assert np.max(np.abs(got.mean(0) - ph.mean(0))) < 1e-6
+
+
+def _modes(M, N, seed, powers):
+    rng = np.random.default_rng(seed)
+    P = rng.standard_normal((M, N, N)) + 1j * rng.standard_normal((M, N, N))
+    P *= np.sqrt(np.asarray(powers))[:, None, None] / np.sqrt(N * N * 2)
+    return P.astype(np.complex64)
+
+
+@pytest.mark.parametrize("M,N", [(2, 64), (6, 128), (12, 64), (24, 64)])
+def test_probe_orthogonalisation_matches_oracle(M, N):
+    print(f"probe orthogonalisation M={M} N={N}", flush=True)
+    powers = 1.0 + 0.3 * np.arange(M)[::-1]          # well separated (overlaps mix them a little)
+    P = _modes(M, N, 20 + M, powers)
+    eng = Engine(N, M, 1, N, N, 1, 0.2, 0.02, device=DEV)
+    pr = T(P)
+    eng.constrain(probe=pr, probe_orthogonal=True)
+    eng.sync()
+    Q = pr.cpu().numpy().astype(np.complex128)
+    Qr, lam = oc.probe_orthogonalize(P.astype(np.complex128))
+    for k in range(M):
+        c = np.vdot(Qr[k], Q[k]) / np.vdot(Qr[k], Qr[k])
+        err = np.linalg.norm(Q[k] - c * Qr[k]) / np.linalg.norm(Qr[k])
+        assert abs(abs(c) - 1) < 1e-5 and err < 1e-5, (k, abs(c), err)
+    G = oc.probe_overlap(Q)
+    assert np.max(np.abs(G - np.diag(np.diag(G)))) < 1e-5 * lam[0]
+    assert np.allclose(np.diag(G).real, lam, rtol=1e-5)
+    inc0 = (np.abs(P.astype(np.complex128)) ** 2).sum(0)
+    assert np.linalg.norm((np.abs(Q) ** 2).sum(0) - inc0) < 1e-5 * np.linalg.norm(inc0)
+
+
+def test_orthogonalisation_keeps_model_intensities():
+    """The incoherent mode sum is invariant, so the forward model gives the
+    same patterns with the orthogonalised probe."""
+    from paper_2505_07814_amd import synth
+    w = synth.small_case(N=64, S=2, M=3, B=3, H=64 + 30, W=64 + 30, seed=41)
+    eng = Engine(64, 3, 2, w.H, w.W, 3, w.dx, synth.wavelength_A(w.kv), device=DEV)
+    args = [T(w.amp, np.float32), T(w.phase, np.float32), T(w.probe, np.complex64), T(w.pos, np.float32),
+            T(w.tilt, np.float32), T(np.array([w.dz], np.float32))]
+    I0 = eng.forward(*args).clone()
+    eng.constrain(probe=args[2], probe_orthogonal=True)
+    I1 = eng.forward(*args)
+    eng.sync()
+    a, b = I1.cpu().numpy(), I0.cpu().numpy()
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-5
+
+
+def test_single_mode_and_degenerate_modes():
+    eng = Engine(64, 1, 1, 64, 64, 1, 0.2, 0.02, device=DEV)
+    P = _modes(1, 64, 5, [1.0])
+    pr = T(P)
+    eng.constrain(probe=pr, probe_orthogonal=True)          # one mode: nothing to do
+    eng.sync()
+    assert np.array_equal(pr.cpu().numpy(), P)
+    # two orthogonal modes of equal power: any unitary mix is a valid answer;
+    # what is unique (orthogonality, powers, incoherent sum) must hold
+    N = 64
+    y, x = np.mgrid[0:N, 0:N] - (N - 1) / 2
+    g = np.exp(-(x ** 2 + y ** 2) / 50.0)
+    a, b = x * g, y * g
+    P2 = np.stack([a / np.linalg.norm(a), b / np.linalg.norm(b)]).astype(np.complex64)
+    eng2 = Engine(64, 2, 1, 64, 64, 1, 0.2, 0.02, device=DEV)
+    pr2 = T(P2)
+    eng2.constrain(probe=pr2, probe_orthogonal=True)
+    eng2.sync()
+    Q = pr2.cpu().numpy().astype(np.complex128)
+    G = oc.probe_overlap(Q)
+    assert abs(G[0, 1]) < 1e-6 and np.allclose(np.diag(G).real, [1, 1], atol=1e-6)
+    assert np.allclose((np.abs(Q) ** 2).sum(0), (np.abs(P2.astype(np.complex128)) ** 2).sum(0), atol=1e-7)
+
+
+def test_bad_arguments_are_rejected():
+    eng = engine(3, 70, 70)
+    a = torch.ones((3, 70, 70), device=DEV)
+    for kw in (dict(rz_sigma=-1.0), dict(rz_sigma=17.0)):
+        with pytest.raises(L.PtyrError) as e:
+            eng.constrain(a, a.clone(), **kw)
+        assert e.value.status == L.PTYR_E_ARG
+    with pytest.raises(L.PtyrError):
+        eng.constrain(phase=a, rz_sigma=1.0)             # amplitude missing
+    big = Engine(64, 25, 1, 64, 64, 1, 0.2, 0.02, device=DEV)
+    with pytest.raises(L.PtyrError):
+        big.constrain(probe=torch.zeros((25, 64, 64), dtype=torch.complex64, device=DEV), probe_orthogonal=True)
