@@ -214,6 +214,72 @@ def sweep_bench(args):
                       "unit": "patterns/s", "n_gpus": 1, "data": "synthetic (timing only)", "rows": rows}), flush=True)
 
 
+def constraints_bench(args):
+    """Per-iteration constraints (ptyr_constrain) on the N=128 workload's
+    object and probe: r_z depth filter (sigma = 1 slice) of amplitude and
+    phase, phase positivity, orthogonalisation of the six probe modes.  The
+    dominant kernel is the depth filter, bound by HBM: each launch reads and
+    writes one 12 x 640 x 640 float field."""
+    import numpy as np
+    import torch
+
+    from paper_2505_07814_amd import synth
+    from paper_2505_07814_amd.ptyr import Engine
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.workload("multislice_128", scan=64)
+    lam = synth.wavelength_A(w.kv)
+    T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a.astype(dt))).to(dev)
+    amp, ph = T(w.amp, np.float32), T(w.phase - 0.05, np.float32)
+    probe = T(w.probe, np.complex64)
+    eng = Engine(w.N, w.M, w.S, w.H, w.W, 1, w.dx, lam, device=dev)
+    cfg = dict(rz_sigma=1.0, phase_positive=True, probe_orthogonal=True)
+    for _ in range(args.warmup):
+        eng.constrain(amp, ph, probe, **cfg)
+    eng.sync()
+    eng.timing(True)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        eng.constrain(amp, ph, probe, **cfg)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_call = e0.elapsed_time(e1) / args.steps
+    kt = eng.timing_read()
+    eng.timing(False)
+    rz_ms, rz_n = kt["rz"]
+    field_bytes = 2 * w.S * w.H * w.W * 4                 # one field read and written
+    achieved = field_bytes * rz_n / (rz_ms * 1e-3) / 1e9
+    out = {"metric": "ptyr_constrain calls/s (N=128 workload: 12 x 640 x 640 object, 6 probe modes)",
+           "value": round(1e3 / ms_call, 1), "unit": "calls/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_call": round(ms_call, 4), "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "constraints on multislice_128: r_z filter sigma 1 slice on amplitude and phase, "
+                                  "phase positivity, orthogonalisation of 6 probe modes of 128 x 128"},
+           "roofline": {"bound": "hbm", "kernel": "k_rz_filter", "achieved": round(achieved, 1),
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                        "traffic": None, "launch_ms": round(rz_ms / rz_n, 4), "bytes_per_launch": field_bytes}}
+    if not args.no_cpu_baseline:
+        from oracle import constraints as oc
+        t0 = time.perf_counter()
+        oc.apply(w.amp, w.phase, w.probe, **cfg)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 3), "unit": "calls/s", "cores": 1, "kind": "oracle",
+                               "sample": "one call on the full object and probe (numpy, float64)"}
+    out["roofline"]["traffic"] = read_traffic("rz", "constraints_128")
+    if args.copy_calibration:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)     # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +297,8 @@ def main():
     ap.add_argument("--objects", type=int, default=3125, help="training objects for --learned-init (64 pairs each)")
     ap.add_argument("--epochs", type=int, default=16, help="training epochs for --learned-init")
     ap.add_argument("--iterations", type=int, default=60, help="reconstruction iterations for --learned-init")
+    ap.add_argument("--constraints", action="store_true",
+                    help="time ptyr_constrain (r_z filter, positivity, probe orthogonalisation) on the N=128 workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy a 512 MiB buffer 4 times (known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -242,6 +310,8 @@ def main():
         return learned_init_bench(args)
     if args.sweep:
         return sweep_bench(args)
+    if args.constraints:
+        return constraints_bench(args)
 
     import numpy as np
     import torch

@@ -112,4 +112,4 @@ HEADER_SYMBOLS = ["ptyr_status_str", "ptyr_check_geom", "ptyr_check_args", "ptyr
 CNN_HEADER_SYMBOLS = ["ptyr_cnn_param_count", "ptyr_cnn_workspace_bytes", "ptyr_cnn_create", "ptyr_cnn_destroy",
                       "ptyr_cnn_sync", "ptyr_cnn_forward", "ptyr_cnn_gradient", "ptyr_cnn_adam", "ptyr_cnn_stitch"]
 
-PTYR_K_FORWARD, PTYR_K_GRADIENT = 0, 1
+PTYR_K_FORWARD, PTYR_K_GRADIENT, PTYR_K_RZ = 0, 1, 2

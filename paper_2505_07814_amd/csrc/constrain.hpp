@@ -7,9 +7,10 @@
 namespace ptyr {
 
 constexpr int RZ_MAX_R = 64;        // largest tap radius (rz_sigma <= 16)
-constexpr int RZ_PIX = 64;          // pixels per workgroup of the depth filter
 constexpr int ORTH_MAX_M = 24;      // most probe modes the orthogonalisation takes
-constexpr int RZ_MAX_S = 256;       // deepest stack the depth filter takes (S * RZ_PIX floats of LDS)
+constexpr int RZ_MAX_S = 256;       // deepest stack the depth filter takes
+constexpr int GRAM_CHUNK = 1024;    // pixels per partial overlap sum
+constexpr int GRAM_MAX_CHUNKS = 64; // N = 256: 65536 / 1024
 
 struct RzTaps {
     float w[2 * RZ_MAX_R + 1];      // normalised taps w[k + R], k = -R..R
@@ -18,6 +19,9 @@ struct RzTaps {
 
 // index i of a stack of S slices extended by mirroring about its outer faces
 __device__ __forceinline__ int mirror_slice(int i, int S) {
+    if (i >= 0 && i < S) return i;                       // inside, or one reflection (taps within S)
+    if (i < 0 && i >= -S) return -1 - i;
+    if (i >= S && i < 2 * S) return 2 * S - 1 - i;
     if (S == 1) return 0;
     const int period = 2 * S;
     i %= period;
@@ -26,24 +30,98 @@ __device__ __forceinline__ int mirror_slice(int i, int S) {
 }
 
 // r_z filter of one field (S x HW, in place), then optionally max(., 0).
-// A workgroup owns RZ_PIX consecutive pixels for all S slices: it stages
-// their columns in LDS (coalesced rows of RZ_PIX floats), convolves along
-// depth and writes them back.  Dynamic LDS: S * RZ_PIX floats.
+// A thread owns one pixel's column: it reads the S values (consecutive
+// threads take consecutive pixels, so each slice is one coalesced row per
+// wave) into its own LDS column, which serves as an indexable array, and
+// writes the filtered column back.  A thread touches only its own column,
+// so no barrier is needed.  Dynamic LDS: S * blockDim.x floats.
 __global__ __launch_bounds__(256) void k_rz_filter(float* v, int S, size_t HW, RzTaps taps, int positive) {
-    extern __shared__ float col[];                 // col[s * RZ_PIX + p]
-    const size_t p0 = (size_t)blockIdx.x * RZ_PIX;
-    const int p = threadIdx.x % RZ_PIX, q = threadIdx.x / RZ_PIX, nq = blockDim.x / RZ_PIX;
-    const bool in = p0 + p < HW;
-    for (int s = q; s < S; s += nq) col[s * RZ_PIX + p] = in ? v[(size_t)s * HW + p0 + p] : 0.f;
-    __syncthreads();
-    if (!in) return;
+    extern __shared__ float col[];
+    const int T = blockDim.x;
+    const size_t px = (size_t)blockIdx.x * T + threadIdx.x;
+    if (px >= HW) return;
+    float* c = col + threadIdx.x;
+    int s = 0;
+    for (; s + 4 <= S; s += 4) {               // four reads in flight per thread
+        float x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = v[(size_t)(s + u) * HW + px];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[(s + u) * T] = x[u];
+    }
+    for (; s < S; ++s) c[s * T] = v[(size_t)s * HW + px];
     const int R = taps.R;
-    for (int s = q; s < S; s += nq) {
+    for (s = 0; s < S; ++s) {
         float acc = 0.f;
-        for (int k = -R; k <= R; ++k) acc = fmaf(taps.w[k + R], col[mirror_slice(s + k, S) * RZ_PIX + p], acc);
-        v[(size_t)s * HW + p0 + p] = positive ? fmaxf(acc, 0.f) : acc;
+        for (int k = -R; k <= R; ++k) acc = fmaf(taps.w[k + R], c[mirror_slice(s + k, S) * T], acc);
+        v[(size_t)s * HW + px] = positive ? fmaxf(acc, 0.f) : acc;
     }
 }
+
+// The depth filter as an S x S matrix: B[s][s'] = sum of the taps w_k with
+// mirror(s + k) = s' (the mirrored boundary folded in).  One thread per entry.
+__global__ void k_rz_matrix(RzTaps taps, int S, float* Bm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S * S) return;
+    const int s = i / S, s2 = i % S;
+    float b = 0.f;
+    for (int k = -taps.R; k <= taps.R; ++k)
+        if (mirror_slice(s + k, S) == s2) b += taps.w[k + taps.R];
+    Bm[i] = b;
+}
+
+// r_z filter for S <= RZ_REG_S: a thread keeps its pixel's column in
+// registers and forms out = B x with the matrix read through the scalar
+// cache (every thread of the launch reads the same entries).
+constexpr int RZ_REG_S = 32;
+__global__ __launch_bounds__(256) void k_rz_filter_reg(float* v, int S, size_t HW, const float* __restrict__ Bm,
+                                                       int positive) {
+    const size_t px = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (px >= HW) return;
+    float x[RZ_REG_S];
+#pragma unroll
+    for (int s = 0; s < RZ_REG_S; ++s) x[s] = s < S ? v[(size_t)s * HW + px] : 0.f;
+#pragma unroll
+    for (int s = 0; s < RZ_REG_S; ++s) {
+        if (s >= S) break;
+        float acc = 0.f;
+#pragma unroll
+        for (int s2 = 0; s2 < RZ_REG_S; ++s2)
+            if (s2 < S) acc = fmaf(Bm[s * S + s2], x[s2], acc);
+        v[(size_t)s * HW + px] = positive ? fmaxf(acc, 0.f) : acc;
+    }
+}
+
+// The same for fields whose slice size is a multiple of 4: a thread owns four
+// consecutive pixels (16-byte reads and writes).
+__global__ __launch_bounds__(256) void k_rz_filter_reg4(float* v, int S, size_t HW, const float* __restrict__ Bm,
+                                                        int positive) {
+    const size_t px = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (px >= HW) return;
+    float4 x[RZ_REG_S];
+#pragma unroll
+    for (int s = 0; s < RZ_REG_S; ++s)
+        x[s] = s < S ? *reinterpret_cast<const float4*>(v + (size_t)s * HW + px) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int s = 0; s < RZ_REG_S; ++s) {
+        if (s >= S) break;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int s2 = 0; s2 < RZ_REG_S; ++s2)
+            if (s2 < S) {
+                const float b = Bm[s * S + s2];
+                acc.x = fmaf(b, x[s2].x, acc.x);
+                acc.y = fmaf(b, x[s2].y, acc.y);
+                acc.z = fmaf(b, x[s2].z, acc.z);
+                acc.w = fmaf(b, x[s2].w, acc.w);
+            }
+        if (positive) acc = make_float4(fmaxf(acc.x, 0.f), fmaxf(acc.y, 0.f), fmaxf(acc.z, 0.f), fmaxf(acc.w, 0.f));
+        *reinterpret_cast<float4*>(v + (size_t)s * HW + px) = acc;
+    }
+}
+
+// threads per workgroup of the depth filter for S slices (LDS <= 64 KiB)
+inline int rz_threads(int S) { return S <= 64 ? 256 : (S <= 128 ? 128 : 64); }
 
 // phase positivity alone (elementwise)
 __global__ void k_clip_negative(float* v, size_t n) {
@@ -60,16 +138,20 @@ __device__ __forceinline__ cd cd_conj(cd a) { return {a.re, -a.im}; }
 __device__ __forceinline__ cd cd_add(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cd cd_scale(cd a, double s) { return {a.re * s, a.im * s}; }
 
-// Overlap matrix A[m][n] = sum_r conj(P_m(r)) P_n(r), one workgroup per pair
-// m <= n, summed in double in a fixed order; A is M x M row-major.
-__global__ __launch_bounds__(256) void k_probe_gram(const float2* P, int M, int NN, cd* A) {
-    int pair = blockIdx.x, m = 0;
+// Partial overlaps conj(P_m(r)) P_n(r) summed over one chunk of GRAM_CHUNK
+// pixels, in double: one workgroup per (chunk, pair m <= n), written to
+// part[pair * nchunk + chunk]; the eigen kernel adds the chunks in order.
+__global__ __launch_bounds__(256) void k_probe_gram(const float2* P, int M, int NN, cd* part) {
+    const int chunk = blockIdx.x, nchunk = gridDim.x;
+    int pair = blockIdx.y, m = 0;
+    const int pair_id = pair;
     while (pair >= M - m) { pair -= M - m; ++m; }
     const int n = m + pair;
     const float2* a = P + (size_t)m * NN;
     const float2* b = P + (size_t)n * NN;
     double re = 0.0, im = 0.0;
-    for (int r = threadIdx.x; r < NN; r += blockDim.x) {
+    const int r1 = min(NN, (chunk + 1) * GRAM_CHUNK);
+    for (int r = chunk * GRAM_CHUNK + threadIdx.x; r < r1; r += blockDim.x) {
         const float2 x = a[r], y = b[r];
         re += (double)x.x * y.x + (double)x.y * y.y;       // conj(x) y
         im += (double)x.x * y.y - (double)x.y * y.x;
@@ -85,27 +167,35 @@ __global__ __launch_bounds__(256) void k_probe_gram(const float2* P, int M, int 
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        A[m * M + n] = {sr[0], m == n ? 0.0 : si[0]};
-        A[n * M + m] = {sr[0], m == n ? 0.0 : -si[0]};
-    }
+    if (threadIdx.x == 0) part[(size_t)pair_id * nchunk + chunk] = {sr[0], si[0]};
 }
 
-// Eigenvectors of the Hermitian overlap matrix by cyclic complex Jacobi
+// Eigenvectors of the Hermitian overlap matrix (summed from the chunk
+// partials) by cyclic complex Jacobi
 // rotations in double (one workgroup, thread k owning row / column k), then
 // ordered by decreasing eigenvalue; each eigenvector is scaled by a unit
 // phase so that its largest-magnitude entry (first of equals) is real and
 // positive.  Writes V (M x M, column k = mode k's mixing coefficients) as
 // float pairs and the eigenvalues.
-__global__ __launch_bounds__(64) void k_probe_eig(const cd* Ain, int M, float2* Vout, double* lam_out) {
+__global__ __launch_bounds__(64) void k_probe_eig(const cd* part, int nchunk, int M, float2* Vout, double* lam_out) {
     __shared__ cd A[ORTH_MAX_M * ORTH_MAX_M], V[ORTH_MAX_M * ORTH_MAX_M];
     __shared__ double lam[ORTH_MAX_M];
     __shared__ int order[ORTH_MAX_M];
     __shared__ double off;
     const int k = threadIdx.x;
-    for (int i = k; i < M * M; i += blockDim.x) {
-        A[i] = Ain[i];
-        V[i] = {(i / M) == (i % M) ? 1.0 : 0.0, 0.0};
+    for (int i = k; i < M * M; i += blockDim.x) V[i] = {(i / M) == (i % M) ? 1.0 : 0.0, 0.0};
+    // overlap matrix from the chunk sums (fixed order)
+    for (int pid = k; pid < M * (M + 1) / 2; pid += blockDim.x) {
+        int pr = pid, m = 0;
+        while (pr >= M - m) { pr -= M - m; ++m; }
+        const int n = m + pr;
+        double re = 0.0, im = 0.0;
+        for (int ch = 0; ch < nchunk; ++ch) {
+            re += part[(size_t)pid * nchunk + ch].re;
+            im += part[(size_t)pid * nchunk + ch].im;
+        }
+        A[m * M + n] = {re, m == n ? 0.0 : im};
+        A[n * M + m] = {re, m == n ? 0.0 : -im};
     }
     __syncthreads();
     double scale = 0.0;

@@ -455,7 +455,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, err, store, gO, gPhat, gPsum, part, gamp, gphase,
-        gprobe, gdz, gpos, gtilt, wave, cons, total;
+        gprobe, gdz, gpos, gtilt, wave, cons, rzmat, total;
     int keep, ckK, nck, waves_per_chain;
 };
 
@@ -510,9 +510,11 @@ Layout make_layout(const ptyr_geom* g) {
     L.gpos = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
     L.gtilt = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
     L.wave = take(g->N == 256 ? B * M * NN * sizeof(float2) : 0);
-    // probe orthogonalisation: overlap matrix (double complex), mixing
+    // probe orthogonalisation: partial overlap sums (double complex), mixing
     // matrix (float complex), eigenvalues
-    L.cons = take((size_t)ORTH_MAX_M * ORTH_MAX_M * (sizeof(cd) + sizeof(float2)) + ORTH_MAX_M * sizeof(double));
+    L.cons = take((size_t)ORTH_MAX_M * (ORTH_MAX_M + 1) / 2 * GRAM_MAX_CHUNKS * sizeof(cd) +
+                  (size_t)ORTH_MAX_M * ORTH_MAX_M * sizeof(float2) + ORTH_MAX_M * sizeof(double));
+    L.rzmat = take((size_t)RZ_REG_S * RZ_REG_S * sizeof(float));     // depth-filter matrix
     L.total = o;
     return L;
 }
@@ -1099,22 +1101,41 @@ ptyr_status ptyr_constrain(ptyr_ctx* c, float* amp, float* phase, float* probe, 
             sum += w[k + t.R];
         }
         for (int k = 0; k <= 2 * t.R; ++k) t.w[k] = (float)(w[k] / sum);
-        const dim3 grid((unsigned)((HW + RZ_PIX - 1) / RZ_PIX));
-        const size_t lds = (size_t)g.S * RZ_PIX * sizeof(float);
-        hipLaunchKernelGGL(k_rz_filter, grid, dim3(256), lds, st, amp, g.S, HW, t, 0);
-        hipLaunchKernelGGL(k_rz_filter, grid, dim3(256), lds, st, phase, g.S, HW, t, cfg->phase_positive ? 1 : 0);
+        float* fields[2] = {amp, phase};
+        if (g.S <= RZ_REG_S) {
+            float* Bm = at<float>(c, c->L.rzmat);
+            hipLaunchKernelGGL(k_rz_matrix, dim3((g.S * g.S + 255) / 256), dim3(256), 0, st, t, g.S, Bm);
+            const bool vec4 = HW % 4 == 0 && reinterpret_cast<uintptr_t>(amp) % 16 == 0 &&
+                              reinterpret_cast<uintptr_t>(phase) % 16 == 0;
+            const dim3 grid((unsigned)((HW / (vec4 ? 4 : 1) + 255) / 256));
+            for (int f = 0; f < 2; ++f) {
+                TimedLaunch tl(c, PTYR_K_RZ, st);
+                const int pos = f == 1 && cfg->phase_positive ? 1 : 0;
+                if (vec4) hipLaunchKernelGGL(k_rz_filter_reg4, grid, dim3(256), 0, st, fields[f], g.S, HW, Bm, pos);
+                else hipLaunchKernelGGL(k_rz_filter_reg, grid, dim3(256), 0, st, fields[f], g.S, HW, Bm, pos);
+            }
+        } else {
+            const int T = rz_threads(g.S);
+            const dim3 grid((unsigned)((HW + T - 1) / T));
+            const size_t lds = (size_t)g.S * T * sizeof(float);
+            for (int f = 0; f < 2; ++f) {
+                TimedLaunch tl(c, PTYR_K_RZ, st);
+                hipLaunchKernelGGL(k_rz_filter, grid, dim3(T), lds, st, fields[f], g.S, HW, t,
+                                   f == 1 && cfg->phase_positive ? 1 : 0);
+            }
+        }
     } else if (cfg->phase_positive) {
         hipLaunchKernelGGL(k_clip_negative, dim3(grid_for((size_t)g.S * HW)), dim3(256), 0, st, phase,
                            (size_t)g.S * HW);
     }
     if (cfg->probe_orthogonal && g.M > 1) {
-        const int M = g.M, NN = g.N * g.N;
-        cd* A = at<cd>(c, c->L.cons);
-        float2* V = reinterpret_cast<float2*>(A + ORTH_MAX_M * ORTH_MAX_M);
+        const int M = g.M, NN = g.N * g.N, nchunk = (NN + GRAM_CHUNK - 1) / GRAM_CHUNK;
+        cd* part = at<cd>(c, c->L.cons);
+        float2* V = reinterpret_cast<float2*>(part + (size_t)ORTH_MAX_M * (ORTH_MAX_M + 1) / 2 * GRAM_MAX_CHUNKS);
         double* lam = reinterpret_cast<double*>(V + ORTH_MAX_M * ORTH_MAX_M);
         float2* P = reinterpret_cast<float2*>(probe);
-        hipLaunchKernelGGL(k_probe_gram, dim3(M * (M + 1) / 2), dim3(256), 0, st, P, M, NN, A);
-        hipLaunchKernelGGL(k_probe_eig, dim3(1), dim3(64), 0, st, A, M, V, lam);
+        hipLaunchKernelGGL(k_probe_gram, dim3(nchunk, M * (M + 1) / 2), dim3(256), 0, st, P, M, NN, part);
+        hipLaunchKernelGGL(k_probe_eig, dim3(1), dim3(64), 0, st, part, nchunk, M, V, lam);
         const size_t lds = ((size_t)M * 256 + (size_t)M * M) * sizeof(float2);
         hipLaunchKernelGGL(k_probe_mix, dim3((NN + 255) / 256), dim3(256), lds, st, P, M, NN, V);
     }

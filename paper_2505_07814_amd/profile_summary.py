@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 # the sources of the multislice forward / gradient kernels and their launches
-MULTISLICE_SOURCES = ("kernels.hpp", "lines256.hpp", "ptyr.hip", "wave.hpp")
+MULTISLICE_SOURCES = ("constrain.hpp", "kernels.hpp", "lines256.hpp", "ptyr.hip", "wave.hpp")
 
 
 def source_hash(files=MULTISLICE_SOURCES):

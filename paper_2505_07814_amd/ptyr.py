@@ -116,13 +116,15 @@ class Engine:
         L.check(self.lib.ptyr_timing_enable(self._ctx, 1 if on else 0), "ptyr_timing_enable")
 
     def timing_read(self):
-        """{'forward': (total_ms, launches), 'gradient': (...)}; clears the record
-        (the record is read once, so both kernels are read together)."""
+        """{'forward': (total_ms, launches), 'gradient': (...), 'rz': (...)} for
+        the kernels launched since timing was enabled; clears the record (it
+        is read once, so all kernels are read together)."""
         out = {}
-        for name, k in (("forward", L.PTYR_K_FORWARD), ("gradient", L.PTYR_K_GRADIENT)):
+        for name, k in (("forward", L.PTYR_K_FORWARD), ("gradient", L.PTYR_K_GRADIENT), ("rz", L.PTYR_K_RZ)):
             ms, n = C.c_double(), C.c_int()
             L.check(self.lib.ptyr_timing_read(self._ctx, k, C.byref(ms), C.byref(n)), "ptyr_timing_read")
-            out[name] = (ms.value, n.value)
+            if n.value:
+                out[name] = (ms.value, n.value)
         L.check(self.lib.ptyr_timing_enable(self._ctx, 1), "ptyr_timing_enable")
         return out
 

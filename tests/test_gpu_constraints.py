@@ -2,8 +2,9 @@
 orthogonalisation) with the FP64 constraints oracle.
 
 Bars (derived from the arithmetic): the depth filter is a convex combination
-of 2R+1 float values with float taps (each rounded to 2^-24 relative) summed
-in float, so each output is within (2R+2) 2^-24 max|v| of the exact value;
+of the column's values with float weights (each the float sum of at most
+2R+1 taps rounded to 2^-24 relative) summed in float over at most S or 2R+1
+terms, so each output is within (S + 2R + 2) 2^-24 max|v| of the exact value;
 clipping is exact.  The orthogonalised modes are sums of M float products of
 a double-precision eigenvector with the float input (relative error ~M 2^-24)
 and the eigenvectors of well-separated powers are stable, so each mode must
@@ -35,10 +36,11 @@ def engine(S, H, W, N=64, M=1):
 
 def rz_bound(sigma, v):
     R = int(math.ceil(4 * sigma))
-    return (2 * R + 2) * 2.0 ** -24 * float(np.max(np.abs(v)))
+    return (v.shape[0] + 2 * R + 2) * 2.0 ** -24 * float(np.max(np.abs(v)))
 
 
-@pytest.mark.parametrize("S,sigma", [(12, 0.6), (12, 1.0), (30, 2.5), (12, 7.0), (2, 1.0), (1, 1.5)])
+@pytest.mark.parametrize("S,sigma", [(12, 0.6), (12, 1.0), (30, 2.5), (12, 7.0), (2, 1.0), (1, 1.5), (32, 1.0),
+                                     (33, 1.0), (70, 3.0), (140, 16.0)])
 def test_rz_filter_matches_oracle(S, sigma):
     print(f"rz filter S={S} sigma={sigma}", flush=True)
     H, W = 70, 67                                   # HW not a multiple of the 64-pixel workgroup
