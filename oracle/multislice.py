@@ -216,9 +216,30 @@ class Gradients:
     loss: float
 
 
+def sparse_term(phase, pos, N):
+    """The sparsity regulariser with p = 1 (Sec. "Optimizers and loss
+    functions"): the mean of |phase| over the object patches of the batch
+    (each position's N x N integer crop, every slice), and its gradient with
+    respect to the phase: sign(phase) / (B S N^2) per covering patch, with
+    sign(0) = 0."""
+    phase = np.asarray(phase, np.float64)
+    S = phase.shape[0]
+    total = 0.0
+    g = np.zeros_like(phase)
+    for rho in np.asarray(pos, np.float64):
+        t, _ = split_position(rho, N)
+        patch = crop(phase, t, N)
+        total += np.sum(np.abs(patch))
+        crop(g, t, N)[...] += np.sign(patch)
+    norm = len(pos) * S * N * N
+    return total / norm, g / norm
+
+
 def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian",
-              p=None):
+              p=None, sparse_w=0.0):
     """Loss and its gradient w.r.t. all six parameters for one batch.
+    sparse_w > 0 adds sparse_w times the sparsity term (the weighted total
+    loss of the paper with the data term's weight 1).
 
     The chain rule is taken through the forward steps in reverse:
     far field -> last slice -> (slice s: object, then propagator) -> shift ->
@@ -277,13 +298,20 @@ def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian"
     G_probe = ifft2(G_Phat)                                 # Phat = F P
     g_amp = np.real(np.conj(G_O) * np.exp(1j * phase))      # O = a e^{i phi}
     g_phase = np.imag(G_O * np.conj(O))
+    if sparse_w:
+        Ls, gs = sparse_term(phase, pos, N)
+        L = L + sparse_w * Ls
+        g_phase = g_phase + sparse_w * gs
     return Gradients(g_amp, g_phase, G_probe, g_pos, g_tilt, float(g_dz), L)
 
 
-def loss_of(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian", p=None):
+def loss_of(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian", p=None, sparse_w=0.0):
     """Scalar loss of the forward model (for finite differences)."""
     I = forward(amp, phase, probe, pos, tilt, dz, dx, lam)
-    return loss(I, I_meas, kind, p)[0]
+    L = loss(I, I_meas, kind, p)[0]
+    if sparse_w:
+        L += sparse_w * sparse_term(phase, pos, probe.shape[-1])[0]
+    return L
 
 
 def scatter_patches(patches, ts, S, H, W):

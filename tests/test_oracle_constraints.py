@@ -173,3 +173,73 @@ def test_mixing_with_the_wrong_side_of_the_eigenvectors_is_caught(monkeypatch):
     monkeypatch.setattr(oc, "probe_orthogonalize", bad)
     with pytest.raises(AssertionError):
         _orth_pins()
+
+
+# ------------------------------------------------------------ sparsity term of the loss
+from oracle import multislice as ms                       # noqa: E402
+from paper_2505_07814_amd import synth                    # noqa: E402
+
+
+def test_sparse_term_constant_phase_closed_form():
+    """A constant phase c gives L = |c|; each pixel's gradient is
+    sign(c) * (patches covering it) / (B S N^2)."""
+    S, H, W, N = 3, 40, 44, 16
+    pos = np.array([[12.0, 12.0], [20.3, 25.6], [27.0, 30.0]])
+    for c in (0.7, -0.4):
+        L, g = ms.sparse_term(np.full((S, H, W), c), pos, N)
+        assert abs(L - abs(c)) < 1e-15
+        cover = np.zeros((H, W))
+        for rho in pos:
+            t = np.round(rho).astype(int) - N // 2
+            cover[t[0]:t[0] + N, t[1]:t[1] + N] += 1
+        assert np.allclose(g, np.sign(c) * cover[None] / (len(pos) * S * N * N), atol=1e-18)
+    L0, g0 = ms.sparse_term(np.zeros((S, H, W)), pos, N)
+    assert L0 == 0.0 and not np.any(g0)                  # sign(0) = 0
+
+
+def test_total_loss_with_sparsity_matches_central_differences():
+    """The data term plus 0.1 x the sparsity term: the phase gradient against
+    fourth-order central differences along random directions (phase kept
+    away from 0, where |phase| has its kink)."""
+    c = synth.small_case(N=16, S=2, M=2, B=3, H=16 + 11, W=16 + 13, seed=61)
+    lam = synth.wavelength_A(c.kv)
+    rng = np.random.default_rng(62)
+    phase = np.abs(c.phase) + 0.3
+    phase[:, ::3, ::2] *= -1                              # both signs present
+    I_true = ms.forward(c.amp, phase, c.probe, c.pos, c.tilt, c.dz, c.dx, lam)
+    probe = c.probe * np.sqrt(50.0 / I_true.max())
+    I_meas = rng.poisson(I_true * 50.0 / I_true.max() + 0.01).astype(np.float64) + 0.5
+    args = (c.amp, phase, probe, c.pos, c.tilt, c.dz, c.dx, lam, I_meas)
+    g = ms.gradients(*args, sparse_w=0.1)
+    g0 = ms.gradients(*args)
+    Ls, gs = ms.sparse_term(phase, c.pos, 16)
+    assert abs(g.loss - (g0.loss + 0.1 * Ls)) < 1e-15
+    h = 1e-6
+    for _ in range(4):
+        d = rng.standard_normal(phase.shape)
+        f = lambda x: ms.loss_of(c.amp, x, probe, c.pos, c.tilt, c.dz, c.dx, lam, I_meas, sparse_w=0.1)
+        fd = (8 * (f(phase + h * d) - f(phase - h * d)) - (f(phase + 2 * h * d) - f(phase - 2 * h * d))) / (12 * h)
+        an = np.sum(g.phase * d)
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9, (fd, an)
+    # and the sparsity part alone is what it adds
+    assert np.allclose(g.phase - g0.phase, 0.1 * gs, atol=1e-18)
+
+
+def test_sparse_term_mistakes_are_caught(monkeypatch):
+    """Dropping the slice count from the normaliser, or the sign, trips the pins."""
+    real = ms.sparse_term
+
+    def no_slices(phase, pos, N):
+        L, g = real(phase, pos, N)
+        S = np.asarray(phase).shape[0]
+        return L * S, g * S
+    monkeypatch.setattr(ms, "sparse_term", no_slices)
+    with pytest.raises(AssertionError):
+        test_sparse_term_constant_phase_closed_form()
+
+    def unsigned(phase, pos, N):
+        L, g = real(phase, pos, N)
+        return L, np.abs(g)
+    monkeypatch.setattr(ms, "sparse_term", unsigned)
+    with pytest.raises(AssertionError):
+        test_sparse_term_constant_phase_closed_form()
