@@ -84,6 +84,11 @@ typedef struct {
     unsigned flags;           /* PTYR_GLOBAL_TILT | PTYR_CHECK_FINITE */
     int n_scan;               /* scan positions ptyr_step may address (sizes its dense
                                  position / tilt gradients); 0 if ptyr_step is unused */
+    double sparse_w;          /* weight of the sparsity term added to the loss of
+                                 ptyr_adjoint / ptyr_step (Sec. "Optimizers and loss
+                                 functions", L^p of the object phase with p = 1: the
+                                 mean |phase| over the batch's N x N object patches,
+                                 every slice); 0 = off (the paper's default when on: 0.1) */
 } ptyr_geom;
 
 /* Parameters of one reconstruction and their Adam moments (all device). */

@@ -21,7 +21,8 @@ class Geom(C.Structure):
     _fields_ = [("N", C.c_int), ("M", C.c_int), ("S", C.c_int), ("H", C.c_int), ("W", C.c_int),
                 ("B_max", C.c_int), ("dx", C.c_double), ("lam", C.c_double),
                 ("loss_kind", C.c_int), ("loss_p", C.c_double),
-                ("wave_budget_bytes", C.c_size_t), ("flags", C.c_uint), ("n_scan", C.c_int)]
+                ("wave_budget_bytes", C.c_size_t), ("flags", C.c_uint), ("n_scan", C.c_int),
+                ("sparse_w", C.c_double)]
 
 
 _fp = C.c_void_p

@@ -138,7 +138,7 @@ __global__ void k_loss_partial(const float* Im, const float* Ie, const int* midx
 //   Gaussian: L = sqrt(D)/Z, dL/dA = (A-E) / (K sqrt(D) Z)
 //   Poisson : L = -mean(E log(A+eps) - A)/Z, dL/dA = -(E/(A+eps) - 1)/(K Z)
 __global__ void k_loss_final(const double* part, int nblk, double K, int kind, int check, double* scal,
-                             double* loss_out, int* err) {
+                             double* loss_out, int* err, const double* spart, int nsp, double spw) {
     __shared__ double sh[3 * 256];
     double s[3] = {0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += 256)
@@ -163,6 +163,11 @@ __global__ void k_loss_final(const double* part, int nblk, double K, int kind, i
         } else {
             L = -(sR / K) / Z;
             c = 1.0 / (K * Z);
+        }
+        if (nsp > 0) {                                  // + sparsity term, sums in order
+            double t = 0.0;
+            for (int i = 0; i < nsp; ++i) t += spart[i];
+            L += spw * t;
         }
         if (check && (bad > 0.0 || !isfinite(L))) atomicOr(err, ERR_NONFINITE);
         scal[0] = L;
@@ -280,7 +285,7 @@ template <bool FUSE>
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int j0, int j1, int M,
                                                         int S, int N, int H, int W, const float* amp,
                                                         const float* phase, const double* scale, float* g_amp,
-                                                        float* g_phase, ObjAdam ad) {
+                                                        float* g_phase, ObjAdam ad, float sp) {
     const int ntx = (W + 31) / 32;
     const int tile = blockIdx.x, s = blockIdx.y;
     const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
@@ -289,6 +294,7 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = make_float2(0.f, 0.f);
     bool touched = false;
+    int cnt[4] = {0, 0, 0, 0};                 // patches covering the pixel (sparsity term)
     const size_t NN = (size_t)N * N;
     for (int j = j0; j < j1; ++j) {
         const PosInfo pi = pinfo[j];
@@ -297,6 +303,12 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
         touched = true;
         const int px = x - pi.tx;
         const bool xin = px >= 0 && px < N;
+        if (sp != 0.f)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int py = yb + 8 * i - pi.ty;
+                cnt[i] += (xin && py >= 0 && py < N) ? 1 : 0;
+            }
         for (int m0 = 0; m0 < M; m0 += SCATTER_MB) {
             float2 buf[SCATTER_MB][4];
 #pragma unroll
@@ -325,12 +337,14 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
         size_t o = ((size_t)s * H + y) * W + x;
         float ga = 0.f, gp = 0.f;
         if (!FUSE || touched) {
+            const float ph = phase[o];
             float sn, cs;
-            sincosf(phase[o], &sn, &cs);
+            sincosf(ph, &sn, &cs);
             float a = amp[o];
             float2 G = cscale(acc[i], sc);
             ga = G.x * cs + G.y * sn;              // Re(conj(G) e^{i phi})
             gp = a * (G.y * cs - G.x * sn);        // Im(G conj(a e^{i phi}))
+            if (sp != 0.f) gp += sp * (float)cnt[i] * (ph > 0.f ? 1.f : (ph < 0.f ? -1.f : 0.f));
         }
         if constexpr (!FUSE) {
             if (g_amp) g_amp[o] += ga;
@@ -349,6 +363,26 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
             }
         }
     }
+}
+
+// Sparsity term: the sum of |phase| over the object patch of batch row j in
+// slice s (one workgroup per (j, s), double), for the loss.
+__global__ __launch_bounds__(256) void k_sparse_partial(const float* phase, const PosInfo* pinfo, int S, int N, int H,
+                                                        int W, double* part) {
+    const int j = blockIdx.x, s = blockIdx.y;
+    const PosInfo pi = pinfo[j];
+    double acc = 0.0;
+    if (pi.ty >= 0)
+        for (int e = threadIdx.x; e < N * N; e += blockDim.x)
+            acc += fabs((double)phase[((size_t)s * H + pi.ty + e / N) * W + pi.tx + e % N]);
+    __shared__ double sh[256];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)j * S + s] = sh[0];
 }
 
 // sum over batch rows of the probe-spectrum gradients (fixed order), times
@@ -454,7 +488,7 @@ __global__ void k_adam_segs(AdamSegs a, float b1, float b2, float eps, float bc1
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, err, store, gO, gPhat, gPsum, part, gamp, gphase,
+    size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, spart, err, store, gO, gPhat, gPsum, part, gamp, gphase,
         gprobe, gdz, gpos, gtilt, wave, cons, rzmat, total;
     int keep, ckK, nck, waves_per_chain;
 };
@@ -497,6 +531,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.wbuf = take(B * NN * sizeof(float));
     L.lpart = take(2 * 3 * NPART * sizeof(double));   // one block of NPART per row range
     L.scal = take(8 * sizeof(double));
+    L.spart = take(B * S * sizeof(double));           // sparsity-term partial sums
     L.err = take(sizeof(int));
     L.store = take(B * M * (size_t)L.waves_per_chain * NN * sizeof(float2));
     L.gO = take(B * M * S * NN * sizeof(float2));
@@ -595,6 +630,7 @@ ptyr_status ptyr_check_geom(const ptyr_geom* g) {
     // grid and index limits of the kernels
     if ((double)g->B_max * g->M > 2147483647.0 / 2) return PTYR_E_ARG;
     if (g->n_scan < 0) return PTYR_E_ARG;
+    if (!(g->sparse_w >= 0.0) || !isfinite(g->sparse_w)) return PTYR_E_ARG;
     if (g->N == 256) {   // the line-pass path keeps every wave (no recomputation)
         int keep, K, nck;
         keep_plan(g, &keep, &K, &nck);
@@ -879,12 +915,16 @@ void loss_rows(ptyr_ctx* c, const float* Ie, const int* midx, int nm, int r0, in
                        at<float>(c, c->L.wbuf) + (size_t)r0 * NN, at<int>(c, c->L.err));
 }
 
-void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev, hipStream_t st) {
+// with_sparse: add the sparsity term of the batch (its partial sums come
+// from k_sparse_partial) to the loss
+void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev, hipStream_t st, bool with_sparse) {
     const ptyr_geom& g = c->g;
     const double n = (double)B * g.N * g.N;
+    const bool sp = with_sparse && g.sparse_w > 0.0;
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, at<double>(c, c->L.lpart), nslots * NPART, n,
                        g.loss_kind, (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
-                       at<int>(c, c->L.err));
+                       at<int>(c, c->L.err), at<double>(c, c->L.spart), sp ? B * g.S : 0,
+                       sp ? g.sparse_w / ((double)B * g.S * g.N * g.N) : 0.0);
 }
 
 ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* midx, int n_meas, int B,
@@ -895,7 +935,7 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
     const int nm = midx ? n_meas : B;
     hipLaunchKernelGGL(k_loss_partial, dim3(NPART), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, g.loss_kind,
                        g.loss_p, at<double>(c, c->L.lpart), at<int>(c, c->L.err));
-    loss_final(c, 1, B, loss_dev, c->stream);
+    loss_final(c, 1, B, loss_dev, c->stream, false);
     if (dLdI)
         hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, g.N,
                            g.loss_kind, g.loss_p, at<double>(c, c->L.scal), dLdI);
@@ -931,6 +971,12 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     const bool reuse = (flags & PTYR_REUSE_FORWARD) && c->fwd_valid && c->fwd_B == B;
     const int nA = reuse ? 0 : split_chains(c, B);
     if (!reuse) prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
+    // sparsity term: |phase| over the batch's patches, before any update of the phase
+    const bool sparse = g.sparse_w > 0.0;
+    if (sparse)
+        hipLaunchKernelGGL(k_sparse_partial, dim3(B, g.S), dim3(256), 0, c->stream, phase, at<PosInfo>(c, c->L.pinfo),
+                           g.S, g.N, g.H, g.W, at<double>(c, c->L.spart));
+    const float sp = sparse && g_phase ? (float)(g.sparse_w / ((double)B * g.S * g.N * g.N)) : 0.f;
     const WaveArgs a = wave_args(c, tilt, dz, B);
     const double* scale = at<double>(c, c->L.scal) + 1;     // the batch factor of w (after loss_final)
     // object-gradient scatter of batch rows [j0, j1) on stream st; `last`
@@ -941,11 +987,11 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         if (last && fuse) {
             hipLaunchKernelGGL(k_scatter_object<true>, dim3(ntiles, g.S), dim3(256), 0, st, at<float2>(c, c->L.gO),
                                at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W, amp, phase, scale,
-                               g_amp, g_phase, *fuse);
+                               g_amp, g_phase, *fuse, sp);
         } else if (j1 > j0) {
             hipLaunchKernelGGL(k_scatter_object<false>, dim3(ntiles, g.S), dim3(256), 0, st,
                                at<float2>(c, c->L.gO), at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W,
-                               amp, phase, scale, g_amp, g_phase, ObjAdam{});
+                               amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
         }
     };
     // probe-spectrum sum and inverse transform, position / tilt / dz partials
@@ -997,7 +1043,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         // the compute units the main stream's last gradient launch leaves free
         if (nA > g1) gradient_chains(c, a, g1, nA - g1, c->side);
         if (hipStreamWaitEvent(c->side, c->ev_a1, 0) != hipSuccess) return PTYR_E_DEVICE;
-        loss_final(c, 2, B, loss_dev, c->side);
+        loss_final(c, 2, B, loss_dev, c->side, true);
         if (hipEventRecord(c->ev_sgrad, c->side) != hipSuccess) return PTYR_E_DEVICE;
         scatter(0, rA, c->side, false);
         // main: the second range's gradient chains, then (with the side
@@ -1025,7 +1071,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     c->fwd_valid = 1;
     c->fwd_B = B;
     if (!scattered) {
-        loss_final(c, 1, B, loss_dev, c->stream);
+        loss_final(c, 1, B, loss_dev, c->stream, true);
         reductions(c->stream);
         scatter(0, B, c->stream, true);
     }

@@ -312,7 +312,7 @@ def test_adam_step_parity():
         assert err < 1e-3, (k, err)
 
 
-@pytest.mark.parametrize("which", ["all", "phase_only"])
+@pytest.mark.parametrize("which", ["all", "phase_only", "sparse"])
 def test_step_split_batch_matches_adjoint_then_adam(which):
     """ptyr_step on a batch of more chains than compute units (two-stream
     schedule, the object's Adam fused into the batch's last scatter) equals
@@ -328,8 +328,9 @@ def test_step_split_batch_matches_adjoint_then_adam(which):
     lr = dict(amp=1e-3, phase=2e-3, probe=1e-2, pos=1e-2, tilt=1e-4, dz=1e-1)
     if which == "phase_only":
         lr = dict(amp=0.0, phase=2e-3, probe=0.0, pos=0.0, tilt=0.0, dz=0.0)
-    eng = Engine(64, 3, 3, w.H, w.W, 90, w.dx, c.lam, device=DEV, n_scan=90)
-    ref_eng = c.engine()
+    sw = 0.1 if which == "sparse" else 0.0
+    eng = Engine(64, 3, 3, w.H, w.W, 90, w.dx, c.lam, device=DEV, n_scan=90, sparse_w=sw)
+    ref_eng = c.engine(sparse_w=sw)
     st = AdamState(*[t.clone() for t in c.gpu_args()])
     meas = T(c.meas)
     b1, b2, eps = float(np.float32(0.9)), float(np.float32(0.999)), float(np.float32(1e-8))
@@ -361,6 +362,32 @@ def test_step_split_batch_matches_adjoint_then_adam(which):
             tol = 2 * np.spacing(np.abs(rp_r).astype(np.float32)) + 1e-5 * np.abs(rp_r - np.ravel(p0_r))
             print(f"step {t + 1} {k}: max |P - P_ref| / tol {np.max(d / tol):.2f}", flush=True)
             assert np.all(d <= tol), (t, k, float(np.max(d / tol)))
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_sparsity_term_parity(split):
+    """Loss and gradients with 0.1 x the L1 sparsity term of the phase, on one
+    stream (B = 5) and on the two-stream schedule (B = 90, 270 chains)."""
+    print(f"sparsity term (split={split})", flush=True)
+    if split:
+        w = synth.small_case(N=64, S=3, M=3, B=90, H=64 + 60, W=64 + 70, seed=31)
+    else:
+        w = small(64, 3, 2, 5, 12)
+    c = Case(w)
+    phase = (c.phase + np.float32(0.2)) * np.where(np.arange(c.phase.size).reshape(c.phase.shape) % 3 == 0,
+                                                   -1, 1).astype(np.float32)
+    eng = c.engine(sparse_w=0.1)
+    loss, g = eng.adjoint(*c.gpu_args(phase=phase), T(c.meas))
+    eng.sync()
+    ref = ms.gradients(c.amp, phase, c.probe, c.pos, c.tilt, c.dz, w.dx, c.lam, c.meas, sparse_w=0.1)
+    el = abs(float(loss.cpu()[0]) - ref.loss) / abs(ref.loss)
+    ep = rel(g["phase"].cpu().numpy(), ref.phase)
+    ea = rel(g["amp"].cpu().numpy(), ref.amp)
+    print(f"loss {el:.2e} phase {ep:.2e} amp {ea:.2e}", flush=True)
+    assert el < 1e-6 and ep < 1e-4 and ea < 1e-4
+    # the sparsity part of the loss and of the phase gradient are really there
+    Ls, gs = ms.sparse_term(phase, c.pos, 64)
+    assert 0.1 * Ls > 1e-3 * abs(ref.loss) and np.linalg.norm(0.1 * gs) > 1e-3 * np.linalg.norm(ref.phase)
 
 
 def test_autograd_function_matches_adjoint():
