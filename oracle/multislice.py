@@ -173,9 +173,33 @@ def exit_waves(amp, phase, probe, rho, tilt, dz, dx, lam):
 
 
 # ---------------------------------------------------------------- loss
-def loss(I_model, I_meas, kind="gaussian", p=None, eps=POISSON_EPS):
+def pacbed_loss(I_model, I_meas, p):
+    """The PACBED loss (Sec. "Optimizers and loss functions"): the RMS over
+    the detector of the difference between the p-th powers of the batch-mean
+    model and measured patterns, over the batch mean of the measured patterns
+    to the power p (the data term's normaliser).  Returns (L, dL/dI_model);
+    batch rows along axis 0."""
+    I = np.asarray(I_model, np.float64)
+    Im = np.asarray(I_meas, np.float64)
+    B = I.shape[0]
+    Abar = I.mean(axis=0)                      # <I_model>_B
+    Ebar = Im.mean(axis=0)                     # <I_meas>_B
+    R = Abar ** p - Ebar ** p
+    D = np.mean(R ** 2)                        # <.>_D
+    Z = np.mean(Im ** p)                       # <I_meas^p>_{D,B}
+    L = np.sqrt(D) / Z
+    if D == 0:
+        return float(L), np.zeros_like(I)
+    npix = R.size
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dAbar = np.where(Abar > 0, R * p * Abar ** (p - 1.0), 0.0) / (npix * np.sqrt(D) * Z)
+    return float(L), np.broadcast_to(dAbar / B, I.shape).copy()
+
+
+def loss(I_model, I_meas, kind="gaussian", p=None, eps=POISSON_EPS, pacbed_w=0.0):
     """Loss of Eq. (5) (kind='gaussian', default p=0.5) or Eq. (6)
-    (kind='poisson', default p=1), averaged over detector and batch.
+    (kind='poisson', default p=1), averaged over detector and batch, plus
+    pacbed_w times the PACBED loss (same p) when pacbed_w > 0.
     Returns (L, dL/dI_model) with the gradient in the layout of I_model."""
     I = np.asarray(I_model, np.float64)
     Im = np.asarray(I_meas, np.float64)
@@ -201,6 +225,10 @@ def loss(I_model, I_meas, kind="gaussian", p=None, eps=POISSON_EPS):
     else:
         with np.errstate(divide="ignore", invalid="ignore"):
             dI = np.where(I > 0, dA * p * I ** (p - 1.0), 0.0)
+    if pacbed_w:
+        Lp, dIp = pacbed_loss(I, Im, p)
+        L = L + pacbed_w * Lp
+        dI = dI + pacbed_w * dIp
     return float(L), dI
 
 
@@ -236,10 +264,11 @@ def sparse_term(phase, pos, N):
 
 
 def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian",
-              p=None, sparse_w=0.0):
+              p=None, sparse_w=0.0, pacbed_w=0.0):
     """Loss and its gradient w.r.t. all six parameters for one batch.
-    sparse_w > 0 adds sparse_w times the sparsity term (the weighted total
-    loss of the paper with the data term's weight 1).
+    sparse_w > 0 adds sparse_w times the sparsity term, pacbed_w > 0 adds
+    pacbed_w times the PACBED loss (the weighted total loss of the paper with
+    the data term's weight 1).
 
     The chain rule is taken through the forward steps in reverse:
     far field -> last slice -> (slice s: object, then propagator) -> shift ->
@@ -254,7 +283,7 @@ def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian"
     S, Hh, Ww = amp.shape
     M, N, _ = probe.shape
     I_model, traces = forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=True)
-    L, dI = loss(I_model, I_meas, kind, p)
+    L, dI = loss(I_model, I_meas, kind, p, pacbed_w=pacbed_w)
     O = transmission(amp, phase)
     Phat = fft2(probe)
     ky, kx = kgrid(N, dx)
@@ -305,10 +334,11 @@ def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian"
     return Gradients(g_amp, g_phase, G_probe, g_pos, g_tilt, float(g_dz), L)
 
 
-def loss_of(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian", p=None, sparse_w=0.0):
+def loss_of(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian", p=None, sparse_w=0.0,
+            pacbed_w=0.0):
     """Scalar loss of the forward model (for finite differences)."""
     I = forward(amp, phase, probe, pos, tilt, dz, dx, lam)
-    L = loss(I, I_meas, kind, p)[0]
+    L = loss(I, I_meas, kind, p, pacbed_w=pacbed_w)[0]
     if sparse_w:
         L += sparse_w * sparse_term(phase, pos, probe.shape[-1])[0]
     return L
