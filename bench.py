@@ -299,6 +299,8 @@ def main():
     ap.add_argument("--iterations", type=int, default=60, help="reconstruction iterations for --learned-init")
     ap.add_argument("--sparse-w", type=float, default=0.0,
                     help="weight of the L1 sparsity term of the object phase in the step's loss (0 = off)")
+    ap.add_argument("--pacbed-w", type=float, default=0.0,
+                    help="weight of the PACBED term in the step's loss (0 = off; on, a batch runs on one stream)")
     ap.add_argument("--constraints", action="store_true",
                     help="time ptyr_constrain (r_z filter, positivity, probe orthogonalisation) on the N=128 workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -330,7 +332,8 @@ def main():
     n_pos = w.pos.shape[0]
     T = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a if dt is None else a.astype(dt))).to(dev)
 
-    eng = Engine(w.N, w.M, w.S, w.H, w.W, B, w.dx, lam, n_scan=n_pos, sparse_w=args.sparse_w, device=dev)
+    eng = Engine(w.N, w.M, w.S, w.H, w.W, B, w.dx, lam, n_scan=n_pos, sparse_w=args.sparse_w,
+                 pacbed_w=args.pacbed_w, device=dev)
     # synthetic measured data: forward model of the true object, Poisson-sampled
     true = dict(amp=T(w.amp, np.float32), phase=T(w.phase, np.float32), probe=T(w.probe, np.complex64),
                 pos=T(w.pos, np.float32), tilt=T(w.tilt, np.float32), dz=T(np.array([w.dz], np.float32)))
@@ -423,7 +426,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "global_batch": B, "N": w.N, "slices": w.S, "modes": w.M, "positions": n_pos,
-                   **({"sparse_w": args.sparse_w} if args.sparse_w else {})},
+                   **({"sparse_w": args.sparse_w} if args.sparse_w else {}),
+                   **({"pacbed_w": args.pacbed_w} if args.pacbed_w else {})},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

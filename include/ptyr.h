@@ -89,6 +89,12 @@ typedef struct {
                                  functions", L^p of the object phase with p = 1: the
                                  mean |phase| over the batch's N x N object patches,
                                  every slice); 0 = off (the paper's default when on: 0.1) */
+    double pacbed_w;          /* weight of the PACBED term added to the loss of ptyr_loss,
+                                 ptyr_adjoint and ptyr_step (Sec. "Optimizers and loss
+                                 functions": RMS over the detector of <I_model>_B^p -
+                                 <I_meas>_B^p over <I_meas^p>_{D,B}, the same p as the
+                                 data term); 0 = off.  It couples the rows of a batch, so
+                                 with it a batch runs on one stream */
 } ptyr_geom;
 
 /* Parameters of one reconstruction and their Adam moments (all device). */

@@ -172,6 +172,7 @@ __global__ void k_loss_final(const double* part, int nblk, double K, int kind, i
         if (check && (bad > 0.0 || !isfinite(L))) atomicOr(err, ERR_NONFINITE);
         scal[0] = L;
         scal[1] = c;
+        scal[2] = Z;
         if (loss_out) *loss_out = L;
     }
 }
@@ -365,6 +366,78 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
     }
 }
 
+constexpr int PAC_BLOCKS = 64;
+
+// PACBED term, pass 1: per detector pixel q (zero frequency at (N/2, N/2)) the
+// batch means of the model and measured patterns, R = Abar^p - Ebar^p, kept
+// as pac[2q] = R, pac[2q + 1] = Abar; per-block partial sums of R^2.
+__global__ __launch_bounds__(256) void k_pacbed_partial(const float* I, const float* Ie, const int* midx, int n_meas,
+                                                        int row0, int B, int NN, double p, double* pac,
+                                                        double* part) {
+    double r2 = 0.0;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < NN; q += gridDim.x * blockDim.x) {
+        double a = 0.0, e = 0.0;
+        for (int j = 0; j < B; ++j) {
+            a += (double)I[(size_t)j * NN + q];
+            const long row = midx ? (long)midx[j] : (long)(row0 + j);
+            if (row >= 0 && row < n_meas) e += (double)Ie[(size_t)row * NN + q];
+        }
+        a = fmax(a / B, 0.0);
+        e = fmax(e / B, 0.0);
+        const double R = powp(a, p) - powp(e, p);
+        pac[2 * q] = R;
+        pac[2 * q + 1] = a;
+        r2 += R * R;
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = r2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// PACBED pass 2: L_pac = sqrt(<R^2>_D) / Z added (times w) to the loss;
+// scal[3] = the gradient factor w p / (NN sqrt(D) Z B).  fold: the batch
+// factor of the data term (scal[1]) moves to scal[4] and scal[1] becomes 1,
+// for weights that carry both terms.
+__global__ void k_pacbed_final(const double* part, int nblk, int NN, int B, double p, double w, double* scal,
+                               double* loss_out, int fold) {
+    if (threadIdx.x != 0) return;
+    double D = 0.0;
+    for (int b = 0; b < nblk; ++b) D += part[b];
+    D /= NN;
+    const double Z = scal[2];
+    const double L = Z > 0.0 ? sqrt(D) / Z : 0.0;
+    scal[0] += w * L;
+    if (loss_out) *loss_out += w * L;
+    scal[3] = (D > 0.0 && Z > 0.0) ? w * p / ((double)NN * sqrt(D) * Z * B) : 0.0;
+    if (fold) {
+        scal[4] = scal[1];
+        scal[1] = 1.0;
+    }
+}
+
+// PACBED pass 3: out = mul * out + fac * scal[3] R Abar^(p-1) for every row,
+// mul = scal[4] (fold) or 1; the adjoint's weights (fac 2, unshifted layout)
+// or ptyr_loss's dL/dI (fac 1, shifted layout).
+__global__ void k_pacbed_grad(float* out, int B, int N, double p, const double* pac, const double* scal, int fold,
+                              float fac, int unshift) {
+    const int NN = N * N;
+    const size_t n = (size_t)B * NN;
+    const double mul = fold ? scal[4] : 1.0, sp = scal[3];
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t j = e / NN;
+        const int q = (int)(e % NN);
+        const double R = pac[2 * q], a = pac[2 * q + 1];
+        const double d = p == 1.0 ? R : (a > 0.0 ? R * powm1(a, p) : 0.0);
+        float* o = out + j * NN + (unshift ? shift_index(q, N) : q);
+        *o = (float)(mul * (double)*o + (double)fac * sp * d);
+    }
+}
+
 // Sparsity term: the sum of |phase| over the object patch of batch row j in
 // slice s (one workgroup per (j, s), double), for the loss.
 __global__ __launch_bounds__(256) void k_sparse_partial(const float* phase, const PosInfo* pinfo, int S, int N, int H,
@@ -488,7 +561,7 @@ __global__ void k_adam_segs(AdamSegs a, float b1, float b2, float eps, float bc1
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, spart, err, store, gO, gPhat, gPsum, part, gamp, gphase,
+    size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, spart, pac, err, store, gO, gPhat, gPsum, part, gamp, gphase,
         gprobe, gdz, gpos, gtilt, wave, cons, rzmat, total;
     int keep, ckK, nck, waves_per_chain;
 };
@@ -532,6 +605,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.lpart = take(2 * 3 * NPART * sizeof(double));   // one block of NPART per row range
     L.scal = take(8 * sizeof(double));
     L.spart = take(B * S * sizeof(double));           // sparsity-term partial sums
+    L.pac = take(2 * NN * sizeof(double) + PAC_BLOCKS * sizeof(double));   // PACBED R, Abar; partial sums
     L.err = take(sizeof(int));
     L.store = take(B * M * (size_t)L.waves_per_chain * NN * sizeof(float2));
     L.gO = take(B * M * S * NN * sizeof(float2));
@@ -631,6 +705,7 @@ ptyr_status ptyr_check_geom(const ptyr_geom* g) {
     if ((double)g->B_max * g->M > 2147483647.0 / 2) return PTYR_E_ARG;
     if (g->n_scan < 0) return PTYR_E_ARG;
     if (!(g->sparse_w >= 0.0) || !isfinite(g->sparse_w)) return PTYR_E_ARG;
+    if (!(g->pacbed_w >= 0.0) || !isfinite(g->pacbed_w)) return PTYR_E_ARG;
     if (g->N == 256) {   // the line-pass path keeps every wave (no recomputation)
         int keep, K, nck;
         keep_plan(g, &keep, &K, &nck);
@@ -927,6 +1002,24 @@ void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev, hipStream_t st
                        sp ? g.sparse_w / ((double)B * g.S * g.N * g.N) : 0.0);
 }
 
+// PACBED term of a batch (after loss_final): adds it to the loss and its
+// gradient to `out` (fold: the adjoint's unscaled weights, which then carry
+// the data term's batch factor too; else ptyr_loss's dL/dI).
+void pacbed(ptyr_ctx* c, const float* I, const float* Ie, const int* midx, int n_meas, int row0, int B,
+            double* loss_dev, float* out, bool fold, hipStream_t st) {
+    const ptyr_geom& g = c->g;
+    const int NN = g.N * g.N;
+    double* pac = at<double>(c, c->L.pac);
+    double* part = pac + 2 * NN;
+    hipLaunchKernelGGL(k_pacbed_partial, dim3(PAC_BLOCKS), dim3(256), 0, st, I, Ie, midx, n_meas, row0, B, NN,
+                       g.loss_p, pac, part);
+    hipLaunchKernelGGL(k_pacbed_final, dim3(1), dim3(64), 0, st, part, PAC_BLOCKS, NN, B, g.loss_p, g.pacbed_w,
+                       at<double>(c, c->L.scal), loss_dev, fold ? 1 : 0);
+    if (out)
+        hipLaunchKernelGGL(k_pacbed_grad, dim3(grid_for((size_t)B * NN)), dim3(256), 0, st, out, B, g.N, g.loss_p,
+                           pac, at<double>(c, c->L.scal), fold ? 1 : 0, fold ? 2.f : 1.f, fold ? 1 : 0);
+}
+
 ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* midx, int n_meas, int B,
                      double* loss_dev, float* dLdI) {
     const ptyr_geom& g = c->g;
@@ -939,6 +1032,7 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
     if (dLdI)
         hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, g.N,
                            g.loss_kind, g.loss_p, at<double>(c, c->L.scal), dLdI);
+    if (g.pacbed_w > 0.0) pacbed(c, Im, Ie, midx, nm, 0, B, loss_dev, dLdI, false, c->stream);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
 
@@ -957,7 +1051,7 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
 // queued behind pending workgroups.  Returns n_cu (0: no split).
 int split_chains(const ptyr_ctx* c, int B) {
     const ptyr_geom& g = c->g;
-    if (g.N > 128 || c->n_cu <= 0 || B * g.M <= c->n_cu) return 0;
+    if (g.N > 128 || c->n_cu <= 0 || B * g.M <= c->n_cu || g.pacbed_w > 0.0) return 0;
     return c->n_cu / g.M >= 1 ? c->n_cu : 0;
 }
 
@@ -1066,12 +1160,19 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     } else {
         if (!reuse) forward_chains(c, a, 0, BM, c->stream);
         loss_rows(c, I_meas, idx, nm, 0, B, 0, c->stream);
+        if (g.pacbed_w > 0.0) {
+            // the PACBED weights need every row's pattern and the data term's
+            // batch factor before the gradient: fold both into the weights
+            loss_final(c, 1, B, loss_dev, c->stream, true);
+            pacbed(c, at<float>(c, c->L.Ibuf), I_meas, idx, nm, 0, B, loss_dev, at<float>(c, c->L.wbuf), true,
+                   c->stream);
+        }
         gradient_chains(c, a, 0, BM, c->stream);
     }
     c->fwd_valid = 1;
     c->fwd_B = B;
     if (!scattered) {
-        loss_final(c, 1, B, loss_dev, c->stream, true);
+        if (!(g.pacbed_w > 0.0)) loss_final(c, 1, B, loss_dev, c->stream, true);
         reductions(c->stream);
         scatter(0, B, c->stream, true);
     }

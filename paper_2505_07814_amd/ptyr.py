@@ -41,13 +41,15 @@ class Engine:
     """One libptyr context: geometry, workspace and stream.
 
     loss: 'gaussian' (Eq. 5, default p=0.5) or 'poisson' (Eq. 6, default p=1);
-    sparse_w: weight of the L1 sparsity term of the object phase (0 = off).
+    sparse_w: weight of the L1 sparsity term of the object phase (0 = off);
+    pacbed_w: weight of the PACBED term of the batch-mean patterns (0 = off).
     wave_budget: bytes the forward may keep for the gradient (None = all
     waves, B_max*M*2S*N*N*8); below that the gradient recomputes waves per
     slice from checkpoints.  n_scan: positions addressable by step()."""
 
     def __init__(self, N, M, S, H, W, B_max, dx, lam, loss="gaussian", p=None, wave_budget=None,
-                 global_tilt=False, check_finite=False, n_scan=0, sparse_w=0.0, device=None, stream=None):
+                 global_tilt=False, check_finite=False, n_scan=0, sparse_w=0.0, pacbed_w=0.0, device=None,
+                 stream=None):
         self.lib = L.lib()
         kind = {"gaussian": L.PTYR_LOSS_GAUSSIAN, "poisson": L.PTYR_LOSS_POISSON}[loss]
         if p is None:
@@ -56,7 +58,8 @@ class Engine:
             wave_budget = B_max * M * 2 * S * N * N * 8     # keep every slice's waves
         flags = (L.PTYR_GLOBAL_TILT if global_tilt else 0) | (L.PTYR_CHECK_FINITE if check_finite else 0)
         self.geom = L.Geom(N, M, S, H, W, B_max, float(dx), float(lam), kind, float(p),
-                           int(wave_budget), flags, int(n_scan), float(sparse_w))
+                           int(wave_budget), flags, int(n_scan), float(sparse_w),
+                           float(pacbed_w))
         L.check(self.lib.ptyr_check_geom(C.byref(self.geom)), "geometry")
         self.N, self.M, self.S, self.H, self.W, self.B_max = N, M, S, H, W, B_max
         self.global_tilt = global_tilt

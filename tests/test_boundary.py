@@ -21,7 +21,7 @@ def header_functions(name="ptyr.h"):
 
 def geom(**kw):
     d = dict(N=128, M=6, S=12, H=640, W=640, B_max=64, dx=0.15, lam=0.0197, loss_kind=0, loss_p=0.5,
-             wave_budget_bytes=64 * 6 * 24 * 128 * 128 * 8, flags=0, n_scan=16384, sparse_w=0.0)
+             wave_budget_bytes=64 * 6 * 24 * 128 * 128 * 8, flags=0, n_scan=16384, sparse_w=0.0, pacbed_w=0.0)
     d.update(kw)
     return L.Geom(*[d[f[0]] for f in L.Geom._fields_])
 

@@ -312,7 +312,7 @@ def test_adam_step_parity():
         assert err < 1e-3, (k, err)
 
 
-@pytest.mark.parametrize("which", ["all", "phase_only", "sparse"])
+@pytest.mark.parametrize("which", ["all", "phase_only", "sparse", "pacbed"])
 def test_step_split_batch_matches_adjoint_then_adam(which):
     """ptyr_step on a batch of more chains than compute units (two-stream
     schedule, the object's Adam fused into the batch's last scatter) equals
@@ -329,8 +329,9 @@ def test_step_split_batch_matches_adjoint_then_adam(which):
     if which == "phase_only":
         lr = dict(amp=0.0, phase=2e-3, probe=0.0, pos=0.0, tilt=0.0, dz=0.0)
     sw = 0.1 if which == "sparse" else 0.0
-    eng = Engine(64, 3, 3, w.H, w.W, 90, w.dx, c.lam, device=DEV, n_scan=90, sparse_w=sw)
-    ref_eng = c.engine(sparse_w=sw)
+    pw = 0.5 if which == "pacbed" else 0.0              # one stream: the batch means couple the rows
+    eng = Engine(64, 3, 3, w.H, w.W, 90, w.dx, c.lam, device=DEV, n_scan=90, sparse_w=sw, pacbed_w=pw)
+    ref_eng = c.engine(sparse_w=sw, pacbed_w=pw)
     st = AdamState(*[t.clone() for t in c.gpu_args()])
     meas = T(c.meas)
     b1, b2, eps = float(np.float32(0.9)), float(np.float32(0.999)), float(np.float32(1e-8))
@@ -388,6 +389,49 @@ def test_sparsity_term_parity(split):
     # the sparsity part of the loss and of the phase gradient are really there
     Ls, gs = ms.sparse_term(phase, c.pos, 64)
     assert 0.1 * Ls > 1e-3 * abs(ref.loss) and np.linalg.norm(0.1 * gs) > 1e-3 * np.linalg.norm(ref.phase)
+
+
+def test_pacbed_loss_parity():
+    """ptyr_loss with 0.5 x the PACBED term: loss and dL/dI against the oracle."""
+    rng = np.random.default_rng(17)
+    Im = rng.gamma(2.0, 20.0, (6, 64, 64)).astype(np.float32)
+    Ie = rng.poisson(Im + 0.5).astype(np.float32)
+    from paper_2505_07814_amd.ptyr import Engine
+    for kind in ("gaussian", "poisson"):
+        eng = Engine(64, 1, 1, 64, 64, 6, 0.2, 0.02, loss=kind, pacbed_w=0.5, device=DEV)
+        L, g = eng.loss(T(Im), T(Ie), want_grad=True)
+        eng.sync()
+        p = 0.5 if kind == "gaussian" else 1.0
+        L0, g0 = ms.loss(Im, Ie, kind, p, pacbed_w=0.5)
+        print(kind, abs(float(L.cpu()[0]) - L0) / abs(L0), rel(g.cpu().numpy(), g0), flush=True)
+        assert abs(float(L.cpu()[0]) - L0) <= 1e-6 * abs(L0)
+        assert rel(g.cpu().numpy(), g0) < 1e-6
+
+
+@pytest.mark.parametrize("B", [5, 90])
+def test_pacbed_gradient_parity(B):
+    """Loss and gradients with 0.5 x the PACBED term; B = 90 (270 chains) would
+    take the two-stream schedule without it."""
+    print(f"pacbed gradients B={B}", flush=True)
+    if B == 90:
+        w = synth.small_case(N=64, S=3, M=3, B=90, H=64 + 60, W=64 + 70, seed=31)
+    else:
+        w = small(64, 3, 2, 5, 12)
+    c = Case(w)
+    eng = c.engine(pacbed_w=0.5)
+    loss, g = eng.adjoint(*c.gpu_args(), T(c.meas))
+    eng.sync()
+    ref = ms.gradients(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, w.dx, c.lam, c.meas, pacbed_w=0.5)
+    errs = {"loss": abs(float(loss.cpu()[0]) - ref.loss) / abs(ref.loss),
+            "amp": rel(g["amp"].cpu().numpy(), ref.amp), "phase": rel(g["phase"].cpu().numpy(), ref.phase),
+            "probe": rel(g["probe"].cpu().numpy(), ref.probe), "pos": rel(g["pos"].cpu().numpy(), ref.pos),
+            "tilt": rel(g["tilt"].cpu().numpy(), ref.tilt), "dz": rel(g["dz"].cpu().numpy(), [ref.dz])}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < (1e-6 if k == "loss" else 1e-4), (k, v)
+    # the term changes the gradient measurably
+    ref0 = ms.gradients(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, w.dx, c.lam, c.meas)
+    assert rel(ref.phase, ref0.phase) > 1e-3
 
 
 def test_autograd_function_matches_adjoint():
