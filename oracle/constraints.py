@@ -17,6 +17,12 @@ out here, in the order the library applies them:
   s1, ...), so no slice mixes with the far end of the stack.
 * positivity (Sec. "Positivity and sparsity"): negative object phase is
   clipped to zero.
+* k_z filter (Sec. "Fourier-space depth regularization"): the object is
+  multiplied in 3-D Fourier space by W_a(k) = W(k) exp(-alpha (k_x^2 +
+  k_y^2)) with W = 1 - (2/pi) arctan(beta^2 k_z^2 / (k_x^2 + k_y^2 + eps)),
+  eps = 1e-3; k in 1/angstrom from the pixel size dx and the slice spacing dz
+  (fftfreq grids, periodic).  Reading: applied to the amplitude and to the
+  phase, each a real field (W_a is real and even, so they stay real).
 * probe-mode orthogonalisation (Sec. "Physical constraints", after
   Thibault & Menzel 2013): the mixed-state modes are replaced by the
   eigenvectors of their overlap matrix, ordered by decreasing power.
@@ -60,6 +66,23 @@ def rz_filter(vol, sigma: float, truncate: float = 4.0) -> np.ndarray:
     return out
 
 
+def kz_weight(S, H, W, beta, alpha, dx, dz, eps=1e-3) -> np.ndarray:
+    """W_a on the S x H x W fftfreq grid (zero frequency at index 0)."""
+    kz = np.fft.fftfreq(S, d=dz)[:, None, None]
+    ky = np.fft.fftfreq(H, d=dx)[None, :, None]
+    kx = np.fft.fftfreq(W, d=dx)[None, None, :]
+    kr2 = kx ** 2 + ky ** 2
+    Wk = 1.0 - (2.0 / np.pi) * np.arctan(beta ** 2 * kz ** 2 / (kr2 + eps))
+    return Wk * np.exp(-alpha * kr2)
+
+
+def kz_filter(vol, beta, alpha, dx, dz) -> np.ndarray:
+    """F3^-1[W_a F3[vol]] of a real S x H x W field (real part of the result)."""
+    vol = np.asarray(vol, np.float64)
+    Wa = kz_weight(*vol.shape, beta, alpha, dx, dz)
+    return np.real(np.fft.ifftn(Wa * np.fft.fftn(vol)))
+
+
 def positivity(phase) -> np.ndarray:
     return np.maximum(np.asarray(phase, np.float64), 0.0)
 
@@ -86,12 +109,16 @@ def probe_orthogonalize(probe):
     return Q, lam
 
 
-def apply(amp, phase, probe, rz_sigma=0.0, phase_positive=False, probe_orthogonal=False):
-    """The three constraints in the library's order: r_z filter (amplitude
-    and phase), positivity, probe orthogonalisation."""
+def apply(amp, phase, probe, rz_sigma=0.0, phase_positive=False, probe_orthogonal=False, kz_beta=0.0,
+          kz_alpha=0.0, dx=1.0, dz=1.0):
+    """The constraints in the library's order: k_z filter, r_z filter (each on
+    amplitude and phase), positivity, probe orthogonalisation."""
     amp = np.asarray(amp, np.float64)
     phase = np.asarray(phase, np.float64)
     probe = None if probe is None else np.asarray(probe, np.complex128)
+    if kz_beta > 0 or kz_alpha > 0:
+        amp = kz_filter(amp, kz_beta, kz_alpha, dx, dz)
+        phase = kz_filter(phase, kz_beta, kz_alpha, dx, dz)
     if rz_sigma > 0:
         amp = rz_filter(amp, rz_sigma)
         phase = rz_filter(phase, rz_sigma)

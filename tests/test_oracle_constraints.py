@@ -243,3 +243,41 @@ def test_sparse_term_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(ms, "sparse_term", unsigned)
     with pytest.raises(AssertionError):
         test_sparse_term_constant_phase_closed_form()
+
+
+# ------------------------------------------------------------ k_z filter
+def _plane(S, H, W, f, dx, dz):
+    z, y, x = np.meshgrid(np.arange(S), np.arange(H), np.arange(W), indexing="ij")
+    kz, ky, kx = f[0] / (S * dz), f[1] / (H * dx), f[2] / (W * dx)
+    return np.cos(2 * np.pi * (kz * z * dz + ky * y * dx + kx * x * dx)), (kz, ky, kx)
+
+
+@pytest.mark.parametrize("f", [(1, 2, 3), (5, 0, 1), (0, 4, 4), (2, 7, -9)])
+def test_kz_plane_waves_are_eigenfunctions(f):
+    """A real plane wave on the grid comes back multiplied by the closed-form
+    W_a at its wave vector (W_a is even, so the cosine stays a cosine)."""
+    S, H, W, dx, dz, beta, alpha = 12, 20, 18, 0.3, 7.0, 0.7, 0.2
+    v, (kz, ky, kx) = _plane(S, H, W, f, dx, dz)
+    kr2 = kx ** 2 + ky ** 2
+    w = (1 - 2 / np.pi * math.atan(beta ** 2 * kz ** 2 / (kr2 + 1e-3))) * math.exp(-alpha * kr2)
+    assert np.allclose(oc.kz_filter(v, beta, alpha, dx, dz), w * v, atol=1e-12)
+
+
+def test_kz_identity_and_depth_constant_fields():
+    v = _vol(6, 10, 12)
+    assert np.allclose(oc.kz_filter(v, 0.0, 0.0, 0.2, 5.0), v, atol=1e-13)
+    # k_z = 0 everywhere for a depth-constant field: W = 1, any beta
+    d = np.repeat(_vol(1, 10, 12, seed=4), 6, axis=0)
+    assert np.allclose(oc.kz_filter(d, 3.0, 0.0, 0.2, 5.0), d, atol=1e-13)
+
+
+def test_kz_filter_mistakes_are_caught(monkeypatch):
+    real = oc.kz_weight
+    monkeypatch.setattr(oc, "kz_weight", lambda S, H, W, beta, alpha, dx, dz, eps=1e-3:
+                        real(S, H, W, beta, alpha, dx, 1.0, eps))                       # dz units dropped
+    with pytest.raises(AssertionError):
+        test_kz_plane_waves_are_eigenfunctions((1, 2, 3))
+    monkeypatch.setattr(oc, "kz_weight", lambda S, H, W, beta, alpha, dx, dz, eps=1e-3:
+                        real(S, H, W, beta, 0.0, dx, dz, eps))                          # lateral blur dropped
+    with pytest.raises(AssertionError):
+        test_kz_plane_waves_are_eigenfunctions((1, 2, 3))
