@@ -41,7 +41,8 @@ class LR(C.Structure):
 
 
 class Constraints(C.Structure):
-    _fields_ = [("rz_sigma", C.c_float), ("phase_positive", C.c_int), ("probe_orthogonal", C.c_int)]
+    _fields_ = [("rz_sigma", C.c_float), ("phase_positive", C.c_int), ("probe_orthogonal", C.c_int),
+                ("kz_beta", C.c_float), ("kz_alpha", C.c_float), ("kz_dz", C.c_float)]
 
 
 class PtyrError(RuntimeError):

@@ -129,6 +129,117 @@ __global__ void k_clip_negative(float* v, size_t n) {
         v[i] = fmaxf(v[i], 0.f);
 }
 
+// ------------------------------------------------------------ k_z filter
+// Mixed-radix (2, 3, 4, 5, 8) Stockham passes through device memory for the
+// 3-D transform of the S x H x W object (sides not powers of two, e.g.
+// 12 x 640 x 640).  Amplitude and phase travel together as one complex field
+// a + i phase: the weight W_a is real and even, so the filtered real and
+// imaginary parts are the two filtered fields.
+
+// the element (line l, index i) of an axis sits at off(l) + i * stride with
+// off(l) = (l / L1) * P1 + (l % L1) * P0
+struct Axis {
+    int n;              // transform length
+    size_t lines;       // independent lines
+    size_t stride;      // element stride along the line
+    size_t L1, P1, P0;
+    int lines_fast;     // consecutive threads take consecutive lines (else consecutive j)
+};
+
+__device__ __forceinline__ float2 cmul_f(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One radix-R pass with Ns = product of the radices before it: thread (l, j),
+// j < n / R, reads the R elements j + r n / R, multiplies element r by
+// exp(sign 2 pi i r (j mod Ns) / (Ns R)), takes their R-point DFT and writes
+// output r to (j / Ns) Ns R + (j mod Ns) + r Ns.
+template <int R>
+__global__ __launch_bounds__(256) void k_fft_pass(const float2* __restrict__ src, float2* __restrict__ dst, Axis a,
+                                                  int Ns, float sign) {
+    const int m = a.n / R;
+    const size_t total = a.lines * m;
+    float2 wr[R];                              // exp(sign 2 pi i q / R)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        float sn, cs;
+        sincospif(sign * 2.0f * (float)q / (float)R, &sn, &cs);
+        wr[q] = make_float2(cs, sn);
+    }
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        size_t l;
+        int j;
+        if (a.lines_fast) { l = t % a.lines; j = (int)(t / a.lines); }
+        else { j = (int)(t % m); l = t / m; }
+        const size_t off = (l / a.L1) * a.P1 + (l % a.L1) * a.P0;
+        const int k = j % Ns;
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float2 x = src[off + (size_t)(j + r * m) * a.stride];
+            float sn, cs;
+            sincospif(sign * 2.0f * (float)(r * k) / (float)(Ns * R), &sn, &cs);
+            v[r] = cmul_f(x, make_float2(cs, sn));
+        }
+        float2 o[R];
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float2 t2 = cmul_f(v[r], wr[(r * b) % R]);
+                acc.x += t2.x;
+                acc.y += t2.y;
+            }
+            o[b] = acc;
+        }
+        const size_t d = (size_t)(j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[off + (d + (size_t)r * Ns) * a.stride] = o[r];
+    }
+}
+
+__global__ void k_kz_pack(const float* amp, const float* phase, size_t n, float2* z) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        z[i] = make_float2(amp[i], phase[i]);
+}
+__global__ void k_kz_unpack(const float2* z, size_t n, float* amp, float* phase) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float2 v = z[i];
+        amp[i] = v.x;
+        phase[i] = v.y;
+    }
+}
+
+// multiply the 3-D spectrum by W_a(k) / (S H W) (the inverse transform's
+// normalisation folded in); k from fftfreq with the pixel size dx and the
+// slice spacing dz (1/angstrom), weight evaluated in double
+__global__ void k_kz_weight(float2* z, int S, int H, int W, double beta, double alpha, double dx, double dz) {
+    const size_t n = (size_t)S * H * W;
+    const double norm = 1.0 / (double)n;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % W), y = (int)((i / W) % H), s = (int)(i / ((size_t)W * H));
+        const double kx = (x < (W + 1) / 2 ? x : x - W) / (W * dx);
+        const double ky = (y < (H + 1) / 2 ? y : y - H) / (H * dx);
+        const double kz = (s < (S + 1) / 2 ? s : s - S) / (S * dz);
+        const double kr2 = kx * kx + ky * ky;
+        const double w = (1.0 - (2.0 / 3.14159265358979323846) * atan(beta * beta * kz * kz / (kr2 + 1e-3))) *
+                         exp(-alpha * kr2) * norm;
+        z[i] = make_float2((float)(z[i].x * w), (float)(z[i].y * w));
+    }
+}
+
+// radices of n (5s, 3s, then 8s, 4s, 2s); 0 if n has another prime factor
+inline int fft_radices(int n, int* rs) {
+    int k = 0;
+    for (int r : {5, 3})
+        while (n % r == 0) { rs[k++] = r; n /= r; }
+    while (n % 8 == 0) { rs[k++] = 8; n /= 8; }
+    while (n % 4 == 0) { rs[k++] = 4; n /= 4; }
+    while (n % 2 == 0) { rs[k++] = 2; n /= 2; }
+    return n == 1 ? k : -1;
+}
+
 // ------------------------------------------------------------ probe modes
 struct cd {
     double re, im;

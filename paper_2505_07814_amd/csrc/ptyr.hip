@@ -562,7 +562,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, spart, pac, err, store, gO, gPhat, gPsum, part, gamp, gphase,
-        gprobe, gdz, gpos, gtilt, wave, cons, rzmat, total;
+        gprobe, gdz, gpos, gtilt, wave, cons, rzmat, kz, total;
     int keep, ckK, nck, waves_per_chain;
 };
 
@@ -624,6 +624,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.cons = take((size_t)ORTH_MAX_M * (ORTH_MAX_M + 1) / 2 * GRAM_MAX_CHUNKS * sizeof(cd) +
                   (size_t)ORTH_MAX_M * ORTH_MAX_M * sizeof(float2) + ORTH_MAX_M * sizeof(double));
     L.rzmat = take((size_t)RZ_REG_S * RZ_REG_S * sizeof(float));     // depth-filter matrix
+    L.kz = take(2 * S * HW * sizeof(float2));                         // k_z filter: two complex fields
     L.total = o;
     return L;
 }
@@ -1236,8 +1237,57 @@ ptyr_status ptyr_constrain(ptyr_ctx* c, float* amp, float* phase, float* probe, 
     if (rz && (!amp || !phase || g.S > RZ_MAX_S)) return PTYR_E_ARG;
     if (cfg->phase_positive && !phase) return PTYR_E_ARG;
     if (cfg->probe_orthogonal && (!probe || g.M > ORTH_MAX_M)) return PTYR_E_ARG;
+    const bool kz = cfg->kz_beta > 0.f || cfg->kz_alpha > 0.f;
+    int rad[3][32], nrad[3] = {0, 0, 0};
+    if (!(cfg->kz_beta >= 0.f) || !(cfg->kz_alpha >= 0.f) || !isfinite(cfg->kz_beta) || !isfinite(cfg->kz_alpha))
+        return PTYR_E_ARG;
+    if (kz) {
+        if (!amp || !phase || !(cfg->kz_dz > 0.f) || !isfinite(cfg->kz_dz)) return PTYR_E_ARG;
+        nrad[0] = fft_radices(g.W, rad[0]);
+        nrad[1] = fft_radices(g.H, rad[1]);
+        nrad[2] = fft_radices(g.S, rad[2]);
+        if (nrad[0] < 0 || nrad[1] < 0 || nrad[2] < 0) return PTYR_E_ARG;
+    }
     const hipStream_t st = c->stream;
     const size_t HW = (size_t)g.H * g.W;
+    if (kz) {
+        // amplitude + i phase, 3-D transform, weight, inverse, back
+        const size_t n = (size_t)g.S * HW;
+        float2* buf[2] = {at<float2>(c, c->L.kz), at<float2>(c, c->L.kz) + n};
+        hipLaunchKernelGGL(k_kz_pack, dim3(grid_for(n)), dim3(256), 0, st, amp, phase, n, buf[0]);
+        const Axis axes[3] = {
+            {g.W, (size_t)g.S * g.H, 1, 1, (size_t)g.W, 0, 0},        // x: rows of W
+            {g.H, (size_t)g.S * g.W, (size_t)g.W, (size_t)g.W, HW, 1, 1},   // y: columns, lines = (s, x)
+            {g.S, HW, HW, HW, 0, 1, 1}};                                   // z: depth columns, lines = (y, x)
+        int cur = 0;
+        for (int dir = 0; dir < 2; ++dir) {
+            const float sign = dir == 0 ? -1.f : 1.f;
+            for (int ax = 0; ax < 3; ++ax) {
+                const Axis& A = axes[ax];
+                int Ns = 1;
+                for (int k = 0; k < nrad[ax]; ++k) {
+                    const int R = rad[ax][k];
+                    const size_t total = A.lines * (size_t)(A.n / R);
+                    const dim3 grid(grid_for(total)), blk(256);
+                    const float2* sp = buf[cur];
+                    float2* dp = buf[cur ^ 1];
+                    switch (R) {
+                        case 2: hipLaunchKernelGGL(k_fft_pass<2>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                        case 3: hipLaunchKernelGGL(k_fft_pass<3>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                        case 4: hipLaunchKernelGGL(k_fft_pass<4>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                        case 5: hipLaunchKernelGGL(k_fft_pass<5>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                        default: hipLaunchKernelGGL(k_fft_pass<8>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                    }
+                    cur ^= 1;
+                    Ns *= R;
+                }
+            }
+            if (dir == 0)
+                hipLaunchKernelGGL(k_kz_weight, dim3(grid_for(n)), dim3(256), 0, st, buf[cur], g.S, g.H, g.W,
+                                   (double)cfg->kz_beta, (double)cfg->kz_alpha, g.dx, (double)cfg->kz_dz);
+        }
+        hipLaunchKernelGGL(k_kz_unpack, dim3(grid_for(n)), dim3(256), 0, st, buf[cur], n, amp, phase);
+    }
     if (rz && g.S > 1) {
         // taps in double, normalised, then rounded (the same on every call)
         RzTaps t;

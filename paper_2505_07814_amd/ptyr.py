@@ -207,16 +207,18 @@ class Engine:
 
 
     def constrain(self, amp=None, phase=None, probe=None, rz_sigma=0.0, phase_positive=False,
-                  probe_orthogonal=False):
+                  probe_orthogonal=False, kz_beta=0.0, kz_alpha=0.0, kz_dz=0.0):
         """Per-iteration constraints in place (include/ptyr.h, ptyr_constrain):
-        r_z depth filter of amplitude and phase (rz_sigma slices), clipping of
+        k_z filter (kz_beta, kz_alpha in angstrom^2, slice spacing kz_dz) and
+        r_z depth filter (rz_sigma slices) of amplitude and phase, clipping of
         negative phase, orthogonalisation of the probe modes."""
         for t, n, dt in ((amp, "amp", torch.float32), (phase, "phase", torch.float32)):
             if t is not None:
                 _need(t, n, dt, (self.S, self.H, self.W), self.device)
         if probe is not None:
             _need(probe, "probe", torch.complex64, (self.M, self.N, self.N), self.device)
-        cfg = L.Constraints(float(rz_sigma), int(bool(phase_positive)), int(bool(probe_orthogonal)))
+        cfg = L.Constraints(float(rz_sigma), int(bool(phase_positive)), int(bool(probe_orthogonal)),
+                            float(kz_beta), float(kz_alpha), float(kz_dz))
         L.check(self.lib.ptyr_constrain(self._ctx, _ptr(amp), _ptr(phase), _ptr(probe), C.byref(cfg)),
                 "ptyr_constrain")
 

@@ -172,3 +172,69 @@ def test_bad_arguments_are_rejected():
     big = Engine(64, 25, 1, 64, 64, 1, 0.2, 0.02, device=DEV)
     with pytest.raises(L.PtyrError):
         big.constrain(probe=torch.zeros((25, 64, 64), dtype=torch.complex64, device=DEV), probe_orthogonal=True)
+
+
+def rel(a, b):
+    a, b = np.ravel(np.asarray(a, np.float64)), np.ravel(np.asarray(b, np.float64))
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("S,H,W", [(12, 80, 75), (1, 64, 90), (30, 72, 72), (6, 64, 64)])
+def test_kz_filter_matches_oracle(S, H, W):
+    """Mixed-radix 3-D transform, weight, inverse: relative L2 <= 1e-5 of the
+    oracle for each field (float transforms of ~log2(SHW) stages each way)."""
+    print(f"kz filter {S}x{H}x{W}", flush=True)
+    rng = np.random.default_rng(S + H + W)
+    amp = rng.uniform(0.5, 1.5, (S, H, W)).astype(np.float32)
+    ph = rng.uniform(-0.5, 1.0, (S, H, W)).astype(np.float32)
+    eng = Engine(64, 1, S, H, W, 1, 0.2, 0.02, device=DEV)
+    a, p = T(amp), T(ph)
+    eng.constrain(a, p, kz_beta=0.8, kz_alpha=0.5, kz_dz=5.0)
+    eng.sync()
+    ra = oc.kz_filter(amp, 0.8, 0.5, 0.2, 5.0)
+    rp = oc.kz_filter(ph, 0.8, 0.5, 0.2, 5.0)
+    ea, ep = rel(a.cpu().numpy(), ra), rel(p.cpu().numpy(), rp)
+    print(f"rel-L2 amp {ea:.2e} phase {ep:.2e}", flush=True)
+    assert ea <= 1e-5 and ep <= 1e-5
+
+
+def test_kz_filter_full_object():
+    """The 12 x 640 x 640 object of the N=128 workload (640 = 5 x 2^7)."""
+    S, H = 12, 640
+    rng = np.random.default_rng(21)
+    ph = rng.uniform(-0.2, 1.0, (S, H, H)).astype(np.float32)
+    amp = np.ones((S, H, H), np.float32)
+    eng = Engine(128, 1, S, H, H, 1, 0.15, 0.02, device=DEV)
+    a, p = T(amp), T(ph)
+    eng.constrain(a, p, kz_beta=0.1, kz_alpha=1.0, kz_dz=20.0)
+    eng.sync()
+    assert rel(p.cpu().numpy(), oc.kz_filter(ph, 0.1, 1.0, 0.15, 20.0)) <= 1e-5
+    assert np.allclose(a.cpu().numpy(), 1.0, atol=1e-5)        # a constant is kept (W_a(0) = 1)
+
+
+def test_all_constraints_in_order():
+    S, H, W = 12, 64, 80
+    rng = np.random.default_rng(23)
+    amp = rng.uniform(0.5, 1.5, (S, H, W)).astype(np.float32)
+    ph = rng.uniform(-0.5, 1.0, (S, H, W)).astype(np.float32)
+    P = _modes(3, 64, 24, [1.0, 1.5, 2.0])
+    eng = Engine(64, 3, S, H, W, 1, 0.2, 0.02, device=DEV)
+    a, p, pr = T(amp), T(ph), T(P)
+    cfg = dict(rz_sigma=1.0, phase_positive=True, probe_orthogonal=True, kz_beta=0.5, kz_alpha=0.2)
+    eng.constrain(a, p, pr, kz_dz=4.0, **cfg)
+    eng.sync()
+    ra, rp, _ = oc.apply(amp, ph, None, dx=0.2, dz=4.0, **dict(cfg, probe_orthogonal=False))
+    assert rel(a.cpu().numpy(), ra) <= 1e-5 and rel(p.cpu().numpy(), rp) <= 1e-5
+    assert np.all(p.cpu().numpy() >= 0)
+
+
+def test_kz_bad_arguments():
+    eng = Engine(64, 1, 3, 70, 64, 1, 0.2, 0.02, device=DEV)          # 70 = 2 x 5 x 7
+    a = torch.ones((3, 70, 64), device=DEV)
+    with pytest.raises(L.PtyrError):
+        eng.constrain(a, a.clone(), kz_beta=1.0, kz_dz=5.0)
+    eng2 = engine(3, 64, 64)
+    b = torch.ones((3, 64, 64), device=DEV)
+    for kw in (dict(kz_beta=1.0, kz_dz=0.0), dict(kz_beta=-1.0, kz_dz=1.0), dict(kz_alpha=1.0, kz_dz=-2.0)):
+        with pytest.raises(L.PtyrError):
+            eng2.constrain(b, b.clone(), **kw)
