@@ -145,10 +145,16 @@ def forward_one(O, Phat, rho, tilt, dz, dx, lam):
 def forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=False):
     """Model intensities for a batch of positions, fftshifted, (B,N,N) float64.
 
-    amp, phase: (S,H,W); probe: (M,N,N) complex; pos, tilt: (B,2) (y,x);
-    dz, dx in angstrom; lam in angstrom."""
+    amp, phase: (S,H,W), or (n_obj,S,H,W) for mixed object modes (Eq. 2: the
+    intensity sums incoherently over probe and object modes); probe: (M,N,N)
+    complex; pos, tilt: (B,2) (y,x); dz, dx in angstrom; lam in angstrom.
+    With object modes the traces are per mode: traces[o][j]."""
     amp = np.asarray(amp, np.float64)
     phase = np.asarray(phase, np.float64)
+    if amp.ndim == 4:
+        outs = [forward(amp[o], phase[o], probe, pos, tilt, dz, dx, lam, True) for o in range(amp.shape[0])]
+        total = np.sum([o_[0] for o_ in outs], axis=0)
+        return (total, [o_[1] for o_ in outs]) if return_trace else total
     probe = np.asarray(probe, np.complex128)
     pos = np.asarray(pos, np.float64)
     tilt = np.asarray(tilt, np.float64)
@@ -280,10 +286,33 @@ def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian"
     pos = np.asarray(pos, np.float64)
     tilt = np.asarray(tilt, np.float64)
     dz, dx, lam = float(dz), float(dx), float(lam)   # every scalar in float64
-    S, Hh, Ww = amp.shape
-    M, N, _ = probe.shape
     I_model, traces = forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=True)
     L, dI = loss(I_model, I_meas, kind, p, pacbed_w=pacbed_w)
+    if amp.ndim == 4:
+        # I = sum over object modes: each mode's adjoint takes the same dL/dI;
+        # the probe, position, tilt and dz gradients add over the modes
+        parts = [_adjoint(amp[o], phase[o], probe, pos, tilt, dz, dx, lam, dI, traces[o])
+                 for o in range(amp.shape[0])]
+        g_amp = np.stack([q[0] for q in parts])
+        g_phase = np.stack([q[1] for q in parts])
+        G_probe, g_pos, g_tilt = (sum(q[k] for q in parts) for k in (2, 3, 4))
+        g_dz = sum(q[5] for q in parts)
+    else:
+        g_amp, g_phase, G_probe, g_pos, g_tilt, g_dz = _adjoint(amp, phase, probe, pos, tilt, dz, dx, lam, dI,
+                                                                traces)
+    if sparse_w:
+        S_all = phase.reshape(-1, *phase.shape[-2:])
+        Ls, gs = sparse_term(S_all, pos, probe.shape[-1])
+        L = L + sparse_w * Ls
+        g_phase = g_phase + sparse_w * gs.reshape(phase.shape)
+    return Gradients(g_amp, g_phase, G_probe, g_pos, g_tilt, float(g_dz), L)
+
+
+def _adjoint(amp, phase, probe, pos, tilt, dz, dx, lam, dI, traces):
+    """Gradients of one object mode (S,H,W) given dL/dI (fftshifted) and the
+    forward traces: (g_amp, g_phase, G_probe, g_pos, g_tilt, g_dz)."""
+    S, Hh, Ww = amp.shape
+    M, N, _ = probe.shape
     O = transmission(amp, phase)
     Phat = fft2(probe)
     ky, kx = kgrid(N, dx)
@@ -327,11 +356,7 @@ def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian"
     G_probe = ifft2(G_Phat)                                 # Phat = F P
     g_amp = np.real(np.conj(G_O) * np.exp(1j * phase))      # O = a e^{i phi}
     g_phase = np.imag(G_O * np.conj(O))
-    if sparse_w:
-        Ls, gs = sparse_term(phase, pos, N)
-        L = L + sparse_w * Ls
-        g_phase = g_phase + sparse_w * gs
-    return Gradients(g_amp, g_phase, G_probe, g_pos, g_tilt, float(g_dz), L)
+    return g_amp, g_phase, G_probe, g_pos, g_tilt, float(g_dz)
 
 
 def loss_of(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian", p=None, sparse_w=0.0,
@@ -340,7 +365,8 @@ def loss_of(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian", 
     I = forward(amp, phase, probe, pos, tilt, dz, dx, lam)
     L = loss(I, I_meas, kind, p, pacbed_w=pacbed_w)[0]
     if sparse_w:
-        L += sparse_w * sparse_term(phase, pos, probe.shape[-1])[0]
+        ph = np.asarray(phase, np.float64)
+        L += sparse_w * sparse_term(ph.reshape(-1, *ph.shape[-2:]), pos, probe.shape[-1])[0]
     return L
 
 
