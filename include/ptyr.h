@@ -95,11 +95,17 @@ typedef struct {
                                  <I_meas>_B^p over <I_meas^p>_{D,B}, the same p as the
                                  data term); 0 = off.  It couples the rows of a batch, so
                                  with it a batch runs on one stream */
+    int n_obj;                /* object modes (Sec. "Physical model", mixed-state formalism,
+                                 Eq. 2): amplitude and
+                                 phase hold n_obj stacks of S x H x W, object mode o is
+                                 transmitted with every probe mode and the model
+                                 intensity sums over all M x n_obj pairs; 0 or 1 = one
+                                 object, at most 64 */
 } ptyr_geom;
 
 /* Parameters of one reconstruction and their Adam moments (all device). */
 typedef struct {
-    float *amp, *phase;       /* S x H x W */
+    float *amp, *phase;       /* n_obj x S x H x W */
     float *probe;             /* M x N x N complex */
     float *pos;               /* n_pos x 2 (y, x) */
     float *tilt;              /* n_pos x 2, or 2 with PTYR_GLOBAL_TILT */
@@ -162,7 +168,7 @@ void ptyr_destroy(ptyr_ctx* ctx);
  * PTYR_E_DEVICE.  Clears the device flags. */
 ptyr_status ptyr_sync(ptyr_ctx* ctx);
 
-/* Forward model, Eq. 1-4 (a_s, phase_s: S x H x W; probe: M x N x N complex;
+/* Forward model, Eq. 1-4 (a_s, phase_s: n_obj x S x H x W; probe: M x N x N complex;
  * pos: rows x 2; tilt: rows x 2 or 2 (global); dz: 1 float).  Writes the
  * fftshifted intensities I_out (B x N x N).  idx (nullable, B device ints)
  * selects rows idx[b] (0 <= idx[b] < n_rows) of pos/tilt for batch row b;
@@ -190,7 +196,7 @@ ptyr_status ptyr_loss(ptyr_ctx* ctx, const float* I_model, const float* I_meas,
  * itself unless flags has PTYR_REUSE_FORWARD.  idx (nullable, B device ints in
  * [0, n_rows)) selects rows of pos/tilt/I_meas and the rows of g_pos/g_tilt
  * that receive the gradient; the rows of one batch must be distinct.
- * Gradients accumulate (+=): g_amp, g_phase S x H x W; g_probe M x N x N
+ * Gradients accumulate (+=): g_amp, g_phase n_obj x S x H x W; g_probe M x N x N
  * complex; g_pos, g_tilt like pos, tilt; g_dz 1.  Any gradient pointer may be
  * NULL to skip it.  loss_dev (nullable) receives the batch loss. */
 ptyr_status ptyr_adjoint(ptyr_ctx* ctx, const float* amp, const float* phase,
@@ -244,7 +250,8 @@ typedef struct {
 } ptyr_constraints;
 
 /* Apply the constraints in place on the context's stream: amp, phase
- * (S x H x W), probe (M x N x N complex); the pointer of a constraint that is
+ * (n_obj x S x H x W; the filters act on each object mode's stack on its
+ * own), probe (M x N x N complex); the pointer of a constraint that is
  * off may be NULL.  PTYR_E_ARG for rz_sigma outside [0, 16], S > 256 with the
  * r_z filter, M > 24 with probe_orthogonal, negative k_z parameters, kz_dz <= 0
  * or a side with another prime factor with the k_z filter, or a needed NULL

@@ -22,7 +22,7 @@ class Geom(C.Structure):
                 ("B_max", C.c_int), ("dx", C.c_double), ("lam", C.c_double),
                 ("loss_kind", C.c_int), ("loss_p", C.c_double),
                 ("wave_budget_bytes", C.c_size_t), ("flags", C.c_uint), ("n_scan", C.c_int),
-                ("sparse_w", C.c_double), ("pacbed_w", C.c_double)]
+                ("sparse_w", C.c_double), ("pacbed_w", C.c_double), ("n_obj", C.c_int)]
 
 
 _fp = C.c_void_p

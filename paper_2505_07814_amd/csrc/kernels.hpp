@@ -43,7 +43,9 @@ struct WaveArgs {
     int keep;              // KEEP_FULL / KEEP_CKPT
     int ckK;               // checkpoint spacing (CKPT)
     int nck;               // checkpoints per chain (CKPT)
-    int B, M, S, H, W;
+    int B, M, S, H, W;     // M: chain modes per row (probe modes x object modes)
+    int Mp;                // probe modes: chain mode e uses probe mode e % Mp and object mode e / Mp
+    size_t ostride;        // object-mode stride of Oc (S x H x W)
     int chain0;            // first chain (row * M + mode) of this launch; block b handles chain0 + b
     double dx, lam;
     int global_tilt;
@@ -53,6 +55,14 @@ struct WaveArgs {
     float2* gPhat;         // B x M x N x N probe-spectrum gradients
     float* part;           // B x M x 8 scalar partial sums
 };
+
+// probe spectrum and object transmission (all slices) of chain mode e
+__device__ __forceinline__ const float2* chain_probe(const WaveArgs& a, int e, int NN) {
+    return a.Phat + (size_t)(e % a.Mp) * NN;
+}
+__device__ __forceinline__ const float2* chain_object(const WaveArgs& a, int e) {
+    return a.Oc + (size_t)(e / a.Mp) * a.ostride;
+}
 
 // Wave slots of one chain in the store.
 template <int N> struct Slots {
@@ -246,14 +256,15 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     const bool ckpt = KEEP == KEEP_CKPT && a.ckK <= a.S;
     const size_t HW = (size_t)a.H * a.W;
 
+    const float2* Ocm = chain_object(a, m);
     float2 v[16];
-    shift_probe<N>(v, a.Phat + (size_t)m * N * N, lds, tab, l, c);
+    shift_probe<N>(v, chain_probe(a, m, N * N), lds, tab, l, c);
     for (int s = 0; s < a.S - 1; ++s) {
         // the object patch is read before phi_s is written: waiting for the
         // reads then does not also wait for those writes (one in-order
         // counter covers both)
         float2 ov[16];
-        load_patch<N>(ov, a.Oc + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
+        load_patch<N>(ov, Ocm + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
         // chi_s is formed before phi_s is written: waiting for the patch then
         // cannot wait for those (conditional) writes as well
 #pragma unroll
@@ -270,7 +281,7 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     const int s = a.S - 1;
     if (full) wstore<N, COL, NAT>(v, sl.phi(s), N, l, c);
     else if (ckpt && s % a.ckK == 0) wstore<N, COL, NAT>(v, sl.ckpt(s / a.ckK), N, l, c);
-    transmit<N>(v, a.Oc + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
+    transmit<N>(v, Ocm + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
     fft2_from_col<N>(v, lds, tab.tw, l, c);
     if (full) wstore<N, ROW, MID>(v, sl.far(), N, l, c);
     // far field |F chi|^2 / N^2 (zero frequency at (0, 0); the mode sum shifts it)
@@ -294,11 +305,12 @@ __device__ __forceinline__ void recompute_phi(float2 (&v)[16], int s, const Wave
         s0 = s > 0 ? ((s - 1) / a.ckK) * a.ckK : 0;
         wload<N, COL, NAT>(v, sl.ckpt(s0 / a.ckK), N, l, c);
     } else {
-        shift_probe<N>(v, a.Phat + (size_t)m * N * N, lds, t, l, c);
+        shift_probe<N>(v, chain_probe(a, m, N * N), lds, t, l, c);
     }
     const size_t HW = (size_t)a.H * a.W;
+    const float2* Ocm = chain_object(a, m);
     for (int u = s0; u < s; ++u)
-        slice_step<N>(v, a.Oc + (size_t)u * HW, a.W, ty, tx, u == s - 1 ? spec : nullptr, lds, t, l, c);
+        slice_step<N>(v, Ocm + (size_t)u * HW, a.W, ty, tx, u == s - 1 ? spec : nullptr, lds, t, l, c);
 }
 
 // Gradient: one workgroup per (batch row j, probe mode m).  Walks the slices
@@ -336,7 +348,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
         wload<N, ROW, MID>(g, sl.far(), N, l, c);
     } else {
         recompute_phi<N>(g, a.S - 1, a, sl, m, pi.ty, pi.tx, sl.sc_spec(), lds, tab, l, c);
-        transmit<N>(g, a.Oc + (size_t)(a.S - 1) * HW, a.W, pi.ty, pi.tx, l, c);
+        transmit<N>(g, chain_object(a, m) + (size_t)(a.S - 1) * HW, a.W, pi.ty, pi.tx, l, c);
         fft2_from_col<N>(g, lds, tab.tw, l, c);
     }
     {   // G_chi_{S-1} = F^-1[ w F[chi_{S-1}] ]   (w = 2 dL/dI)
@@ -369,7 +381,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
             phi_s = sl.sc_phi();
             Y_s = sl.sc_spec();
         }
-        const float2* Os = a.Oc + (size_t)s * HW + (size_t)pi.ty * a.W + pi.tx;
+        const float2* Os = chain_object(a, m) + (size_t)s * HW + (size_t)pi.ty * a.W + pi.tx;
         float2* go = a.gO + ((size_t)(j * a.M + m) * a.S + s) * N * N;
         // The reads of each half are issued before its writes: the
         // patch-gradient writes could alias the reads as far as the compiler
@@ -423,7 +435,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     // probe spectrum and position: phi_0 = F^-1[Phat R]
     float acc_py = 0.f, acc_px = 0.f;
     {
-        const float2* Pm = a.Phat + (size_t)m * N * N;
+        const float2* Pm = chain_probe(a, m, N * N);
         const float2 ry = tab.ry[l];
         const float qy = (float)sfreq<N>(l) * inv_n;
 #pragma unroll

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
     rows_load(v, w, y, c);
     // the object patch is read now, so that its latency overlaps the line DFT
     // (three workgroups per CU by LDS leave room for the extra registers)
-    const float2* Os = a.Oc + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
+    const float2* Os = chain_object(a, ch % a.M) + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
 #pragma unroll
     for (int r = 0; r < 16; ++r) ov[r] = Os[c + 16 * r];
     if (P.s == 0) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k256_fwd_col(Pass256 P) {
     float2* w = P.wave + (size_t)ch * N256 * N256;
     float2 v[16];
     if (P.s < 0) {
-        cols_load(v, a.Phat + (size_t)m * N256 * N256, x, c);
+        cols_load(v, chain_probe(a, m, N256 * N256), x, c);
         const float sc = 1.0f / N256;
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = cscale(cmul(v[r], tab.r[c + 16 * r]), sc);
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
         mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
         cols_store(v, w, x, c);
     } else {
-        const float2* Pm = a.Phat + (size_t)m * N256 * N256;
+        const float2* Pm = chain_probe(a, m, N256 * N256);
         float2* gP = a.gPhat + (size_t)ch * N256 * N256;
         const float2 rx = tab.rl[l];
         const float qx = (float)sfreq<N256>(x) * inv_n;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
     // phi_s and the object patch are read now, so that their latency
     // overlaps the line DFT
     rows_load(ph, sl.phi(P.s), y, c);
-    const float2* Os = a.Oc + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
+    const float2* Os = chain_object(a, ch % a.M) + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
 #pragma unroll
     for (int r = 0; r < 16; ++r) ov[r] = Os[c + 16 * r];
     mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                      // G_chi_s (space)

@@ -284,11 +284,12 @@ struct ObjAdam {
 constexpr int SCATTER_MB = 8;
 template <bool FUSE>
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int j0, int j1, int M,
-                                                        int S, int N, int H, int W, const float* amp,
+                                                        int Mc, int S, int N, int H, int W, const float* amp,
                                                         const float* phase, const double* scale, float* g_amp,
                                                         float* g_phase, ObjAdam ad, float sp) {
     const int ntx = (W + 31) / 32;
-    const int tile = blockIdx.x, s = blockIdx.y;
+    // blockIdx.y = o S + s: object mode o, slice s; chain modes o M .. o M + M - 1
+    const int tile = blockIdx.x, s = blockIdx.y % S, om = (blockIdx.y / S) * M;
     const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
     const int x = x0 + (int)threadIdx.x % 32, yb = y0 + (int)threadIdx.x / 32;
     float2 acc[4];
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
 #pragma unroll
             for (int mm = 0; mm < SCATTER_MB; ++mm) {
                 const int m = m0 + mm;
-                const float2* src = gO + ((size_t)(j * M + m) * S + s) * NN + px;
+                const float2* src = gO + ((size_t)(j * Mc + om + m) * S + s) * NN + px;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int py = yb + 8 * i - pi.ty;
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
     for (int i = 0; i < 4; ++i) {
         const int y = yb + 8 * i;
         if (y >= H) continue;
-        size_t o = ((size_t)s * H + y) * W + x;
+        size_t o = ((size_t)blockIdx.y * H + y) * W + x;
         float ga = 0.f, gp = 0.f;
         if (!FUSE || touched) {
             const float ph = phase[o];
@@ -560,6 +561,11 @@ __global__ void k_adam_segs(AdamSegs a, float b1, float b2, float eps, float bc1
 // ------------------------------------------------------------------ host helpers
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// object modes (0 in the geometry means one) and chain modes per batch row
+// (every probe mode with every object mode)
+int obj_modes(const ptyr_geom& g) { return g.n_obj > 0 ? g.n_obj : 1; }
+int chain_modes(const ptyr_geom& g) { return g.M * obj_modes(g); }
+
 struct Layout {
     size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, spart, pac, err, store, gO, gPhat, gPsum, part, gamp, gphase,
         gprobe, gdz, gpos, gtilt, wave, cons, rzmat, kz, total;
@@ -571,7 +577,7 @@ struct Layout {
 // else a 3-wave scratch plus checkpoints of phi every K >= 2 slices; with no
 // room for a checkpoint, K = S + 1 (recompute from the probe).
 void keep_plan(const ptyr_geom* g, int* keep, int* K, int* nck) {
-    size_t per = (size_t)g->B_max * g->M * g->N * g->N * sizeof(float2);
+    size_t per = (size_t)g->B_max * chain_modes(*g) * g->N * g->N * sizeof(float2);
     size_t fit = g->wave_budget_bytes / per;
     if (fit >= (size_t)(2 * g->S)) { *keep = KEEP_FULL; *K = 1; *nck = 0; return; }
     *keep = KEEP_CKPT;
@@ -592,33 +598,34 @@ int checkpoint_stride(const ptyr_geom* g) {
 Layout make_layout(const ptyr_geom* g) {
     Layout L;
     const size_t NN = (size_t)g->N * g->N, HW = (size_t)g->H * g->W, B = g->B_max, M = g->M, S = g->S;
+    const size_t Mc = chain_modes(*g), OS = obj_modes(*g) * S;     // chain modes; object slices of all modes
     keep_plan(g, &L.keep, &L.ckK, &L.nck);
     L.waves_per_chain = L.keep == KEEP_FULL ? 2 * g->S : L.nck + 3;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    L.Oc = take(S * HW * sizeof(float2));
+    L.Oc = take(OS * HW * sizeof(float2));
     L.Phat = take(M * NN * sizeof(float2));
     L.pinfo = take(B * sizeof(PosInfo));
-    L.Imode = take(B * M * NN * sizeof(float));
+    L.Imode = take(B * Mc * NN * sizeof(float));
     L.Ibuf = take(B * NN * sizeof(float));
     L.wbuf = take(B * NN * sizeof(float));
     L.lpart = take(2 * 3 * NPART * sizeof(double));   // one block of NPART per row range
     L.scal = take(8 * sizeof(double));
-    L.spart = take(B * S * sizeof(double));           // sparsity-term partial sums
+    L.spart = take(B * OS * sizeof(double));           // sparsity-term partial sums
     L.pac = take(2 * NN * sizeof(double) + PAC_BLOCKS * sizeof(double));   // PACBED R, Abar; partial sums
     L.err = take(sizeof(int));
-    L.store = take(B * M * (size_t)L.waves_per_chain * NN * sizeof(float2));
-    L.gO = take(B * M * S * NN * sizeof(float2));
-    L.gPhat = take(B * M * NN * sizeof(float2));
+    L.store = take(B * Mc * (size_t)L.waves_per_chain * NN * sizeof(float2));
+    L.gO = take(B * Mc * S * NN * sizeof(float2));
+    L.gPhat = take(B * Mc * NN * sizeof(float2));
     L.gPsum = take(M * NN * sizeof(float2));
-    L.part = take(B * M * (g->N == 256 ? NBLK256 : 1) * 8 * sizeof(float));
-    L.gamp = take(S * HW * sizeof(float));
-    L.gphase = take(S * HW * sizeof(float));
+    L.part = take(B * Mc * (g->N == 256 ? NBLK256 : 1) * 8 * sizeof(float));
+    L.gamp = take(OS * HW * sizeof(float));
+    L.gphase = take(OS * HW * sizeof(float));
     L.gprobe = take(M * NN * sizeof(float2));
     L.gdz = take(sizeof(float));
     L.gpos = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
     L.gtilt = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
-    L.wave = take(g->N == 256 ? B * M * NN * sizeof(float2) : 0);
+    L.wave = take(g->N == 256 ? B * Mc * NN * sizeof(float2) : 0);
     // probe orthogonalisation: partial overlap sums (double complex), mixing
     // matrix (float complex), eigenvalues
     L.cons = take((size_t)ORTH_MAX_M * (ORTH_MAX_M + 1) / 2 * GRAM_MAX_CHUNKS * sizeof(cd) +
@@ -703,7 +710,8 @@ ptyr_status ptyr_check_geom(const ptyr_geom* g) {
     if (!(g->loss_p > 0.0) || !isfinite(g->loss_p)) return PTYR_E_ARG;
     if (g->flags & ~(PTYR_GLOBAL_TILT | PTYR_CHECK_FINITE)) return PTYR_E_ARG;
     // grid and index limits of the kernels
-    if ((double)g->B_max * g->M > 2147483647.0 / 2) return PTYR_E_ARG;
+    if (g->n_obj < 0 || g->n_obj > 64) return PTYR_E_ARG;
+    if ((double)g->B_max * g->M * (g->n_obj > 0 ? g->n_obj : 1) > 2147483647.0 / 2) return PTYR_E_ARG;
     if (g->n_scan < 0) return PTYR_E_ARG;
     if (!(g->sparse_w >= 0.0) || !isfinite(g->sparse_w)) return PTYR_E_ARG;
     if (!(g->pacbed_w >= 0.0) || !isfinite(g->pacbed_w)) return PTYR_E_ARG;
@@ -859,7 +867,9 @@ WaveArgs wave_args(ptyr_ctx* c, const float* tilt, const float* dz, int B) {
     a.keep = c->L.keep;
     a.ckK = c->L.ckK;
     a.nck = c->L.nck;
-    a.B = B; a.M = g.M; a.S = g.S; a.H = g.H; a.W = g.W;
+    a.B = B; a.M = chain_modes(g); a.S = g.S; a.H = g.H; a.W = g.W;
+    a.Mp = g.M;
+    a.ostride = (size_t)g.S * g.H * g.W;
     a.chain0 = 0;
     a.dx = g.dx;
     a.lam = g.lambda;
@@ -943,7 +953,7 @@ void prepare_forward(ptyr_ctx* c, const float* amp, const float* phase, const fl
                      const int* idx, int n_rows, int B) {
     const hipStream_t st = c->stream;
     const ptyr_geom& g = c->g;
-    size_t nobj = (size_t)g.S * g.H * g.W;
+    size_t nobj = (size_t)obj_modes(g) * g.S * g.H * g.W;
     hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, st, amp, phase,
                        at<float2>(c, c->L.Oc), nobj);
     hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, st, pos, idx, idx ? n_rows : B, B, g.N, g.H,
@@ -963,14 +973,14 @@ void modesum_rows(ptyr_ctx* c, int r0, int nr, hipStream_t st) {
     const ptyr_geom& g = c->g;
     const size_t NN = (size_t)g.N * g.N;
     hipLaunchKernelGGL(k_modesum, dim3(grid_for((size_t)nr * NN)), dim3(256), 0, st,
-                       at<float>(c, c->L.Imode) + (size_t)r0 * g.M * NN, at<float>(c, c->L.Ibuf) + (size_t)r0 * NN,
-                       nr, g.M, g.N);
+                       at<float>(c, c->L.Imode) + (size_t)r0 * chain_modes(g) * NN,
+                       at<float>(c, c->L.Ibuf) + (size_t)r0 * NN, nr, chain_modes(g), g.N);
 }
 
 ptyr_status run_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
                         const float* tilt, const float* dz, const int* idx, int n_rows, int B) {
     prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
-    forward_chains(c, wave_args(c, tilt, dz, B), 0, B * c->g.M, c->stream);
+    forward_chains(c, wave_args(c, tilt, dz, B), 0, B * chain_modes(c->g), c->stream);
     modesum_rows(c, 0, B, c->stream);
     if (hipGetLastError() != hipSuccess) return PTYR_E_DEVICE;
     c->fwd_valid = 1;
@@ -985,8 +995,9 @@ ptyr_status run_forward(ptyr_ctx* c, const float* amp, const float* phase, const
 void loss_rows(ptyr_ctx* c, const float* Ie, const int* midx, int nm, int r0, int nr, int slot, hipStream_t st) {
     const ptyr_geom& g = c->g;
     const size_t NN = (size_t)g.N * g.N;
-    hipLaunchKernelGGL(k_loss_rows, dim3(NPART), dim3(256), 0, st, at<float>(c, c->L.Imode) + (size_t)r0 * g.M * NN,
-                       at<float>(c, c->L.Ibuf) + (size_t)r0 * NN, Ie, midx ? midx + r0 : nullptr, nm, nr, g.M, g.N,
+    hipLaunchKernelGGL(k_loss_rows, dim3(NPART), dim3(256), 0, st,
+                       at<float>(c, c->L.Imode) + (size_t)r0 * chain_modes(g) * NN, at<float>(c, c->L.Ibuf) + (size_t)r0 * NN,
+                       Ie, midx ? midx + r0 : nullptr, nm, nr, chain_modes(g), g.N,
                        g.loss_kind, g.loss_p, r0, at<double>(c, c->L.lpart) + 3 * (size_t)slot * NPART,
                        at<float>(c, c->L.wbuf) + (size_t)r0 * NN, at<int>(c, c->L.err));
 }
@@ -999,8 +1010,8 @@ void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev, hipStream_t st
     const bool sp = with_sparse && g.sparse_w > 0.0;
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, at<double>(c, c->L.lpart), nslots * NPART, n,
                        g.loss_kind, (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
-                       at<int>(c, c->L.err), at<double>(c, c->L.spart), sp ? B * g.S : 0,
-                       sp ? g.sparse_w / ((double)B * g.S * g.N * g.N) : 0.0);
+                       at<int>(c, c->L.err), at<double>(c, c->L.spart), sp ? B * g.S * obj_modes(g) : 0,
+                       sp ? g.sparse_w / ((double)B * g.S * obj_modes(g) * g.N * g.N) : 0.0);
 }
 
 // PACBED term of a batch (after loss_final): adds it to the loss and its
@@ -1052,8 +1063,9 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
 // queued behind pending workgroups.  Returns n_cu (0: no split).
 int split_chains(const ptyr_ctx* c, int B) {
     const ptyr_geom& g = c->g;
-    if (g.N > 128 || c->n_cu <= 0 || B * g.M <= c->n_cu || g.pacbed_w > 0.0) return 0;
-    return c->n_cu / g.M >= 1 ? c->n_cu : 0;
+    const int Mc = chain_modes(g);
+    if (g.N > 128 || c->n_cu <= 0 || B * Mc <= c->n_cu || g.pacbed_w > 0.0) return 0;
+    return c->n_cu / Mc >= 1 ? c->n_cu : 0;
 }
 
 ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
@@ -1062,16 +1074,17 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
                         float* g_tilt, float* g_dz, double* loss_dev, unsigned flags,
                         const ObjAdam* fuse = nullptr) {
     const ptyr_geom& g = c->g;
-    const int M = g.M, nm = idx ? n_rows : B, BM = B * M;
+    const int M = chain_modes(g), nm = idx ? n_rows : B, BM = B * M;   // M: chain modes
     const bool reuse = (flags & PTYR_REUSE_FORWARD) && c->fwd_valid && c->fwd_B == B;
     const int nA = reuse ? 0 : split_chains(c, B);
     if (!reuse) prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
     // sparsity term: |phase| over the batch's patches, before any update of the phase
     const bool sparse = g.sparse_w > 0.0;
     if (sparse)
-        hipLaunchKernelGGL(k_sparse_partial, dim3(B, g.S), dim3(256), 0, c->stream, phase, at<PosInfo>(c, c->L.pinfo),
-                           g.S, g.N, g.H, g.W, at<double>(c, c->L.spart));
-    const float sp = sparse && g_phase ? (float)(g.sparse_w / ((double)B * g.S * g.N * g.N)) : 0.f;
+        hipLaunchKernelGGL(k_sparse_partial, dim3(B, g.S * obj_modes(g)), dim3(256), 0, c->stream, phase,
+                           at<PosInfo>(c, c->L.pinfo), g.S * obj_modes(g), g.N, g.H, g.W, at<double>(c, c->L.spart));
+    const float sp =
+        sparse && g_phase ? (float)(g.sparse_w / ((double)B * g.S * obj_modes(g) * g.N * g.N)) : 0.f;
     const WaveArgs a = wave_args(c, tilt, dz, B);
     const double* scale = at<double>(c, c->L.scal) + 1;     // the batch factor of w (after loss_final)
     // object-gradient scatter of batch rows [j0, j1) on stream st; `last`
@@ -1079,13 +1092,14 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     auto scatter = [&](int j0, int j1, hipStream_t st, bool last) {
         if (!(g_amp || g_phase)) return;
         const int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
+        const dim3 grid(ntiles, g.S * obj_modes(g));
         if (last && fuse) {
-            hipLaunchKernelGGL(k_scatter_object<true>, dim3(ntiles, g.S), dim3(256), 0, st, at<float2>(c, c->L.gO),
-                               at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W, amp, phase, scale,
+            hipLaunchKernelGGL(k_scatter_object<true>, grid, dim3(256), 0, st, at<float2>(c, c->L.gO),
+                               at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, M, g.S, g.N, g.H, g.W, amp, phase, scale,
                                g_amp, g_phase, *fuse, sp);
         } else if (j1 > j0) {
-            hipLaunchKernelGGL(k_scatter_object<false>, dim3(ntiles, g.S), dim3(256), 0, st,
-                               at<float2>(c, c->L.gO), at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, g.S, g.N, g.H, g.W,
+            hipLaunchKernelGGL(k_scatter_object<false>, grid, dim3(256), 0, st,
+                               at<float2>(c, c->L.gO), at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, M, g.S, g.N, g.H, g.W,
                                amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
         }
     };
@@ -1094,7 +1108,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         if (g_probe) {
             int NN = g.N * g.N;
             hipLaunchKernelGGL(k_sum_rows, dim3(grid_for((size_t)g.M * NN)), dim3(256), 0, st,
-                               at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B, g.M, NN, scale);
+                               at<float2>(c, c->L.gPhat), at<float2>(c, c->L.gPsum), B * obj_modes(g), g.M, NN, scale);
             if (g.N == 64) launch_probe_ifft_acc<64>(c, g_probe, st);
             else if (g.N == 128) launch_probe_ifft_acc<128>(c, g_probe, st);
             else {
@@ -1107,7 +1121,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         }
         if (g_pos || g_tilt || g_dz)
             hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(256), 0, st, at<float>(c, c->L.part),
-                               g.N == 256 ? NBLK256 : 1, at<PosInfo>(c, c->L.pinfo), B, g.M, tilt, a.global_tilt, dz,
+                               g.N == 256 ? NBLK256 : 1, at<PosInfo>(c, c->L.pinfo), B, M, tilt, a.global_tilt, dz,
                                g.lambda, scale, g_pos, g_tilt, g_dz);
     };
     int scattered = 0;                                       // rows already scattered
@@ -1250,81 +1264,87 @@ ptyr_status ptyr_constrain(ptyr_ctx* c, float* amp, float* phase, float* probe, 
     }
     const hipStream_t st = c->stream;
     const size_t HW = (size_t)g.H * g.W;
-    if (kz) {
-        // amplitude + i phase, 3-D transform, weight, inverse, back
-        const size_t n = (size_t)g.S * HW;
-        float2* buf[2] = {at<float2>(c, c->L.kz), at<float2>(c, c->L.kz) + n};
-        hipLaunchKernelGGL(k_kz_pack, dim3(grid_for(n)), dim3(256), 0, st, amp, phase, n, buf[0]);
-        const Axis axes[3] = {
-            {g.W, (size_t)g.S * g.H, 1, 1, (size_t)g.W, 0, 0},        // x: rows of W
-            {g.H, (size_t)g.S * g.W, (size_t)g.W, (size_t)g.W, HW, 1, 1},   // y: columns, lines = (s, x)
-            {g.S, HW, HW, HW, 0, 1, 1}};                                   // z: depth columns, lines = (y, x)
-        int cur = 0;
-        for (int dir = 0; dir < 2; ++dir) {
-            const float sign = dir == 0 ? -1.f : 1.f;
-            for (int ax = 0; ax < 3; ++ax) {
-                const Axis& A = axes[ax];
-                int Ns = 1;
-                for (int k = 0; k < nrad[ax]; ++k) {
-                    const int R = rad[ax][k];
-                    const size_t total = A.lines * (size_t)(A.n / R);
-                    const dim3 grid(grid_for(total)), blk(256);
-                    const float2* sp = buf[cur];
-                    float2* dp = buf[cur ^ 1];
-                    switch (R) {
-                        case 2: hipLaunchKernelGGL(k_fft_pass<2>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                        case 3: hipLaunchKernelGGL(k_fft_pass<3>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                        case 4: hipLaunchKernelGGL(k_fft_pass<4>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                        case 5: hipLaunchKernelGGL(k_fft_pass<5>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                        default: hipLaunchKernelGGL(k_fft_pass<8>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+    const int nob = obj_modes(g);
+    // every object mode is filtered on its own (S x H x W each)
+    for (int ob = 0; ob < nob; ++ob) {
+        float* const amp_o = amp ? amp + (size_t)ob * g.S * HW : nullptr;
+        float* const phase_o = phase ? phase + (size_t)ob * g.S * HW : nullptr;
+        if (kz) {
+            // amplitude + i phase, 3-D transform, weight, inverse, back
+            const size_t n = (size_t)g.S * HW;
+            float2* buf[2] = {at<float2>(c, c->L.kz), at<float2>(c, c->L.kz) + n};
+            hipLaunchKernelGGL(k_kz_pack, dim3(grid_for(n)), dim3(256), 0, st, amp_o, phase_o, n, buf[0]);
+            const Axis axes[3] = {
+                {g.W, (size_t)g.S * g.H, 1, 1, (size_t)g.W, 0, 0},        // x: rows of W
+                {g.H, (size_t)g.S * g.W, (size_t)g.W, (size_t)g.W, HW, 1, 1},   // y: columns, lines = (s, x)
+                {g.S, HW, HW, HW, 0, 1, 1}};                                   // z: depth columns, lines = (y, x)
+            int cur = 0;
+            for (int dir = 0; dir < 2; ++dir) {
+                const float sign = dir == 0 ? -1.f : 1.f;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const Axis& A = axes[ax];
+                    int Ns = 1;
+                    for (int k = 0; k < nrad[ax]; ++k) {
+                        const int R = rad[ax][k];
+                        const size_t total = A.lines * (size_t)(A.n / R);
+                        const dim3 grid(grid_for(total)), blk(256);
+                        const float2* sp = buf[cur];
+                        float2* dp = buf[cur ^ 1];
+                        switch (R) {
+                            case 2: hipLaunchKernelGGL(k_fft_pass<2>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                            case 3: hipLaunchKernelGGL(k_fft_pass<3>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                            case 4: hipLaunchKernelGGL(k_fft_pass<4>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                            case 5: hipLaunchKernelGGL(k_fft_pass<5>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                            default: hipLaunchKernelGGL(k_fft_pass<8>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
+                        }
+                        cur ^= 1;
+                        Ns *= R;
                     }
-                    cur ^= 1;
-                    Ns *= R;
+                }
+                if (dir == 0)
+                    hipLaunchKernelGGL(k_kz_weight, dim3(grid_for(n)), dim3(256), 0, st, buf[cur], g.S, g.H, g.W,
+                                       (double)cfg->kz_beta, (double)cfg->kz_alpha, g.dx, (double)cfg->kz_dz);
+            }
+            hipLaunchKernelGGL(k_kz_unpack, dim3(grid_for(n)), dim3(256), 0, st, buf[cur], n, amp_o, phase_o);
+        }
+        if (rz && g.S > 1) {
+            // taps in double, normalised, then rounded (the same on every call)
+            RzTaps t;
+            t.R = (int)ceil(4.0 * (double)cfg->rz_sigma);
+            double w[2 * RZ_MAX_R + 1], sum = 0.0;
+            for (int k = -t.R; k <= t.R; ++k) {
+                w[k + t.R] = exp(-(double)k * k / (2.0 * (double)cfg->rz_sigma * cfg->rz_sigma));
+                sum += w[k + t.R];
+            }
+            for (int k = 0; k <= 2 * t.R; ++k) t.w[k] = (float)(w[k] / sum);
+            float* fields[2] = {amp_o, phase_o};
+            if (g.S <= RZ_REG_S) {
+                float* Bm = at<float>(c, c->L.rzmat);
+                hipLaunchKernelGGL(k_rz_matrix, dim3((g.S * g.S + 255) / 256), dim3(256), 0, st, t, g.S, Bm);
+                const bool vec4 = HW % 4 == 0 && reinterpret_cast<uintptr_t>(amp_o) % 16 == 0 &&
+                                  reinterpret_cast<uintptr_t>(phase_o) % 16 == 0;
+                const dim3 grid((unsigned)((HW / (vec4 ? 4 : 1) + 255) / 256));
+                for (int f = 0; f < 2; ++f) {
+                    TimedLaunch tl(c, PTYR_K_RZ, st);
+                    const int pos = f == 1 && cfg->phase_positive ? 1 : 0;
+                    if (vec4) hipLaunchKernelGGL(k_rz_filter_reg4, grid, dim3(256), 0, st, fields[f], g.S, HW, Bm, pos);
+                    else hipLaunchKernelGGL(k_rz_filter_reg, grid, dim3(256), 0, st, fields[f], g.S, HW, Bm, pos);
+                }
+            } else {
+                const int T = rz_threads(g.S);
+                const dim3 grid((unsigned)((HW + T - 1) / T));
+                const size_t lds = (size_t)g.S * T * sizeof(float);
+                for (int f = 0; f < 2; ++f) {
+                    TimedLaunch tl(c, PTYR_K_RZ, st);
+                    hipLaunchKernelGGL(k_rz_filter, grid, dim3(T), lds, st, fields[f], g.S, HW, t,
+                                       f == 1 && cfg->phase_positive ? 1 : 0);
                 }
             }
-            if (dir == 0)
-                hipLaunchKernelGGL(k_kz_weight, dim3(grid_for(n)), dim3(256), 0, st, buf[cur], g.S, g.H, g.W,
-                                   (double)cfg->kz_beta, (double)cfg->kz_alpha, g.dx, (double)cfg->kz_dz);
         }
-        hipLaunchKernelGGL(k_kz_unpack, dim3(grid_for(n)), dim3(256), 0, st, buf[cur], n, amp, phase);
     }
-    if (rz && g.S > 1) {
-        // taps in double, normalised, then rounded (the same on every call)
-        RzTaps t;
-        t.R = (int)ceil(4.0 * (double)cfg->rz_sigma);
-        double w[2 * RZ_MAX_R + 1], sum = 0.0;
-        for (int k = -t.R; k <= t.R; ++k) {
-            w[k + t.R] = exp(-(double)k * k / (2.0 * (double)cfg->rz_sigma * cfg->rz_sigma));
-            sum += w[k + t.R];
-        }
-        for (int k = 0; k <= 2 * t.R; ++k) t.w[k] = (float)(w[k] / sum);
-        float* fields[2] = {amp, phase};
-        if (g.S <= RZ_REG_S) {
-            float* Bm = at<float>(c, c->L.rzmat);
-            hipLaunchKernelGGL(k_rz_matrix, dim3((g.S * g.S + 255) / 256), dim3(256), 0, st, t, g.S, Bm);
-            const bool vec4 = HW % 4 == 0 && reinterpret_cast<uintptr_t>(amp) % 16 == 0 &&
-                              reinterpret_cast<uintptr_t>(phase) % 16 == 0;
-            const dim3 grid((unsigned)((HW / (vec4 ? 4 : 1) + 255) / 256));
-            for (int f = 0; f < 2; ++f) {
-                TimedLaunch tl(c, PTYR_K_RZ, st);
-                const int pos = f == 1 && cfg->phase_positive ? 1 : 0;
-                if (vec4) hipLaunchKernelGGL(k_rz_filter_reg4, grid, dim3(256), 0, st, fields[f], g.S, HW, Bm, pos);
-                else hipLaunchKernelGGL(k_rz_filter_reg, grid, dim3(256), 0, st, fields[f], g.S, HW, Bm, pos);
-            }
-        } else {
-            const int T = rz_threads(g.S);
-            const dim3 grid((unsigned)((HW + T - 1) / T));
-            const size_t lds = (size_t)g.S * T * sizeof(float);
-            for (int f = 0; f < 2; ++f) {
-                TimedLaunch tl(c, PTYR_K_RZ, st);
-                hipLaunchKernelGGL(k_rz_filter, grid, dim3(T), lds, st, fields[f], g.S, HW, t,
-                                   f == 1 && cfg->phase_positive ? 1 : 0);
-            }
-        }
-    } else if (cfg->phase_positive) {
-        hipLaunchKernelGGL(k_clip_negative, dim3(grid_for((size_t)g.S * HW)), dim3(256), 0, st, phase,
-                           (size_t)g.S * HW);
-    }
+    if (!(rz && g.S > 1) && cfg->phase_positive)
+        hipLaunchKernelGGL(k_clip_negative, dim3(grid_for((size_t)nob * g.S * HW)), dim3(256), 0, st, phase,
+                           (size_t)nob * g.S * HW);
     if (cfg->probe_orthogonal && g.M > 1) {
         const int M = g.M, NN = g.N * g.N, nchunk = (NN + GRAM_CHUNK - 1) / GRAM_CHUNK;
         cd* part = at<cd>(c, c->L.cons);
@@ -1357,7 +1377,7 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
         return PTYR_E_ARG;
     const ptyr_geom& g = c->g;
     const bool gt = (g.flags & PTYR_GLOBAL_TILT) != 0;
-    const size_t nobj = (size_t)g.S * g.H * g.W, nprb = (size_t)g.M * g.N * g.N * 2;
+    const size_t nobj = (size_t)obj_modes(g) * g.S * g.H * g.W, nprb = (size_t)g.M * g.N * g.N * 2;
     const size_t npos = (size_t)p->n_pos * 2, ntilt = gt ? 2 : npos;
     float* gamp = at<float>(c, c->L.gamp);
     float* gphase = at<float>(c, c->L.gphase);

@@ -48,20 +48,23 @@ class Engine:
     slice from checkpoints.  n_scan: positions addressable by step()."""
 
     def __init__(self, N, M, S, H, W, B_max, dx, lam, loss="gaussian", p=None, wave_budget=None,
-                 global_tilt=False, check_finite=False, n_scan=0, sparse_w=0.0, pacbed_w=0.0, device=None,
-                 stream=None):
+                 global_tilt=False, check_finite=False, n_scan=0, sparse_w=0.0, pacbed_w=0.0, n_obj=1,
+                 device=None, stream=None):
         self.lib = L.lib()
         kind = {"gaussian": L.PTYR_LOSS_GAUSSIAN, "poisson": L.PTYR_LOSS_POISSON}[loss]
         if p is None:
             p = 0.5 if kind == L.PTYR_LOSS_GAUSSIAN else 1.0
         if wave_budget is None:
-            wave_budget = B_max * M * 2 * S * N * N * 8     # keep every slice's waves
+            wave_budget = B_max * M * n_obj * 2 * S * N * N * 8     # keep every slice's waves
         flags = (L.PTYR_GLOBAL_TILT if global_tilt else 0) | (L.PTYR_CHECK_FINITE if check_finite else 0)
         self.geom = L.Geom(N, M, S, H, W, B_max, float(dx), float(lam), kind, float(p),
                            int(wave_budget), flags, int(n_scan), float(sparse_w),
-                           float(pacbed_w))
+                           float(pacbed_w), int(n_obj))
         L.check(self.lib.ptyr_check_geom(C.byref(self.geom)), "geometry")
         self.N, self.M, self.S, self.H, self.W, self.B_max = N, M, S, H, W, B_max
+        self.n_obj = int(n_obj)
+        # object arrays: (S, H, W) for one object mode, (n_obj, S, H, W) for several
+        self.obj_shape = (S, H, W) if self.n_obj == 1 else (self.n_obj, S, H, W)
         self.global_tilt = global_tilt
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -93,10 +96,10 @@ class Engine:
         return k.value
 
     def _check_params(self, amp, phase, probe, pos, tilt, dz, idx, B):
-        S, H, W, M, N = self.S, self.H, self.W, self.M, self.N
+        M, N = self.M, self.N
         d = self.device
-        _need(amp, "amp", torch.float32, (S, H, W), d)
-        _need(phase, "phase", torch.float32, (S, H, W), d)
+        _need(amp, "amp", torch.float32, self.obj_shape, d)
+        _need(phase, "phase", torch.float32, self.obj_shape, d)
         _need(probe, "probe", torch.complex64, (M, N, N), d)
         _need(pos, "pos", torch.float32, None, d)
         if pos.dim() != 2 or pos.shape[1] != 2:
@@ -214,7 +217,7 @@ class Engine:
         negative phase, orthogonalisation of the probe modes."""
         for t, n, dt in ((amp, "amp", torch.float32), (phase, "phase", torch.float32)):
             if t is not None:
-                _need(t, n, dt, (self.S, self.H, self.W), self.device)
+                _need(t, n, dt, self.obj_shape, self.device)
         if probe is not None:
             _need(probe, "probe", torch.complex64, (self.M, self.N, self.N), self.device)
         cfg = L.Constraints(float(rz_sigma), int(bool(phase_positive)), int(bool(probe_orthogonal)),

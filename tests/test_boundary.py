@@ -21,7 +21,8 @@ def header_functions(name="ptyr.h"):
 
 def geom(**kw):
     d = dict(N=128, M=6, S=12, H=640, W=640, B_max=64, dx=0.15, lam=0.0197, loss_kind=0, loss_p=0.5,
-             wave_budget_bytes=64 * 6 * 24 * 128 * 128 * 8, flags=0, n_scan=16384, sparse_w=0.0, pacbed_w=0.0)
+             wave_budget_bytes=64 * 6 * 24 * 128 * 128 * 8, flags=0, n_scan=16384, sparse_w=0.0, pacbed_w=0.0,
+             n_obj=0)
     d.update(kw)
     return L.Geom(*[d[f[0]] for f in L.Geom._fields_])
 
@@ -58,6 +59,9 @@ def test_status_strings():
     (dict(loss_kind=7), L.PTYR_E_ARG),
     (dict(loss_p=0.0), L.PTYR_E_ARG),
     (dict(flags=0x80), L.PTYR_E_ARG),
+    (dict(n_obj=2), L.PTYR_OK),
+    (dict(n_obj=-1), L.PTYR_E_ARG),
+    (dict(n_obj=65), L.PTYR_E_ARG),
     (dict(n_scan=-1), L.PTYR_E_ARG),
 ])
 def test_check_geom(kw, expect):
