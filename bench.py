@@ -47,7 +47,7 @@ def fft_flops(N):
     return 5.0 * N * N * math.log2(N * N)
 
 
-def line_pass_bytes(w, B):
+def line_pass_bytes(w, B, n_obj=1):
     """Algorithmic HBM bytes per step of the N=256 line passes (one wave =
     N*N complex64).  Forward, per chain: shifted probe (read the spectrum,
     write the wave) 2 waves; per slice a row pass (read wave, keep phi, write
@@ -55,10 +55,11 @@ def line_pass_bytes(w, B):
     column pass writing the far field and the mode intensity instead (2.5);
     so 6S + 1.5 waves.  Gradient, per chain: 7S + 1.5 waves (the column pass
     also reads Y, the row pass reads phi and writes the patch gradient).
-    Object patches are read once per batch row and slice."""
+    Object patches are read once per batch row, slice and object mode; with
+    n_obj object modes every probe mode meets every object mode."""
     wave = w.N * w.N * 8
-    chains = B * w.M
-    patches = B * w.S * wave
+    chains = B * w.M * n_obj
+    patches = B * w.S * wave * n_obj
     return {"forward": chains * (6 * w.S + 1.5) * wave + patches,
             "gradient": chains * (7 * w.S + 1.5) * wave + patches}
 
@@ -329,6 +330,8 @@ def main():
                     help="weight of the L1 sparsity term of the object phase in the step's loss (0 = off)")
     ap.add_argument("--pacbed-w", type=float, default=0.0,
                     help="weight of the PACBED term in the step's loss (0 = off; on, a batch runs on one stream)")
+    ap.add_argument("--obj-modes", type=int, default=1,
+                    help="object modes (the extra modes are weaker, partly different copies of the object)")
     ap.add_argument("--constraints", action="store_true",
                     help="time ptyr_constrain (r_z filter, positivity, probe orthogonalisation) on the N=128 workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -360,10 +363,13 @@ def main():
     n_pos = w.pos.shape[0]
     T = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a if dt is None else a.astype(dt))).to(dev)
 
+    K = args.obj_modes
     eng = Engine(w.N, w.M, w.S, w.H, w.W, B, w.dx, lam, n_scan=n_pos, sparse_w=args.sparse_w,
-                 pacbed_w=args.pacbed_w, device=dev)
+                 pacbed_w=args.pacbed_w, n_obj=K, device=dev)
+    obj = lambda x, f: x if K == 1 else np.stack([x * f ** k for k in range(K)])
     # synthetic measured data: forward model of the true object, Poisson-sampled
-    true = dict(amp=T(w.amp, np.float32), phase=T(w.phase, np.float32), probe=T(w.probe, np.complex64),
+    true = dict(amp=T(obj(w.amp, 0.9), np.float32), phase=T(obj(w.phase, 0.7), np.float32),
+                probe=T(w.probe, np.complex64),
                 pos=T(w.pos, np.float32), tilt=T(w.tilt, np.float32), dz=T(np.array([w.dz], np.float32)))
     meas = torch.empty((n_pos, w.N, w.N), dtype=torch.float32, device=dev)
     gen = torch.Generator(device=dev)
@@ -376,7 +382,8 @@ def main():
     del true
 
     amp0, ph0 = synth.plain_init(w.S, w.H, w.W, w.seed_base + 5)
-    st = AdamState(T(amp0, np.float32), T(ph0, np.float32), T(w.probe, np.complex64), T(w.pos, np.float32),
+    st = AdamState(T(obj(amp0, 1.0), np.float32), T(obj(ph0, 1.0), np.float32), T(w.probe, np.complex64),
+                   T(w.pos, np.float32),
                    T(np.zeros_like(w.pos), np.float32), T(np.array([w.dz], np.float32)))
     lr = dict(amp=5e-4, phase=5e-4, probe=1e-4, pos=1e-3, tilt=1e-5, dz=1e-2)
     perm = np.random.default_rng(w.seed_base + 6).permutation(n_pos)
@@ -413,12 +420,12 @@ def main():
     launches = kt[dom][1]
     if w.N < 256:
         # wave-resident chains: bound by the FFT arithmetic
-        flops_step = B * w.M * 2 * w.S * fft_flops(w.N)     # nominal FFT flops of either fused kernel per step
+        flops_step = B * w.M * K * 2 * w.S * fft_flops(w.N)   # nominal FFT flops of either fused kernel per step
         achieved = flops_step * args.steps / (kt[dom][0] * 1e-3) / 1e12
         roofline = {
             "bound": "alu", "kernel": f"k_{dom}<{w.N}>", "achieved": round(achieved, 3),
             "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-            "traffic": read_traffic(dom, workload),
+            "traffic": read_traffic(dom, workload) if K == 1 else None,
             "launch_ms": round(per_launch[dom], 4),
             "launches_per_step": launches / args.steps,
             "flops_per_launch": flops_step * args.steps / launches,
@@ -427,12 +434,12 @@ def main():
         }
     else:
         # line passes: every pass reads and writes the chain's wave through HBM
-        by = line_pass_bytes(w, B)[dom]
+        by = line_pass_bytes(w, B, K)[dom]
         achieved = by * args.steps / (kt[dom][0] * 1e-3) / 1e9
         roofline = {
             "bound": "hbm", "kernel": f"{dom} line passes (N=256)", "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": read_traffic(dom, workload),
+            "traffic": read_traffic(dom, workload) if K == 1 else None,
             "launch_ms": round(per_launch[dom], 4),
             "launches_per_step": launches / args.steps,
             "bytes_per_launch": by * args.steps / launches,
@@ -455,7 +462,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "global_batch": B, "N": w.N, "slices": w.S, "modes": w.M, "positions": n_pos,
                    **({"sparse_w": args.sparse_w} if args.sparse_w else {}),
-                   **({"pacbed_w": args.pacbed_w} if args.pacbed_w else {})},
+                   **({"pacbed_w": args.pacbed_w} if args.pacbed_w else {}),
+                   **({"object_modes": K} if K > 1 else {})},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
