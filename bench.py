@@ -64,6 +64,24 @@ def line_pass_bytes(w, B, n_obj=1):
             "gradient": chains * (7 * w.S + 1.5) * wave + patches}
 
 
+def copy_calibration(out, dev):
+    """Copy a 512 MiB buffer 4 times after one untimed copy: a kernel of known
+    size for the HBM counters, and the rate a plain device copy reaches
+    (read + write bytes over the event-timed copies)."""
+    import torch
+    src = torch.ones(128 << 20, dtype=torch.float32, device=dev)     # 512 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(4):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = src.numel() * 4
+    out["copy_gbs"] = round(4 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+
+
 def read_traffic(kernel, workload):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
     taken on the current kernel sources (else None)."""
@@ -300,12 +318,7 @@ def constraints_bench(args):
                         "achieved_GBs": round(kz_bytes / (ms_kz * 1e-3) / 1e9, 1),
                         "frac_of_hbm_peak": round(kz_bytes / (ms_kz * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     if args.copy_calibration:
-        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)     # 512 MiB
-        dst = torch.empty_like(src)
-        for _ in range(4):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = src.numel() * 4
+        copy_calibration(out, dev)
     print(json.dumps(out), flush=True)
 
 
@@ -469,12 +482,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, B)
     if args.copy_calibration:
-        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)     # 512 MiB
-        dst = torch.empty_like(src)
-        for _ in range(4):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = src.numel() * 4
+        copy_calibration(out, dev)
     print(json.dumps(out), flush=True)
 
 
