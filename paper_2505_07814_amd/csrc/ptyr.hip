@@ -543,6 +543,11 @@ struct AdamSegs {
     float lr[ADAM_SEGS];
     int upd[ADAM_SEGS];
 };
+// the Adam constants of one step beside the segments
+struct SegAdam {
+    AdamSegs A;
+    float b1, b2, eps, bc1, bc2s;
+};
 __global__ void k_adam_segs(AdamSegs a, float b1, float b2, float eps, float bc1, float bc2s) {
     const size_t n = a.off[ADAM_SEGS];
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -1072,7 +1077,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
                         const float* tilt, const float* dz, const int* idx, int n_rows, int B,
                         const float* I_meas, float* g_amp, float* g_phase, float* g_probe, float* g_pos,
                         float* g_tilt, float* g_dz, double* loss_dev, unsigned flags,
-                        const ObjAdam* fuse = nullptr) {
+                        const ObjAdam* fuse = nullptr, const SegAdam* seg = nullptr) {
     const ptyr_geom& g = c->g;
     const int M = chain_modes(g), nm = idx ? n_rows : B, BM = B * M;   // M: chain modes
     const bool reuse = (flags & PTYR_REUSE_FORWARD) && c->fwd_valid && c->fwd_B == B;
@@ -1124,6 +1129,14 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
                                g.N == 256 ? NBLK256 : 1, at<PosInfo>(c, c->L.pinfo), B, M, tilt, a.global_tilt, dz,
                                g.lambda, scale, g_pos, g_tilt, g_dz);
     };
+    // ptyr_step: Adam of the probe, positions, tilts and dz, whose gradients
+    // are complete once the reductions are; on the main stream right after
+    // them, so it runs beside the last object scatter instead of after it
+    auto seg_adam = [&]() {
+        if (seg && seg->A.off[ADAM_SEGS] > 0)
+            hipLaunchKernelGGL(k_adam_segs, dim3(grid_for(seg->A.off[ADAM_SEGS])), dim3(256), 0, c->stream, seg->A,
+                               seg->b1, seg->b2, seg->eps, seg->bc1, seg->bc2s);
+    };
     int scattered = 0;                                       // rows already scattered
     if (nA) {
         const int rA = nA / M;                                     // rows complete after the first forward
@@ -1167,6 +1180,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
             hipStreamWaitEvent(c->stream, c->ev_sgrad, 0) != hipSuccess)
             return PTYR_E_DEVICE;
         reductions(c->stream);
+        seg_adam();
         scatter(rA, B, c->side, true);
         if (hipEventRecord(c->ev_join, c->side) != hipSuccess ||
             hipStreamWaitEvent(c->stream, c->ev_join, 0) != hipSuccess)
@@ -1189,6 +1203,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     if (!scattered) {
         if (!(g.pacbed_w > 0.0)) loss_final(c, 1, B, loss_dev, c->stream, true);
         reductions(c->stream);
+        seg_adam();
         scatter(0, B, c->stream, true);
     }
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
@@ -1399,12 +1414,9 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
     const ObjAdam oa{p->amp,     p->phase,  p->m_amp,   p->v_amp,  p->m_phase,    p->v_phase,
                      rates[0],   rates[1],  lr->beta1,  lr->beta2, lr->eps,       (float)bc1,
                      (float)sqrt(bc2)};
-    st = run_adjoint(c, p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz, idx, p->n_pos, B, I_meas_all,
-                     rates[0] > 0.f ? gamp : nullptr, rates[1] > 0.f ? gphase : nullptr,
-                     rates[2] > 0.f ? gprobe : nullptr, gpos, gtilt, gdz, loss_dev, 0, &oa);
-    if (st != PTYR_OK) return st;
+    SegAdam sa;
     {
-        AdamSegs A;
+        AdamSegs& A = sa.A;
         float* const params[6] = {p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz};
         float* const grads[6] = {gamp, gphase, gprobe, gpos, gtilt, gdz};
         const size_t sizes[6] = {nobj, nobj, nprb, npos, ntilt, 1};
@@ -1423,11 +1435,17 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
             A.upd[k] = on ? 1 : 0;
             A.off[k + 1] = A.off[k] + ((on || k >= 3) ? sizes[k] : 0);
         }
-        if (A.off[6] > 0)
-            hipLaunchKernelGGL(k_adam_segs, dim3(grid_for(A.off[6])), dim3(256), 0, c->stream, A, lr->beta1,
-                               lr->beta2, lr->eps, (float)bc1, (float)sqrt(bc2));
-        c->step_grads_clear = 1;
+        sa.b1 = lr->beta1;
+        sa.b2 = lr->beta2;
+        sa.eps = lr->eps;
+        sa.bc1 = (float)bc1;
+        sa.bc2s = (float)sqrt(bc2);
     }
+    st = run_adjoint(c, p->amp, p->phase, p->probe, p->pos, p->tilt, p->dz, idx, p->n_pos, B, I_meas_all,
+                     rates[0] > 0.f ? gamp : nullptr, rates[1] > 0.f ? gphase : nullptr,
+                     rates[2] > 0.f ? gprobe : nullptr, gpos, gtilt, gdz, loss_dev, 0, &oa, &sa);
+    if (st != PTYR_OK) return st;
+    c->step_grads_clear = 1;
     p->step = t;
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
