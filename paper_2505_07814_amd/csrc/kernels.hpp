@@ -459,8 +459,10 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     }
 }
 
+// One N x N 2-D DFT of sign SG by a whole workgroup (N*N/16 threads), scaled
+// by 1/N (orthonormal); the result is written to dst, or added to it (ACC).
 template <int N, int SG, bool ACC>
-__global__ __launch_bounds__(N * N / 16) void k_fft2(const float2* in, float2* out) {
+__device__ __forceinline__ void fft2_block(const float2* src, float2* dst) {
     constexpr int L = N / 16;
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ float4 tw[N];
@@ -471,8 +473,6 @@ __global__ __launch_bounds__(N * N / 16) void k_fft2(const float2* in, float2* o
         tw[n] = unit_pair(co, s);
     }
     __syncthreads();
-    const float2* src = in + (size_t)blockIdx.x * N * N;
-    float2* dst = out + (size_t)blockIdx.x * N * N;
     float2 v[16];
     wload<N, ROW, NAT>(v, src, N, l, c);
     nat2mid<WaveGeo<N>, SG>(v, lds, tw, l, c);
@@ -484,6 +484,12 @@ __global__ __launch_bounds__(N * N / 16) void k_fft2(const float2* in, float2* o
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[r] = ACC ? cadd(cscale(v[r], sc), o[r]) : cscale(v[r], sc);
     wstore<N, COL, MID>(o, dst, N, l, c);
+}
+
+// the 2-D DFT of each of gridDim.x fields (one workgroup each)
+template <int N, int SG, bool ACC>
+__global__ __launch_bounds__(N * N / 16) void k_fft2(const float2* in, float2* out) {
+    fft2_block<N, SG, ACC>(in + (size_t)blockIdx.x * N * N, out + (size_t)blockIdx.x * N * N);
 }
 
 }  // namespace ptyr

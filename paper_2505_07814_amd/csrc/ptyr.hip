@@ -38,11 +38,9 @@ __global__ void k_transmission(const float* amp, const float* phase, float2* Oc,
     }
 }
 
-// crop corner (round half to even) and sub-pixel shift of every batch row
-__global__ void k_positions(const float* pos, const int* idx, int n_rows, int B, int N, int H, int W,
-                            PosInfo* out, int* err) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= B) return;
+// crop corner (round half to even) and sub-pixel shift of batch row j
+__device__ void position_info(int j, const float* pos, const int* idx, int n_rows, int N, int H, int W,
+                              PosInfo* out, int* err) {
     PosInfo pi;
     pi.ty = -1; pi.tx = -1; pi.dry = 0.f; pi.drx = 0.f; pi.row = 0;
     pi.pad[0] = pi.pad[1] = pi.pad[2] = 0;
@@ -68,6 +66,36 @@ __global__ void k_positions(const float* pos, const int* idx, int n_rows, int B,
     }
     if (!ok) atomicOr(err, ERR_BOUNDS);
     out[j] = pi;
+}
+__global__ void k_positions(const float* pos, const int* idx, int n_rows, int B, int N, int H, int W,
+                            PosInfo* out, int* err) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < B) position_info(j, pos, idx, n_rows, N, H, W, out, err);
+}
+
+// The work a batch shares, in one launch (N = 64, 128): workgroups 0 .. M-1
+// transform the probe modes (long, one compute unit each), the others form
+// the transmission of every slice, and the first of them the positions, so
+// the transform overlaps the streaming pass instead of following it.
+template <int N>
+__global__ __launch_bounds__(N * N / 16) void k_prepare(const float* amp, const float* phase, float2* Oc,
+                                                        size_t nobj, const float* pos, const int* idx, int n_rows,
+                                                        int B, int H, int W, PosInfo* pinfo, int* err,
+                                                        const float2* probe, float2* Phat, int M) {
+    const int b = blockIdx.x;
+    if (b < M) {
+        fft2_block<N, -1, false>(probe + (size_t)b * N * N, Phat + (size_t)b * N * N);
+        return;
+    }
+    const int nb = gridDim.x - M;
+    if (b == M)
+        for (int j = threadIdx.x; j < B; j += blockDim.x) position_info(j, pos, idx, n_rows, N, H, W, pinfo, err);
+    for (size_t i = (size_t)(b - M) * blockDim.x + threadIdx.x; i < nobj; i += (size_t)nb * blockDim.x) {
+        float s, c;
+        sincosf(phase[i], &s, &c);
+        const float a = amp[i];
+        Oc[i] = make_float2(a * c, a * s);
+    }
 }
 
 // fftshift index of an N x N array (its own inverse for even N)
@@ -943,9 +971,19 @@ void gradient_chains(ptyr_ctx* c, const WaveArgs& a, int c0, int nc, hipStream_t
     else gradient256(c, a, c0, nc, st);
 }
 
-template <int N> void launch_probe_fft(ptyr_ctx* c, const float* probe, hipStream_t st) {
-    hipLaunchKernelGGL((k_fft2<N, -1, false>), dim3(c->g.M), dim3(N * N / 16), 0, st,
-                       reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat));
+// probe transforms, positions and transmission in one launch; the streaming
+// part gets about two workgroups per compute unit (the transform's LDS allows
+// no more), four elements per thread at least
+template <int N>
+void launch_prepare(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
+                    const int* idx, int n_rows, int B, size_t nobj, hipStream_t st) {
+    const ptyr_geom& g = c->g;
+    constexpr int T = N * N / 16;
+    const size_t want = (nobj + 4 * (size_t)T - 1) / (4 * (size_t)T);
+    const int nb = (int)std::max<size_t>(1, std::min<size_t>(want, 2 * (size_t)std::max(c->n_cu, 1)));
+    hipLaunchKernelGGL(k_prepare<N>, dim3(g.M + nb), dim3(T), 0, st, amp, phase, at<float2>(c, c->L.Oc), nobj, pos,
+                       idx, idx ? n_rows : B, B, g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err),
+                       reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat), g.M);
 }
 template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe, hipStream_t st) {
     hipLaunchKernelGGL((k_fft2<N, +1, true>), dim3(c->g.M), dim3(N * N / 16), 0, st,
@@ -959,13 +997,13 @@ void prepare_forward(ptyr_ctx* c, const float* amp, const float* phase, const fl
     const hipStream_t st = c->stream;
     const ptyr_geom& g = c->g;
     size_t nobj = (size_t)obj_modes(g) * g.S * g.H * g.W;
-    hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, st, amp, phase,
-                       at<float2>(c, c->L.Oc), nobj);
-    hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, st, pos, idx, idx ? n_rows : B, B, g.N, g.H,
-                       g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err));
-    if (g.N == 64) launch_probe_fft<64>(c, probe, st);
-    else if (g.N == 128) launch_probe_fft<128>(c, probe, st);
+    if (g.N == 64) launch_prepare<64>(c, amp, phase, probe, pos, idx, n_rows, B, nobj, st);
+    else if (g.N == 128) launch_prepare<128>(c, amp, phase, probe, pos, idx, n_rows, B, nobj, st);
     else {
+        hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, st, amp, phase,
+                           at<float2>(c, c->L.Oc), nobj);
+        hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, st, pos, idx, idx ? n_rows : B, B, g.N,
+                           g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err));
         const dim3 grid(g.M * NBLK256), blk(256);
         hipLaunchKernelGGL((k256_fft<-1, true, false>), grid, blk, 0, st, reinterpret_cast<const float2*>(probe),
                            at<float2>(c, c->L.Phat));
