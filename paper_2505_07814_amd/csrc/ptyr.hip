@@ -296,6 +296,8 @@ struct ObjAdam {
     float *amp, *phase;                     // the parameters (read, then updated in place)
     float *m_amp, *v_amp, *m_phase, *v_phase;
     float lr_amp, lr_phase, b1, b2, eps, bc1, bc2s;
+    int gin;    // 1: g_amp / g_phase hold an earlier scatter's sums of this step
+                // (added, then cleared); 0: they are zero (neither read nor written)
 };
 
 // Object gradient: each workgroup owns a 32 x 32 tile of one slice and sums,
@@ -307,8 +309,9 @@ struct ObjAdam {
 // instruction reads two whole 256-byte tile rows of a patch; the loads of up
 // to MB modes of one position are issued together before they are added (in
 // mode order), to keep enough bytes in flight per workgroup.  FUSE: the
-// launch also takes every pixel's complete gradient (buffer + this sum)
-// through Adam (ObjAdam) and clears the buffer, untouched tiles included.
+// launch also takes every pixel's complete gradient (this sum, plus the
+// buffer's when an earlier scatter filled it, which is then cleared) through
+// Adam (ObjAdam), untouched tiles included.
 constexpr int SCATTER_MB = 8;
 template <bool FUSE>
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int j0, int j1, int M,
@@ -381,13 +384,19 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
             if (g_phase) g_phase[o] += gp;
         } else {
             if (g_amp) {
-                const float gi = g_amp[o] + ga;
-                g_amp[o] = 0.f;
+                float gi = ga;
+                if (ad.gin) {
+                    gi += g_amp[o];
+                    g_amp[o] = 0.f;
+                }
                 adam_elem(ad.amp[o], ad.m_amp[o], ad.v_amp[o], gi, ad.lr_amp, ad.b1, ad.b2, ad.eps, ad.bc1, ad.bc2s);
             }
             if (g_phase) {
-                const float gi = g_phase[o] + gp;
-                g_phase[o] = 0.f;
+                float gi = gp;
+                if (ad.gin) {
+                    gi += g_phase[o];
+                    g_phase[o] = 0.f;
+                }
                 adam_elem(ad.phase[o], ad.m_phase[o], ad.v_phase[o], gi, ad.lr_phase, ad.b1, ad.b2, ad.eps, ad.bc1,
                           ad.bc2s);
             }
@@ -1132,14 +1141,18 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     const double* scale = at<double>(c, c->L.scal) + 1;     // the batch factor of w (after loss_final)
     // object-gradient scatter of batch rows [j0, j1) on stream st; `last`
     // (the batch's final scatter) runs the fused object Adam when asked
+    // rows [j0, j1); `last` fuses the object's Adam (ptyr_step), for which
+    // j0 > 0 means rows [0, j0) were scattered into the gradient buffers first
     auto scatter = [&](int j0, int j1, hipStream_t st, bool last) {
         if (!(g_amp || g_phase)) return;
         const int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
         const dim3 grid(ntiles, g.S * obj_modes(g));
         if (last && fuse) {
+            ObjAdam ad = *fuse;
+            ad.gin = j0 > 0 ? 1 : 0;
             hipLaunchKernelGGL(k_scatter_object<true>, grid, dim3(256), 0, st, at<float2>(c, c->L.gO),
                                at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, M, g.S, g.N, g.H, g.W, amp, phase, scale,
-                               g_amp, g_phase, *fuse, sp);
+                               g_amp, g_phase, ad, sp);
         } else if (j1 > j0) {
             hipLaunchKernelGGL(k_scatter_object<false>, grid, dim3(256), 0, st,
                                at<float2>(c, c->L.gO), at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, M, g.S, g.N, g.H, g.W,
@@ -1440,7 +1453,9 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
     float* gtilt = at<float>(c, c->L.gtilt);
     // The six gradient buffers are consecutive in the workspace; they are
     // cleared once here and afterwards by each step's Adam as it reads them
-    // (an interrupted step leaves them to be cleared again).
+    // (an interrupted step leaves them to be cleared again).  The object's two
+    // are only written by the first scatter of a two-stream batch, and read
+    // and cleared by its fused Adam; otherwise they stay zero.
     if (!c->step_grads_clear)
         zero(c, gamp, (size_t)(reinterpret_cast<char*>(at<float>(c, c->L.gtilt) + std::max(g.n_scan, 1) * 2) -
                                reinterpret_cast<char*>(gamp)) / sizeof(float));
@@ -1451,7 +1466,7 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
     // the object's Adam runs inside the batch's last object scatter
     const ObjAdam oa{p->amp,     p->phase,  p->m_amp,   p->v_amp,  p->m_phase,    p->v_phase,
                      rates[0],   rates[1],  lr->beta1,  lr->beta2, lr->eps,       (float)bc1,
-                     (float)sqrt(bc2)};
+                     (float)sqrt(bc2), 0};
     SegAdam sa;
     {
         AdamSegs& A = sa.A;
