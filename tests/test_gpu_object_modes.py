@@ -173,3 +173,30 @@ def test_constraints_per_mode():
         ea, ep = rel(amp[o].cpu().numpy(), ra), rel(phase[o].cpu().numpy(), rp)
         print(f"mode {o}: amp {ea:.2e} phase {ep:.2e}", flush=True)
         assert ea < 1e-5 and ep < 1e-5
+
+
+@pytest.mark.parametrize("budget", [0, 3])
+def test_recompute_equals_stored_waves(budget):
+    """Per-slice recomputation from checkpoints (budget 0: from the probe;
+    3: every few slices) gives the stored-wave gradients of both object modes
+    up to float32 rounding."""
+    c = ModeCase(64, 5, 2, 4, seed=64)
+    g_store = c.engine().adjoint(*c.gpu_args(), T(c.meas))[1]
+    eng = c.engine(wave_budget=budget * c.B * 4 * 64 * 64 * 8)       # 4 chain modes per row
+    g_rec = eng.adjoint(*c.gpu_args(), T(c.meas))[1]
+    eng.sync()
+    print(f"budget {budget}: checkpoint stride {eng.checkpoint_stride}", flush=True)
+    for k in g_store:
+        a, b = g_rec[k].cpu().numpy(), g_store[k].cpu().numpy()
+        assert rel(a, b) <= 1e-7, (k, rel(a, b))
+
+
+def test_pacbed_with_object_modes():
+    """The PACBED term on the pattern summed over all probe and object modes."""
+    c = ModeCase(64, 3, 2, 5, seed=65)
+    loss, g = c.engine(pacbed_w=0.5).adjoint(*c.gpu_args(), T(c.meas))
+    ref = ms.gradients(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, c.w.dx, c.lam, c.meas, pacbed_w=0.5)
+    el = abs(float(loss.cpu()[0]) - ref.loss) / abs(ref.loss)
+    ep, eb = rel(g["phase"].cpu().numpy(), ref.phase), rel(g["probe"].cpu().numpy(), ref.probe)
+    print(f"loss {el:.2e} phase {ep:.2e} probe {eb:.2e}", flush=True)
+    assert el < 1e-5 and ep < 1e-4 and eb < 1e-4
