@@ -311,9 +311,10 @@ struct ObjAdam {
 // mode order), to keep enough bytes in flight per workgroup.  FUSE: the
 // launch also takes every pixel's complete gradient (this sum, plus the
 // buffer's when an earlier scatter filled it, which is then cleared) through
-// Adam (ObjAdam), untouched tiles included.
-constexpr int SCATTER_MB = 8;
-template <bool FUSE>
+// Adam (ObjAdam), untouched tiles included.  MB: 8 when the probe modes come
+// in eights, else 4 (fewer registers, more resident workgroups; a partial
+// batch of 8 would hold registers for loads it does not issue).
+template <bool FUSE, int SCATTER_MB>
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int j0, int j1, int M,
                                                         int Mc, int S, int N, int H, int W, const float* amp,
                                                         const float* phase, const double* scale, float* g_amp,
@@ -1147,16 +1148,25 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         if (!(g_amp || g_phase)) return;
         const int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
         const dim3 grid(ntiles, g.S * obj_modes(g));
+        const bool mb8 = g.M % 8 == 0;
+        const float2* gO = at<float2>(c, c->L.gO);
+        const PosInfo* pinfo = at<PosInfo>(c, c->L.pinfo);
         if (last && fuse) {
             ObjAdam ad = *fuse;
             ad.gin = j0 > 0 ? 1 : 0;
-            hipLaunchKernelGGL(k_scatter_object<true>, grid, dim3(256), 0, st, at<float2>(c, c->L.gO),
-                               at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, M, g.S, g.N, g.H, g.W, amp, phase, scale,
-                               g_amp, g_phase, ad, sp);
+            if (mb8)
+                hipLaunchKernelGGL((k_scatter_object<true, 8>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, g.M, M,
+                                   g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ad, sp);
+            else
+                hipLaunchKernelGGL((k_scatter_object<true, 4>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, g.M, M,
+                                   g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ad, sp);
         } else if (j1 > j0) {
-            hipLaunchKernelGGL(k_scatter_object<false>, grid, dim3(256), 0, st,
-                               at<float2>(c, c->L.gO), at<PosInfo>(c, c->L.pinfo), j0, j1, g.M, M, g.S, g.N, g.H, g.W,
-                               amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
+            if (mb8)
+                hipLaunchKernelGGL((k_scatter_object<false, 8>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, g.M, M,
+                                   g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
+            else
+                hipLaunchKernelGGL((k_scatter_object<false, 4>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, g.M, M,
+                                   g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
         }
     };
     // probe-spectrum sum and inverse transform, position / tilt / dz partials
