@@ -306,14 +306,13 @@ struct ObjAdam {
 // then applies the chain rule to amplitude and phase (O = a exp(i phase)):
 //   g_a += Re(conj(G) exp(i phase)),  g_phase += Im(G conj(O)).
 // A thread owns one column of the tile and four rows 8 apart, so each load
-// instruction reads two whole 256-byte tile rows of a patch; the loads of up
-// to MB modes of one position are issued together before they are added (in
-// mode order), to keep enough bytes in flight per workgroup.  FUSE: the
+// instruction reads two whole 256-byte tile rows of a patch; the loads of MB
+// consecutive (position, mode) items are issued together before they are
+// added (in item order), to keep enough bytes in flight per workgroup.  FUSE: the
 // launch also takes every pixel's complete gradient (this sum, plus the
 // buffer's when an earlier scatter filled it, which is then cleared) through
 // Adam (ObjAdam), untouched tiles included.  MB: 8 when the probe modes come
-// in eights, else 4 (fewer registers, more resident workgroups; a partial
-// batch of 8 would hold registers for loads it does not issue).
+// in eights, else 4 (fewer registers, more resident workgroups).
 template <bool FUSE, int SCATTER_MB>
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int j0, int j1, int M,
                                                         int Mc, int S, int N, int H, int W, const float* amp,
@@ -330,37 +329,54 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
     bool touched = false;
     int cnt[4] = {0, 0, 0, 0};                 // patches covering the pixel (sparsity term)
     const size_t NN = (size_t)N * N;
-    for (int j = j0; j < j1; ++j) {
-        const PosInfo pi = pinfo[j];
-        if (pi.ty < 0) continue;
-        if (pi.ty >= y0 + 32 || pi.ty + N <= y0 || pi.tx >= x0 + 32 || pi.tx + N <= x0) continue;
-        touched = true;
-        const int px = x - pi.tx;
-        const bool xin = px >= 0 && px < N;
-        if (sp != 0.f)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int py = yb + 8 * i - pi.ty;
-                cnt[i] += (xin && py >= 0 && py < N) ? 1 : 0;
-            }
-        for (int m0 = 0; m0 < M; m0 += SCATTER_MB) {
-            float2 buf[SCATTER_MB][4];
-#pragma unroll
-            for (int mm = 0; mm < SCATTER_MB; ++mm) {
-                const int m = m0 + mm;
-                const float2* src = gO + ((size_t)(j * Mc + om + m) * S + s) * NN + px;
+    // Work items are the (row, mode) pairs of the rows whose patch covers the
+    // tile, in row then mode order; SCATTER_MB consecutive items are loaded
+    // together, so with few modes the loads of several rows are in flight.
+    // The cursor (jc, mc) is the same for the whole workgroup; jc == j1 once
+    // no item is left.
+    int jc = j0 - 1, mc = M - 1;
+    PosInfo pc = {0, 0, 0.f, 0.f, 0, {0, 0, 0}};
+    auto advance = [&]() {
+        if (++mc < M) return;
+        mc = 0;
+        for (++jc; jc < j1; ++jc) {
+            pc = pinfo[jc];
+            if (pc.ty < 0) continue;
+            if (pc.ty >= y0 + 32 || pc.ty + N <= y0 || pc.tx >= x0 + 32 || pc.tx + N <= x0) continue;
+            touched = true;
+            if (sp != 0.f) {
+                const int px = x - pc.tx;
+                const bool xin = px >= 0 && px < N;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int py = yb + 8 * i - pi.ty;
-                    const bool in = m < M && xin && py >= 0 && py < N;
-                    buf[mm][i] = in ? src[(size_t)py * N] : make_float2(0.f, 0.f);
+                    const int py = yb + 8 * i - pc.ty;
+                    cnt[i] += (xin && py >= 0 && py < N) ? 1 : 0;
                 }
             }
-#pragma unroll
-            for (int mm = 0; mm < SCATTER_MB; ++mm)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i] = cadd(acc[i], buf[mm][i]);
+            return;
         }
+    };
+    advance();
+    while (jc < j1) {
+        float2 buf[SCATTER_MB][4];
+#pragma unroll
+        for (int mm = 0; mm < SCATTER_MB; ++mm) {
+            const bool live = jc < j1;
+            const int px = x - pc.tx;
+            const bool xin = live && px >= 0 && px < N;
+            const float2* src = gO + ((size_t)(jc * Mc + om + mc) * S + s) * NN + px;   // read only when xin
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int py = yb + 8 * i - pc.ty;
+                const bool in = xin && py >= 0 && py < N;
+                buf[mm][i] = in ? src[(size_t)py * N] : make_float2(0.f, 0.f);
+            }
+            if (live) advance();
+        }
+#pragma unroll
+        for (int mm = 0; mm < SCATTER_MB; ++mm)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = cadd(acc[i], buf[mm][i]);
     }
     if ((!FUSE && !touched) || x >= W) return;
     const float sc = (float)*scale;
