@@ -1,0 +1,52 @@
+"""The benchmark's command-line contract, run in-process: a request for more
+than one GPU exits with a message before any device work (no GPU needed), and
+on the GPU one short run prints one JSON line with the metric, the roofline of
+the dominant kernel and the configuration."""
+import json
+import sys
+
+import pytest
+
+import bench
+
+
+def run_main(argv, capsys):
+    old = sys.argv
+    sys.argv = ["bench.py", *argv]
+    try:
+        code = 0
+        try:
+            bench.main()
+        except SystemExit as e:
+            code = e.code
+    finally:
+        sys.argv = old
+    out = capsys.readouterr()
+    return code, out.out, out.err
+
+
+def test_more_than_one_gpu_exits_with_a_message(capsys):
+    code, out, err = run_main(["--gpus", "2"], capsys)
+    assert code not in (0, None)
+    assert "single GPU" in err
+    assert out.strip() == ""
+
+
+@pytest.mark.gpu
+def test_short_run_prints_the_contract_line(capsys):
+    code, out, err = run_main(["--positions", "512", "--steps", "4", "--warmup", "1", "--no-cpu-baseline"], capsys)
+    assert code in (0, None), err[-2000:]
+    lines = [l for l in out.splitlines() if l.strip()]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 4 and d["warmup"] == 1
+    assert d["value"] > 0 and d["ms_per_step"] > 0
+    assert abs(d["value"] - d["config"]["global_batch"] / (d["ms_per_step"] * 1e-3)) <= 1e-2 * d["value"]
+    rf = d["roofline"]
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in rf, k
+    assert rf["bound"] in ("hbm", "mfma", "alu") and 0 < rf["frac"] < 1
+    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-3
