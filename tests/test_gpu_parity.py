@@ -365,6 +365,57 @@ def test_step_split_batch_matches_adjoint_then_adam(which):
             assert np.all(d <= tol), (t, k, float(np.max(d / tol)))
 
 
+def test_step_full_workload_matches_adjoint_then_adam():
+    """The benchmark's own launch (multislice_128: N=128, 12 slices of
+    640 x 640, 6 modes, 64 positions per step, two-stream schedule, object
+    Adam fused into the last scatter): ptyr_step equals ptyr_adjoint's
+    gradients of the same batch (which the oracle checks at this size)
+    followed by Adam in float64, within the rounding of a float32 Adam update
+    (bound below)."""
+    from paper_2505_07814_amd.ptyr import AdamState, Engine
+    print("step multislice_128 B=64", flush=True)
+    w = synth.workload("multislice_128", scan=128)
+    c = Case(w, B=128)
+    lr = dict(amp=5e-4, phase=5e-4, probe=1e-4, pos=1e-3, tilt=1e-5, dz=1e-2)
+    eng = Engine(w.N, w.M, w.S, w.H, w.W, 64, w.dx, c.lam, device=DEV, n_scan=128)
+    ref_eng = Engine(w.N, w.M, w.S, w.H, w.W, 64, w.dx, c.lam, device=DEV)
+    st = AdamState(*[t.clone() for t in c.gpu_args()])
+    meas = T(c.meas)
+    b1, b2, eps = float(np.float32(0.9)), float(np.float32(0.999)), float(np.float32(1e-8))
+    order = np.random.default_rng(5).permutation(128)
+    for t, idx_np in enumerate([order[:64], order[64:]]):
+        idx = torch.tensor(idx_np, dtype=torch.int32, device=DEV)
+        before = {k: getattr(st, k).clone() for k in st.NAMES}
+        m0 = {k: st.m[k].clone() for k in st.NAMES}
+        v0 = {k: st.v[k].clone() for k in st.NAMES}
+        eng.step(st, idx, meas, lr)
+        _, g = ref_eng.adjoint(*[before[k] for k in st.NAMES], meas, idx=idx)
+        eng.sync()
+        ref_eng.sync()
+        for k in st.NAMES:
+            f64 = lambda x: np.asarray(x, np.complex128 if np.iscomplexobj(x) else np.float64)
+            p0 = before[k].cpu().numpy()
+            got = getattr(st, k).cpu().numpy()
+            rp, _, _ = adam_step(f64(p0), f64(g[k].cpu().numpy()), f64(m0[k].cpu().numpy()),
+                                 f64(v0[k].cpu().numpy()), t, lr[k], beta1=b1, beta2=b2, eps=eps)
+            flat = lambda x: np.ravel(np.asarray(x).view(np.float32) if np.iscomplexobj(x) else x).astype(np.float64)
+            got_r, gr, mr, vr = flat(got), flat(g[k].cpu().numpy()), flat(m0[k].cpu().numpy()), flat(v0[k].cpu().numpy())
+            rp_r = np.stack([rp.real, rp.imag], -1).ravel() if np.iscomplexobj(rp) else np.ravel(rp)
+            # float32 Adam: the update u = a m' / D (a = lr / bc1, D = sqrt(v') / bc2s + eps)
+            # carries a few roundings relative to itself, plus the absolute error
+            # of m' = b1 m + (1 - b1) g, which can cancel: ~u32 (|b1 m| + |(1 - b1) g|);
+            # the parameter adds half an ulp of its own
+            u32 = 2.0 ** -24
+            a = lr[k] / (1.0 - b1 ** (t + 1))
+            D = np.sqrt(b2 * vr + (1 - b2) * gr * gr) / np.sqrt(1.0 - b2 ** (t + 1)) + eps
+            mm = np.abs(b1 * mr) + np.abs((1 - b1) * gr)
+            u = np.abs(a * (b1 * mr + (1 - b1) * gr) / D)
+            tol = 2 * np.spacing(np.abs(rp_r).astype(np.float32)) + 8 * u32 * u + 2 * u32 * a * mm / D
+            d = np.abs(got_r - rp_r)
+            print(f"step {t + 1} {k}: max |P - P_ref| / tol {np.max(d / tol):.2f}", flush=True)
+            assert np.all(d <= tol), (t, k, float(np.max(d / tol)))
+
+
 @pytest.mark.parametrize("split", [False, True])
 def test_sparsity_term_parity(split):
     """Loss and gradients with 0.1 x the L1 sparsity term of the phase, on one
