@@ -424,6 +424,21 @@ def main():
     kt = eng.timing_read()
     eng.timing(False)
     eng.sync()
+    # the same batches through ptyr_adjoint alone (forward, loss and the six
+    # gradients, no Adam), reported beside the step
+    grads = {k: torch.zeros_like(getattr(st, k)) for k in st.NAMES}
+    params = [getattr(st, k) for k in st.NAMES]
+    for s in range(min(args.warmup, 4)):
+        eng.adjoint(*params, meas, idx=batches[s % nb], grads=grads)
+    torch.cuda.synchronize()
+    n_adj = min(args.steps, 16)
+    e0.record(stream)
+    for s in range(n_adj):
+        eng.adjoint(*params, meas, idx=batches[(args.warmup + s) % nb], grads=grads)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_adj = e0.elapsed_time(e1) / n_adj
+    eng.sync()
 
     ms_step = ms_total / args.steps
     value = B * args.steps / (ms_total / 1e3)
@@ -482,6 +497,10 @@ def main():
                    **({"pacbed_w": args.pacbed_w} if args.pacbed_w else {}),
                    **({"object_modes": K} if K > 1 else {})},
         "roofline": roofline,
+        "fwd_adjoint_only": {"ms_per_step": round(ms_adj, 4), "value": round(B / (ms_adj * 1e-3), 1),
+                             "unit": "patterns/s", "steps": n_adj,
+                             "note": "ptyr_adjoint on the first batches of the timed ones: forward, loss, all six "
+                                     "gradients, no Adam"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, B)
