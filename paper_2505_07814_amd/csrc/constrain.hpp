@@ -74,8 +74,11 @@ __global__ void k_rz_matrix(RzTaps taps, int S, float* Bm) {
 // registers and forms out = B x with the matrix read through the scalar
 // cache (every thread of the launch reads the same entries).
 constexpr int RZ_REG_S = 32;
-__global__ __launch_bounds__(256) void k_rz_filter_reg(float* v, int S, size_t HW, const float* __restrict__ Bm,
-                                                       int positive) {
+__global__ __launch_bounds__(256) void k_rz_filter_reg(float* v0, float* v1, int S, size_t HW,
+                                                       const float* __restrict__ Bm, int positive1) {
+    // blockIdx.y: 0 filters v0 (amplitude), 1 filters v1 (phase; clipped at 0 with positive1)
+    float* const v = blockIdx.y ? v1 : v0;
+    const int positive = blockIdx.y ? positive1 : 0;
     const size_t px = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (px >= HW) return;
     float x[RZ_REG_S];
@@ -94,8 +97,10 @@ __global__ __launch_bounds__(256) void k_rz_filter_reg(float* v, int S, size_t H
 
 // The same for fields whose slice size is a multiple of 4: a thread owns four
 // consecutive pixels (16-byte reads and writes).
-__global__ __launch_bounds__(256) void k_rz_filter_reg4(float* v, int S, size_t HW, const float* __restrict__ Bm,
-                                                        int positive) {
+__global__ __launch_bounds__(256) void k_rz_filter_reg4(float* v0, float* v1, int S, size_t HW,
+                                                        const float* __restrict__ Bm, int positive1) {
+    float* const v = blockIdx.y ? v1 : v0;
+    const int positive = blockIdx.y ? positive1 : 0;
     const size_t px = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (px >= HW) return;
     float4 x[RZ_REG_S];

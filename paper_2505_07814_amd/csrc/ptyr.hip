@@ -1415,13 +1415,14 @@ ptyr_status ptyr_constrain(ptyr_ctx* c, float* amp, float* phase, float* probe, 
                 hipLaunchKernelGGL(k_rz_matrix, dim3((g.S * g.S + 255) / 256), dim3(256), 0, st, t, g.S, Bm);
                 const bool vec4 = HW % 4 == 0 && reinterpret_cast<uintptr_t>(amp_o) % 16 == 0 &&
                                   reinterpret_cast<uintptr_t>(phase_o) % 16 == 0;
-                const dim3 grid((unsigned)((HW / (vec4 ? 4 : 1) + 255) / 256));
-                for (int f = 0; f < 2; ++f) {
-                    TimedLaunch tl(c, PTYR_K_RZ, st);
-                    const int pos = f == 1 && cfg->phase_positive ? 1 : 0;
-                    if (vec4) hipLaunchKernelGGL(k_rz_filter_reg4, grid, dim3(256), 0, st, fields[f], g.S, HW, Bm, pos);
-                    else hipLaunchKernelGGL(k_rz_filter_reg, grid, dim3(256), 0, st, fields[f], g.S, HW, Bm, pos);
-                }
+                // amplitude (grid row 0) and phase (row 1) in one launch
+                const dim3 grid((unsigned)((HW / (vec4 ? 4 : 1) + 255) / 256), 2);
+                const int pos = cfg->phase_positive ? 1 : 0;
+                TimedLaunch tl(c, PTYR_K_RZ, st);
+                if (vec4)
+                    hipLaunchKernelGGL(k_rz_filter_reg4, grid, dim3(256), 0, st, fields[0], fields[1], g.S, HW, Bm, pos);
+                else
+                    hipLaunchKernelGGL(k_rz_filter_reg, grid, dim3(256), 0, st, fields[0], fields[1], g.S, HW, Bm, pos);
             } else {
                 const int T = rz_threads(g.S);
                 const dim3 grid((unsigned)((HW + T - 1) / T));
