@@ -262,8 +262,9 @@ ptyr_status ptyr_constrain(ptyr_ctx* ctx, float* amp, float* phase, float* probe
 /* Instrumentation (not part of the method): when enabled, the context brackets
  * each launch of its fused wave kernels with HIP events on its stream.
  * kernel ids: PTYR_K_FORWARD (the multislice forward kernel),
- * PTYR_K_GRADIENT (the gradient kernel) and PTYR_K_RZ (one field's r_z
- * depth filter in ptyr_constrain).  Enabling creates the events (no
+ * PTYR_K_GRADIENT (the gradient kernel) and PTYR_K_RZ (the r_z depth filter
+ * in ptyr_constrain: one launch for amplitude and phase while S <= 32, one
+ * per field beyond).  Enabling creates the events (no
  * device memory is allocated); at most 4096 launches are recorded between
  * reads, later ones are not timed. */
 enum { PTYR_K_FORWARD = 0, PTYR_K_GRADIENT = 1, PTYR_K_RZ = 2 };
