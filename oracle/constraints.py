@@ -33,6 +33,8 @@ import math
 
 import numpy as np
 
+from . import dft
+
 
 def gaussian_taps(sigma: float, truncate: float = 4.0) -> np.ndarray:
     """Normalised taps w[k + R], k = -R..R, R = ceil(truncate * sigma)."""
@@ -68,9 +70,9 @@ def rz_filter(vol, sigma: float, truncate: float = 4.0) -> np.ndarray:
 
 def kz_weight(S, H, W, beta, alpha, dx, dz, eps=1e-3) -> np.ndarray:
     """W_a on the S x H x W fftfreq grid (zero frequency at index 0)."""
-    kz = np.fft.fftfreq(S, d=dz)[:, None, None]
-    ky = np.fft.fftfreq(H, d=dx)[None, :, None]
-    kx = np.fft.fftfreq(W, d=dx)[None, None, :]
+    kz = dft.fftfreq(S, d=dz)[:, None, None]
+    ky = dft.fftfreq(H, d=dx)[None, :, None]
+    kx = dft.fftfreq(W, d=dx)[None, None, :]
     kr2 = kx ** 2 + ky ** 2
     Wk = 1.0 - (2.0 / np.pi) * np.arctan(beta ** 2 * kz ** 2 / (kr2 + eps))
     return Wk * np.exp(-alpha * kr2)
@@ -80,7 +82,7 @@ def kz_filter(vol, beta, alpha, dx, dz) -> np.ndarray:
     """F3^-1[W_a F3[vol]] of a real S x H x W field (real part of the result)."""
     vol = np.asarray(vol, np.float64)
     Wa = kz_weight(*vol.shape, beta, alpha, dx, dz)
-    return np.real(np.fft.ifftn(Wa * np.fft.fftn(vol)))
+    return np.real(dft.ifftn(Wa * dft.fftn(vol)))
 
 
 def positivity(phase) -> np.ndarray:

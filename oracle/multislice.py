@@ -22,7 +22,8 @@ equations:
   dL/dRe + i dL/dIm.
 
 Conventions (readings where the paper is silent):
-* F is the orthonormal 2-D DFT with the e^{-2 pi i} sign; F^-1 uses e^{+2 pi i}.
+* F is the orthonormal 2-D DFT with the e^{-2 pi i} sign; F^-1 uses e^{+2 pi i};
+  both are the oracle's own radix-2 FFT (`oracle/dft.py`).
 * q = fftfreq(N) in cycles/pixel, k = q/dx in 1/angstrom; axis 0 is y, axis 1
   is x; positions and tilts are given as (y, x) pairs.
 * the patch for position rho has top-left corner round_half_even(rho) - N/2;
@@ -39,23 +40,25 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from . import dft
+
 POISSON_EPS = 1e-6   # epsilon inside the Poisson log, Eq. (6)
 
 
 # ---------------------------------------------------------------- transforms
 def fft2(x):
-    """Orthonormal forward 2-D DFT over the last two axes."""
-    return np.fft.fft2(x, norm="ortho")
+    """Orthonormal forward 2-D DFT over the last two axes (own radix-2 FFT)."""
+    return dft.fft2(x)
 
 
 def ifft2(x):
-    """Orthonormal inverse 2-D DFT over the last two axes."""
-    return np.fft.ifft2(x, norm="ortho")
+    """Orthonormal inverse 2-D DFT over the last two axes (own radix-2 FFT)."""
+    return dft.ifft2(x)
 
 
 def kgrid(N, dx):
     """Spatial frequencies (k_y column, k_x row) in 1/angstrom."""
-    k = np.fft.fftfreq(N) / dx
+    k = dft.fftfreq(N) / dx
     return k[:, None], k[None, :]
 
 
@@ -72,7 +75,7 @@ def split_position(rho, N):
 def shift_ramp(dr, N):
     """Fourier shift ramp R(u,v) = exp(-2 pi i (q_u dr_y + q_v dr_x)); applying
     F^-1[R F[P]] moves the probe by +dr pixels."""
-    q = np.fft.fftfreq(N)
+    q = dft.fftfreq(N)
     return np.exp(-2j * np.pi * (q[:, None] * dr[0] + q[None, :] * dr[1]))
 
 
@@ -119,27 +122,42 @@ class ForwardTrace:
     Psi: np.ndarray        # (M,N,N) far-field waves
 
 
-def forward_one(O, Phat, rho, tilt, dz, dx, lam):
-    """Multislice exit wave and far-field intensity for one scan position,
-    Eq. (2)-(4).  O: (S,H,W) complex object; Phat: (M,N,N) probe spectra."""
+def forward_batch(O, Phat, pos, tilt, dz, dx, lam):
+    """Multislice exit waves and far-field intensities for a batch of scan
+    positions, Eq. (2)-(4), each position on its own (the arrays run over
+    positions and modes: (B, M, N, N)).  O: (S,H,W) complex object; Phat:
+    (M,N,N) probe spectra; pos, tilt: (B,2).  Returns the (B,N,N) intensities
+    (zero frequency at (0, 0)) and one ForwardTrace per position."""
     S = O.shape[0]
     N = Phat.shape[-1]
     dz, dx, lam = float(dz), float(dx), float(lam)
-    tilt = np.asarray(tilt, np.float64)
-    t, dr = split_position(rho, N)
-    R = shift_ramp(dr, N)
-    Hp = propagator(N, dx, lam, dz, tilt)
-    phi = ifft2(Phat * R)                      # shifted probe modes P_j^(m)
+    pos = np.asarray(pos, np.float64).reshape(-1, 2)
+    tilt = np.asarray(tilt, np.float64).reshape(-1, 2)
+    B = len(pos)
+    split = [split_position(rho, N) for rho in pos]
+    R = np.stack([shift_ramp(dr, N) for _, dr in split])                     # (B,N,N)
+    Hp = np.stack([propagator(N, dx, lam, dz, tilt[j]) for j in range(B)])    # (B,N,N)
+    phi = ifft2(Phat[None] * R[:, None])       # shifted probe modes P_j^(m), (B,M,N,N)
     phis, chis = [], []
     for s in range(S):
         phis.append(phi)
-        chi = crop(O[s], t, N) * phi           # transmit through slice s
+        patch = np.stack([crop(O[s], t, N) for t, _ in split])                # (B,N,N)
+        chi = patch[:, None] * phi             # transmit through slice s
         chis.append(chi)
         if s < S - 1:
-            phi = ifft2(Hp * fft2(chi))        # propagate to slice s+1
+            phi = ifft2(Hp[:, None] * fft2(chi))   # propagate to slice s+1
     Psi = fft2(chis[-1])
-    I = np.sum(np.abs(Psi) ** 2, axis=0)       # incoherent sum over modes
-    return I, ForwardTrace(t, dr, R, Hp, phis, chis, Psi)
+    I = np.sum(np.abs(Psi) ** 2, axis=1)       # incoherent sum over modes
+    traces = [ForwardTrace(split[j][0], split[j][1], R[j], Hp[j], [p_[j] for p_ in phis],
+                           [c_[j] for c_ in chis], Psi[j]) for j in range(B)]
+    return I, traces
+
+
+def forward_one(O, Phat, rho, tilt, dz, dx, lam):
+    """Multislice exit wave and far-field intensity for one scan position,
+    Eq. (2)-(4).  O: (S,H,W) complex object; Phat: (M,N,N) probe spectra."""
+    I, traces = forward_batch(O, Phat, [rho], [tilt], dz, dx, lam)
+    return I[0], traces[0]
 
 
 def forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=False):
@@ -162,12 +180,8 @@ def forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=False):
     check_bounds(pos, N, amp.shape[1], amp.shape[2])
     O = transmission(amp, phase)
     Phat = fft2(probe)
-    out, traces = [], []
-    for j in range(len(pos)):
-        I, tr = forward_one(O, Phat, pos[j], tilt[j], dz, dx, lam)
-        out.append(np.fft.fftshift(I))
-        traces.append(tr)
-    out = np.stack(out)
+    I, traces = forward_batch(O, Phat, pos, tilt, dz, dx, lam)
+    out = dft.fftshift2(I)
     return (out, traces) if return_trace else out
 
 
@@ -316,14 +330,14 @@ def _adjoint(amp, phase, probe, pos, tilt, dz, dx, lam, dI, traces):
     O = transmission(amp, phase)
     Phat = fft2(probe)
     ky, kx = kgrid(N, dx)
-    q = np.fft.fftfreq(N)
+    q = dft.fftfreq(N)
     G_O = np.zeros_like(O)
     G_Phat = np.zeros_like(Phat)
     g_pos = np.zeros((len(pos), 2))
     g_tilt = np.zeros((len(pos), 2))
     g_dz = 0.0
     for j, tr in enumerate(traces):
-        gI = np.fft.ifftshift(dI[j])                       # back to DC-at-0 layout
+        gI = dft.ifftshift2(dI[j])                       # back to DC-at-0 layout
         G_Psi = 2.0 * gI * tr.Psi                           # I = sum_m |Psi_m|^2
         G_chi = ifft2(G_Psi)                                # Psi = F chi_{S-1}
         G_H = np.zeros((N, N), np.complex128)

@@ -63,6 +63,37 @@ MUTANTS = {
 }
 
 
+def _fft_pins():
+    pins.test_fft_is_orthonormal_dft(8)
+    pins.test_fft_is_orthonormal_dft(64)
+
+
+FFT_MUTANTS = {   # wrong butterfly twiddle angles, as functions of (sign, h)
+    # the twiddle with the wrong sign
+    "conjugated butterfly twiddle": lambda s, h: -s * np.pi * np.arange(h) / h,
+    # w = exp(sign 2 pi i / h) instead of exp(sign pi i / h)
+    "twiddle angle doubled": lambda s, h: s * 2 * np.pi * np.arange(h) / h,
+    # a twiddle index off by one
+    "twiddle index shifted": lambda s, h: s * np.pi * (np.arange(h) + 1) / h,
+}
+
+
+@pytest.mark.parametrize("name", list(FFT_MUTANTS) + ["bit reversal skipped", "plain reversal instead of bit reversal"])
+def test_planted_fft_mistake_is_caught(name, monkeypatch):
+    """Mistakes planted inside the oracle's own radix-2 FFT trip the
+    brute-force DFT pins."""
+    from oracle import dft
+    if name in FFT_MUTANTS:
+        tw = FFT_MUTANTS[name]
+        monkeypatch.setattr(dft, "_twiddles", lambda h, sign: np.exp(1j * tw(sign, h)))
+    elif name == "bit reversal skipped":
+        monkeypatch.setattr(dft, "_bit_reverse", lambda n: np.arange(n))
+    else:
+        monkeypatch.setattr(dft, "_bit_reverse", lambda n: np.arange(n)[::-1].copy())
+    with pytest.raises(AssertionError):
+        _fft_pins()
+
+
 @pytest.mark.parametrize("name", list(MUTANTS))
 def test_planted_mistake_is_caught(name, monkeypatch):
     attr, bad, pin = MUTANTS[name]
