@@ -216,15 +216,11 @@ def pacbed_loss(I_model, I_meas, p):
     return float(L), np.broadcast_to(dAbar / B, I.shape).copy()
 
 
-def loss(I_model, I_meas, kind="gaussian", p=None, eps=POISSON_EPS, pacbed_w=0.0):
-    """Loss of Eq. (5) (kind='gaussian', default p=0.5) or Eq. (6)
-    (kind='poisson', default p=1), averaged over detector and batch, plus
-    pacbed_w times the PACBED loss (same p) when pacbed_w > 0.
-    Returns (L, dL/dI_model) with the gradient in the layout of I_model."""
+def data_term(I_model, I_meas, kind, p, eps=POISSON_EPS):
+    """One data term: Eq. (5) (kind='gaussian') or Eq. (6) (kind='poisson')
+    with power p, averaged over detector and batch.  Returns (L, dL/dI)."""
     I = np.asarray(I_model, np.float64)
     Im = np.asarray(I_meas, np.float64)
-    if p is None:
-        p = 0.5 if kind == "gaussian" else 1.0
     K = I.size
     A = I ** p
     E = Im ** p
@@ -245,8 +241,28 @@ def loss(I_model, I_meas, kind="gaussian", p=None, eps=POISSON_EPS, pacbed_w=0.0
     else:
         with np.errstate(divide="ignore", invalid="ignore"):
             dI = np.where(I > 0, dA * p * I ** (p - 1.0), 0.0)
+    return float(L), dI
+
+
+def loss(I_model, I_meas, kind="gaussian", p=None, eps=POISSON_EPS, pacbed_w=0.0, terms=None):
+    """Loss of Eq. (5) (kind='gaussian', default p=0.5) or Eq. (6)
+    (kind='poisson', default p=1), averaged over detector and batch; or, with
+    terms = [(kind, w, p), ...], the weighted sum of data terms of Eq. (9)
+    (w_1 L_Gaussian + w_2 L_Poisson, each term with its own power and its own
+    batch normaliser).  pacbed_w > 0 adds pacbed_w times the PACBED loss, with
+    the power of the (first) data term.  Returns (L, dL/dI_model) with the
+    gradient in the layout of I_model."""
+    if terms is None:
+        if p is None:
+            p = 0.5 if kind == "gaussian" else 1.0
+        terms = [(kind, 1.0, p)]
+    L, dI = 0.0, 0.0
+    for k, w, pt in terms:
+        Lt, dIt = data_term(I_model, I_meas, k, pt, eps)
+        L = L + w * Lt
+        dI = dI + w * dIt
     if pacbed_w:
-        Lp, dIp = pacbed_loss(I, Im, p)
+        Lp, dIp = pacbed_loss(I_model, I_meas, terms[0][2])
         L = L + pacbed_w * Lp
         dI = dI + pacbed_w * dIp
     return float(L), dI
@@ -284,11 +300,11 @@ def sparse_term(phase, pos, N):
 
 
 def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian",
-              p=None, sparse_w=0.0, pacbed_w=0.0):
+              p=None, sparse_w=0.0, pacbed_w=0.0, terms=None):
     """Loss and its gradient w.r.t. all six parameters for one batch.
     sparse_w > 0 adds sparse_w times the sparsity term, pacbed_w > 0 adds
-    pacbed_w times the PACBED loss (the weighted total loss of the paper with
-    the data term's weight 1).
+    pacbed_w times the PACBED loss, terms (see `loss`) weights the data terms
+    (the weighted total loss of Eq. 9; by default one data term at weight 1).
 
     The chain rule is taken through the forward steps in reverse:
     far field -> last slice -> (slice s: object, then propagator) -> shift ->
@@ -301,7 +317,7 @@ def gradients(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian"
     tilt = np.asarray(tilt, np.float64)
     dz, dx, lam = float(dz), float(dx), float(lam)   # every scalar in float64
     I_model, traces = forward(amp, phase, probe, pos, tilt, dz, dx, lam, return_trace=True)
-    L, dI = loss(I_model, I_meas, kind, p, pacbed_w=pacbed_w)
+    L, dI = loss(I_model, I_meas, kind, p, pacbed_w=pacbed_w, terms=terms)
     if amp.ndim == 4:
         # I = sum over object modes: each mode's adjoint takes the same dL/dI;
         # the probe, position, tilt and dz gradients add over the modes
@@ -374,10 +390,10 @@ def _adjoint(amp, phase, probe, pos, tilt, dz, dx, lam, dI, traces):
 
 
 def loss_of(amp, phase, probe, pos, tilt, dz, dx, lam, I_meas, kind="gaussian", p=None, sparse_w=0.0,
-            pacbed_w=0.0):
+            pacbed_w=0.0, terms=None):
     """Scalar loss of the forward model (for finite differences)."""
     I = forward(amp, phase, probe, pos, tilt, dz, dx, lam)
-    L = loss(I, I_meas, kind, p, pacbed_w=pacbed_w)[0]
+    L = loss(I, I_meas, kind, p, pacbed_w=pacbed_w, terms=terms)[0]
     if sparse_w:
         ph = np.asarray(phase, np.float64)
         L += sparse_w * sparse_term(ph.reshape(-1, *ph.shape[-2:]), pos, probe.shape[-1])[0]
