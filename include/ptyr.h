@@ -101,6 +101,18 @@ typedef struct {
                                  transmitted with every probe mode and the model
                                  intensity sums over all M x n_obj pairs; 0 or 1 = one
                                  object, at most 64 */
+    double w_gaussian;        /* weighted total loss (Sec. "Optimizers and loss functions",
+                                 Eq. 9): w_1 of the Gaussian term (Eq. 5) ... */
+    double w_poisson;         /* ... and w_2 of the Poisson term (Eq. 6), each with its own
+                                 batch normaliser <I_meas^p>; both 0 = the loss_kind
+                                 term alone at weight 1 (loss_kind is then ignored when
+                                 either is set).  With both set the batch runs on one
+                                 stream (the weights of each pixel need both terms'
+                                 batch factors) */
+    double p_gaussian, p_poisson; /* powers of the two terms when w_gaussian or w_poisson
+                                 is set; 0 = the paper's defaults 0.5 and 1.  The PACBED
+                                 term then takes the power of the first weighted term
+                                 (Gaussian if w_gaussian > 0), else loss_p */
 } ptyr_geom;
 
 /* Parameters of one reconstruction and their Adam moments (all device). */
@@ -160,8 +172,10 @@ ptyr_status ptyr_checkpoint_plan(const ptyr_geom* g, int* stride);
  * their own stream.  PTYR_E_DEVICE if the stream or events cannot be made. */
 ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes,
                         void* stream, ptyr_ctx** out);
-/* Release the context, its stream and events (waits for the stream's work). */
-void ptyr_destroy(ptyr_ctx* ctx);
+/* Release the context, its stream and events (waits for the side stream's
+ * work).  The context is freed in any case; PTYR_E_DEVICE reports that one of
+ * the HIP releases failed. */
+ptyr_status ptyr_destroy(ptyr_ctx* ctx);
 
 /* Wait for the context's stream and report the first asynchronous error:
  * PTYR_E_BOUNDS / PTYR_E_NONFINITE raised by kernels since the last call, or
@@ -181,9 +195,9 @@ ptyr_status ptyr_forward(ptyr_ctx* ctx, const float* amp, const float* phase,
                          const float* dz, const int* idx, int n_rows, int B,
                          float* I_out);
 
-/* Loss of Eq. 5 (Gaussian) or Eq. 6 (Poisson, eps = 1e-6) between fftshifted
- * model and measured intensities (B x N x N each), averaged over detector and
- * batch.  Writes the loss to loss_dev (1 double, overwritten) and, if dLdI is
+/* Loss of Eq. 5 (Gaussian) or Eq. 6 (Poisson, eps = 1e-6), or their weighted
+ * sum of Eq. 9 (w_gaussian, w_poisson), between fftshifted model and measured
+ * intensities (B x N x N each), averaged over detector and batch.  Writes the loss to loss_dev (1 double, overwritten) and, if dLdI is
  * not NULL, dL/dI_model (B x N x N, overwritten).  meas_idx (nullable, B
  * device ints) selects measured pattern meas_idx[b] of the n_meas patterns in
  * I_meas for batch row b. */
@@ -195,7 +209,9 @@ ptyr_status ptyr_loss(ptyr_ctx* ctx, const float* I_model, const float* I_meas,
  * positions, tilts and dz (chain rule through Eq. 1-6).  Runs the forward
  * itself unless flags has PTYR_REUSE_FORWARD.  idx (nullable, B device ints in
  * [0, n_rows)) selects rows of pos/tilt/I_meas and the rows of g_pos/g_tilt
- * that receive the gradient; the rows of one batch must be distinct.
+ * that receive the gradient; the rows of one batch must be distinct (a row
+ * met again later in the batch is skipped and reported by ptyr_sync as
+ * PTYR_E_ARG: its gradient would otherwise race with the first one's).
  * Gradients accumulate (+=): g_amp, g_phase n_obj x S x H x W; g_probe M x N x N
  * complex; g_pos, g_tilt like pos, tilt; g_dz 1.  Any gradient pointer may be
  * NULL to skip it.  loss_dev (nullable) receives the batch loss. */
@@ -212,8 +228,8 @@ ptyr_status ptyr_adjoint(ptyr_ctx* ctx, const float* amp, const float* phase,
  * I_meas_all, n_pos x N x N), then a dense Adam update of every parameter
  * whose rate is non-zero (entries outside the batch see a zero gradient, as
  * in PyTorch), and p->step += 1.  loss_dev (nullable) receives the batch
- * loss.  Row indices outside [0, n_pos) are skipped and reported by
- * ptyr_sync as PTYR_E_ARG. */
+ * loss.  Row indices outside [0, n_pos) and repeats of an earlier row of the
+ * batch are skipped and reported by ptyr_sync as PTYR_E_ARG. */
 ptyr_status ptyr_step(ptyr_ctx* ctx, ptyr_params* p, const int* idx, int B,
                       const float* I_meas_all, const ptyr_lr* lr, double* loss_dev);
 

@@ -22,7 +22,9 @@ class Geom(C.Structure):
                 ("B_max", C.c_int), ("dx", C.c_double), ("lam", C.c_double),
                 ("loss_kind", C.c_int), ("loss_p", C.c_double),
                 ("wave_budget_bytes", C.c_size_t), ("flags", C.c_uint), ("n_scan", C.c_int),
-                ("sparse_w", C.c_double), ("pacbed_w", C.c_double), ("n_obj", C.c_int)]
+                ("sparse_w", C.c_double), ("pacbed_w", C.c_double), ("n_obj", C.c_int),
+                ("w_gaussian", C.c_double), ("w_poisson", C.c_double),
+                ("p_gaussian", C.c_double), ("p_poisson", C.c_double)]
 
 
 _fp = C.c_void_p
@@ -72,7 +74,7 @@ def lib():
         "ptyr_workspace_bytes": (C.c_size_t, [C.POINTER(Geom)]),
         "ptyr_checkpoint_plan": (st, [C.POINTER(Geom), C.POINTER(C.c_int)]),
         "ptyr_create": (st, [C.POINTER(Geom), vp, C.c_size_t, vp, C.POINTER(vp)]),
-        "ptyr_destroy": (None, [vp]),
+        "ptyr_destroy": (st, [vp]),
         "ptyr_sync": (st, [vp]),
         "ptyr_forward": (st, [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, vp]),
         "ptyr_loss": (st, [vp, vp, vp, vp, C.c_int, C.c_int, vp, vp]),

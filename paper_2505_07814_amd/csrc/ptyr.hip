@@ -38,14 +38,25 @@ __global__ void k_transmission(const float* amp, const float* phase, float2* Oc,
     }
 }
 
-// crop corner (round half to even) and sub-pixel shift of batch row j
+// true when batch row j repeats the row of an earlier batch row (a gradient
+// batch needs distinct rows: their position / tilt gradient updates would race)
+__device__ bool repeated_row(int j, const int* idx) {
+    const int row = idx[j];
+    for (int i = 0; i < j; ++i)
+        if (idx[i] == row) return true;
+    return false;
+}
+
+// crop corner (round half to even) and sub-pixel shift of batch row j; with
+// `distinct`, a row already used by an earlier batch row is skipped as a bad
+// index
 __device__ void position_info(int j, const float* pos, const int* idx, int n_rows, int N, int H, int W,
-                              PosInfo* out, int* err) {
+                              PosInfo* out, int* err, int distinct) {
     PosInfo pi;
     pi.ty = -1; pi.tx = -1; pi.dry = 0.f; pi.drx = 0.f; pi.row = 0;
     pi.pad[0] = pi.pad[1] = pi.pad[2] = 0;
     int row = idx ? idx[j] : j;
-    if (row < 0 || row >= n_rows) {
+    if (row < 0 || row >= n_rows || (distinct && idx && repeated_row(j, idx))) {
         atomicOr(err, ERR_INDEX);
         out[j] = pi;
         return;
@@ -68,9 +79,19 @@ __device__ void position_info(int j, const float* pos, const int* idx, int n_row
     out[j] = pi;
 }
 __global__ void k_positions(const float* pos, const int* idx, int n_rows, int B, int N, int H, int W,
-                            PosInfo* out, int* err) {
+                            PosInfo* out, int* err, int distinct) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < B) position_info(j, pos, idx, n_rows, N, H, W, out, err);
+    if (j < B) position_info(j, pos, idx, n_rows, N, H, W, out, err, distinct);
+}
+
+// distinct rows for a gradient that reuses an earlier forward's positions:
+// a repeated row is flagged (ptyr_sync reports PTYR_E_ARG) and skipped
+__global__ void k_check_distinct(const int* idx, int B, PosInfo* pinfo, int* err) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < B; j += gridDim.x * blockDim.x)
+        if (repeated_row(j, idx)) {
+            atomicOr(err, ERR_INDEX);
+            pinfo[j].ty = -1;
+        }
 }
 
 // The work a batch shares, in one launch (N = 64, 128): workgroups 0 .. M-1
@@ -81,7 +102,7 @@ template <int N>
 __global__ __launch_bounds__(N * N / 16) void k_prepare(const float* amp, const float* phase, float2* Oc,
                                                         size_t nobj, const float* pos, const int* idx, int n_rows,
                                                         int B, int H, int W, PosInfo* pinfo, int* err,
-                                                        const float2* probe, float2* Phat, int M) {
+                                                        const float2* probe, float2* Phat, int M, int distinct) {
     const int b = blockIdx.x;
     if (b < M) {
         fft2_block<N, -1, false>(probe + (size_t)b * N * N, Phat + (size_t)b * N * N);
@@ -89,7 +110,8 @@ __global__ __launch_bounds__(N * N / 16) void k_prepare(const float* amp, const 
     }
     const int nb = gridDim.x - M;
     if (b == M)
-        for (int j = threadIdx.x; j < B; j += blockDim.x) position_info(j, pos, idx, n_rows, N, H, W, pinfo, err);
+        for (int j = threadIdx.x; j < B; j += blockDim.x)
+            position_info(j, pos, idx, n_rows, N, H, W, pinfo, err, distinct);
     for (size_t i = (size_t)(b - M) * blockDim.x + threadIdx.x; i < nobj; i += (size_t)nb * blockDim.x) {
         float s, c;
         sincosf(phase[i], &s, &c);
@@ -130,12 +152,60 @@ __device__ __forceinline__ double powm1(double v, double p) {
     return pow(v, p - 1.0);
 }
 
-// pass 1 of the loss: per-block sums of E = I_meas^p and of the residual term
-// (ptyr_loss; inside the step k_loss_rows does this per row range)
-__global__ void k_loss_partial(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int NN,
-                               int kind, double p, double* part, int* err) {
-    __shared__ double sh[3 * 256];
-    double sE = 0.0, sR = 0.0, bad = 0.0;
+// The data terms of the loss (Eq. 5 / Eq. 6, or their weighted sum of
+// Eq. 9): term t has kind k[t], power p[t] and weight w[t]; n = 1 or 2.
+struct LossTerms {
+    int n;
+    int k[2];
+    double p[2], w[2];
+};
+
+// per-pixel pieces of data term (kind, p) at model value I and measured value
+// Em (both clamped at 0): the summand of the term's mean, dL/dA without the
+// batch factor, and dL/dI without it
+struct TermVal {
+    double E, R, dI;
+};
+__device__ __forceinline__ TermVal term_val(int kind, double p, double Iv, double Em) {
+    const double A = powp(Iv, p), E = powp(Em, p);
+    TermVal t;
+    t.E = E;
+    double dA;
+    if (kind == PTYR_LOSS_GAUSSIAN) {
+        t.R = (A - E) * (A - E);
+        dA = A - E;
+    } else {
+        t.R = E * log(A + POISSON_EPS) - A;
+        dA = -(E / (A + POISSON_EPS) - 1.0);
+    }
+    t.dI = p == 1.0 ? dA : (Iv > 0.0 ? dA * p * powm1(Iv, p) : 0.0);
+    return t;
+}
+
+// deterministic block sum of NP doubles per thread into part[NP * block + k]
+template <int NP>
+__device__ __forceinline__ void block_partials(double (&v)[NP], double* part) {
+    __shared__ double sh[NP * 256];
+    for (int k = 0; k < NP; ++k) sh[k * 256 + threadIdx.x] = v[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < NP; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NP; ++k) part[NP * blockIdx.x + k] = sh[k * 256];
+}
+
+// loss partial sums per block: E_0, R_0, E_1, R_1 (term means' summands) and
+// the count of non-finite inputs
+constexpr int NLP = 5;
+
+// pass 1 of the loss: per-block partial sums (ptyr_loss; inside the step
+// k_loss_rows does this per row range)
+__global__ __launch_bounds__(256) void k_loss_partial(const float* Im, const float* Ie, const int* midx, int n_meas,
+                                                      int B, int NN, LossTerms lt, double* part, int* err) {
+    double v[NLP] = {0, 0, 0, 0, 0};
     size_t n = (size_t)B * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         size_t j = e / NN, q = e % NN;
@@ -145,52 +215,58 @@ __global__ void k_loss_partial(const float* Im, const float* Ie, const int* midx
             continue;
         }
         double I = Im[e], Em = Ie[(size_t)row * NN + q];
-        if (!isfinite(I) || !isfinite(Em)) { bad += 1.0; continue; }
-        double A = powp(fmax(I, 0.0), p), E = powp(fmax(Em, 0.0), p);
-        sE += E;
-        if (kind == PTYR_LOSS_GAUSSIAN) sR += (A - E) * (A - E);
-        else sR += E * log(A + POISSON_EPS) - A;
+        if (!isfinite(I) || !isfinite(Em)) { v[4] += 1.0; continue; }
+        I = fmax(I, 0.0); Em = fmax(Em, 0.0);
+        for (int t = 0; t < lt.n; ++t) {
+            const TermVal tv = term_val(lt.k[t], lt.p[t], I, Em);
+            v[2 * t] += tv.E;
+            v[2 * t + 1] += tv.R;
+        }
     }
-    sh[threadIdx.x] = sE; sh[256 + threadIdx.x] = sR; sh[512 + threadIdx.x] = bad;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int k = 0; k < 3; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = sh[k * 256];
+    block_partials<NLP>(v, part);
 }
 
-// pass 2: fixed-order total, loss and the gradient scale
-//   Gaussian: L = sqrt(D)/Z, dL/dA = (A-E) / (K sqrt(D) Z)
-//   Poisson : L = -mean(E log(A+eps) - A)/Z, dL/dA = -(E/(A+eps) - 1)/(K Z)
-__global__ void k_loss_final(const double* part, int nblk, double K, int kind, int check, double* scal,
+// pass 2: fixed-order totals, loss and the gradient scales.  Per term t
+//   Gaussian: L_t = sqrt(D)/Z, dL/dA = (A-E) / (K sqrt(D) Z)
+//   Poisson : L_t = -mean(E log(A+eps) - A)/Z, dL/dA = -(E/(A+eps) - 1)/(K Z)
+// and L = sum_t w_t L_t.  scal[5 + t] = w_t c_t (the batch factor of term t,
+// which the per-pixel dI of term_val is missing); scal[1] = the factor the
+// gradient reductions apply to the weights of k_loss_rows (w_0 c_0, or 1
+// when two terms are folded into the weights by k_loss_mix); scal[2] = Z_0.
+__global__ void k_loss_final(const double* part, int nblk, double K, LossTerms lt, int check, double* scal,
                              double* loss_out, int* err, const double* spart, int nsp, double spw) {
-    __shared__ double sh[3 * 256];
-    double s[3] = {0, 0, 0};
+    __shared__ double sh[NLP * 256];
+    double s[NLP] = {0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += 256)
-        for (int k = 0; k < 3; ++k) s[k] += part[3 * b + k];
-    for (int k = 0; k < 3; ++k) sh[k * 256 + threadIdx.x] = s[k];
+        for (int k = 0; k < NLP; ++k) s[k] += part[NLP * b + k];
+    for (int k = 0; k < NLP; ++k) sh[k * 256 + threadIdx.x] = s[k];
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o)
-            for (int k = 0; k < 3; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
+            for (int k = 0; k < NLP; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double sE = sh[0], sR = sh[256], bad = sh[512];
-        double Z = sE / K, L, c;
-        if (!(Z > 0.0)) {
+        const double bad = sh[4 * 256];
+        double L = 0.0, c[2] = {0.0, 0.0}, Z0 = 0.0;
+        bool zero_mean = false;
+        for (int t = 0; t < lt.n; ++t) {
+            const double sE = sh[(2 * t) * 256], sR = sh[(2 * t + 1) * 256];
+            const double Z = sE / K;
+            if (t == 0) Z0 = Z;
+            if (!(Z > 0.0)) { zero_mean = true; continue; }
+            if (lt.k[t] == PTYR_LOSS_GAUSSIAN) {
+                const double D = sR / K;
+                L += lt.w[t] * sqrt(D) / Z;
+                c[t] = D > 0.0 ? lt.w[t] / (K * sqrt(D) * Z) : 0.0;
+            } else {
+                L += lt.w[t] * (-(sR / K) / Z);
+                c[t] = lt.w[t] / (K * Z);
+            }
+        }
+        if (zero_mean) {
             atomicOr(err, ERR_ZERO_MEAN);
-            L = 0.0; c = 0.0;
-        } else if (kind == PTYR_LOSS_GAUSSIAN) {
-            double D = sR / K;
-            L = sqrt(D) / Z;
-            c = D > 0.0 ? 1.0 / (K * sqrt(D) * Z) : 0.0;
-        } else {
-            L = -(sR / K) / Z;
-            c = 1.0 / (K * Z);
+            L = 0.0; c[0] = c[1] = 0.0;
         }
         if (nsp > 0) {                                  // + sparsity term, sums in order
             double t = 0.0;
@@ -199,17 +275,19 @@ __global__ void k_loss_final(const double* part, int nblk, double K, int kind, i
         }
         if (check && (bad > 0.0 || !isfinite(L))) atomicOr(err, ERR_NONFINITE);
         scal[0] = L;
-        scal[1] = c;
-        scal[2] = Z;
+        scal[1] = lt.n > 1 ? 1.0 : c[0];
+        scal[2] = Z0;
+        scal[5] = c[0];
+        scal[6] = c[1];
         if (loss_out) *loss_out = L;
     }
 }
 
 // dL/dI per value, in the layout of I_model (ptyr_loss)
 __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, int n_meas, int B, int N,
-                            int kind, double p, const double* scal, float* dLdI) {
+                            LossTerms lt, const double* scal, float* dLdI) {
     const int NN = N * N;
-    const double c = scal[1];
+    const double c0 = scal[5], c1 = scal[6];
     size_t n = (size_t)B * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         size_t j = e / NN, q = e % NN;
@@ -218,28 +296,24 @@ __global__ void k_loss_grad(const float* Im, const float* Ie, const int* midx, i
             dLdI[e] = 0.f;
             continue;
         }
-        double I = fmax((double)Im[e], 0.0), Em = fmax((double)Ie[(size_t)row * NN + q], 0.0);
-        double A = powp(I, p), E = powp(Em, p);
-        double dA = kind == PTYR_LOSS_GAUSSIAN ? (A - E) * c : -(E / (A + POISSON_EPS) - 1.0) * c;
-        double dI;
-        if (p == 1.0) dI = dA;
-        else dI = I > 0.0 ? dA * p * powm1(I, p) : 0.0;
+        const double I = fmax((double)Im[e], 0.0), Em = fmax((double)Ie[(size_t)row * NN + q], 0.0);
+        double dI = c0 * term_val(lt.k[0], lt.p[0], I, Em).dI;
+        if (lt.n > 1) dI += c1 * term_val(lt.k[1], lt.p[1], I, Em).dI;
         dLdI[e] = (float)dI;
     }
 }
 
 // Rows [row0, row0 + nr) of a batch once their forward chains are done, in
 // one pass: the mode sum I (fftshifted, as k_modesum), per-block loss
-// partial sums (as k_loss_partial) and the gradient weights w = 2 dL/dI
-// without the batch factor (as k_loss_grad with unscaled set).  Imode, I,
-// midx and w2 start at row row0's entries.  A fixed grid and a fixed
-// element-to-block map keep the sums deterministic.
+// partial sums (as k_loss_partial) and the gradient weights w = 2 dL/dI of
+// the first data term without its batch factor.  Imode, I, midx and w2 start
+// at row row0's entries.  A fixed grid and a fixed element-to-block map keep
+// the sums deterministic.
 __global__ __launch_bounds__(256) void k_loss_rows(const float* Imode, float* I, const float* Ie, const int* midx,
-                                                   int n_meas, int nr, int M, int N, int kind, double p, int row0,
+                                                   int n_meas, int nr, int M, int N, LossTerms lt, int row0,
                                                    double* part, float* w2, int* err) {
-    __shared__ double sh[3 * 256];
     const int NN = N * N;
-    double sE = 0.0, sR = 0.0, bad = 0.0;
+    double v[NLP] = {0, 0, 0, 0, 0};
     const size_t n = (size_t)nr * NN;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         const size_t j = e / NN;
@@ -257,26 +331,39 @@ __global__ __launch_bounds__(256) void k_loss_rows(const float* Imode, float* I,
         }
         const float em = Ie[(size_t)row * NN + q];
         const double Iv = fmax((double)sum, 0.0), Em = fmax((double)em, 0.0);
-        const double A = powp(Iv, p), E = powp(Em, p);
-        if (!isfinite(sum) || !isfinite(em)) bad += 1.0;
+        const TermVal t0 = term_val(lt.k[0], lt.p[0], Iv, Em);
+        if (!isfinite(sum) || !isfinite(em)) v[4] += 1.0;
         else {
-            sE += E;
-            if (kind == PTYR_LOSS_GAUSSIAN) sR += (A - E) * (A - E);
-            else sR += E * log(A + POISSON_EPS) - A;
+            v[0] += t0.E;
+            v[1] += t0.R;
+            if (lt.n > 1) {
+                const TermVal t1 = term_val(lt.k[1], lt.p[1], Iv, Em);
+                v[2] += t1.E;
+                v[3] += t1.R;
+            }
         }
-        const double dA = kind == PTYR_LOSS_GAUSSIAN ? (A - E) : -(E / (A + POISSON_EPS) - 1.0);
-        const double dI = p == 1.0 ? dA : (Iv > 0.0 ? dA * p * powm1(Iv, p) : 0.0);
-        *w = (float)(2.0 * dI);
+        *w = (float)(2.0 * t0.dI);
     }
-    sh[threadIdx.x] = sE; sh[256 + threadIdx.x] = sR; sh[512 + threadIdx.x] = bad;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int k = 0; k < 3; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
-        __syncthreads();
+    block_partials<NLP>(v, part);
+}
+
+// Two data terms (Eq. 9): once both batch factors are known, the weights of
+// rows [row0, row0 + B) become w = c_0 w + 2 c_1 dI_1 (scal[5], scal[6]; the
+// reductions then apply scal[1] = 1).  I is the fftshifted mode sum.
+__global__ void k_loss_mix(float* w2, const float* I, const float* Ie, const int* midx, int n_meas, int row0, int B,
+                           int N, LossTerms lt, const double* scal) {
+    const int NN = N * N;
+    const double c0 = scal[5], c1 = scal[6];
+    const size_t n = (size_t)B * NN;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t j = e / NN;
+        const int q = (int)(e % NN);
+        float* w = w2 + j * NN + shift_index(q, N);
+        const long row = midx ? (long)midx[j] : (long)(row0 + j);
+        if (row < 0 || row >= n_meas) continue;      // already 0 and reported
+        const double Iv = fmax((double)I[e], 0.0), Em = fmax((double)Ie[(size_t)row * NN + q], 0.0);
+        *w = (float)(c0 * (double)*w + 2.0 * c1 * term_val(lt.k[1], lt.p[1], Iv, Em).dI);
     }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = sh[k * 256];
 }
 
 // One Adam update of a parameter element (Kingma & Ba, Alg. 1 with the bias
@@ -625,6 +712,32 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 int obj_modes(const ptyr_geom& g) { return g.n_obj > 0 ? g.n_obj : 1; }
 int chain_modes(const ptyr_geom& g) { return g.M * obj_modes(g); }
 
+// the data terms of the loss: the loss_kind term alone at weight 1, or the
+// weighted Gaussian and / or Poisson terms of Eq. 9
+LossTerms loss_terms(const ptyr_geom& g) {
+    LossTerms lt{};
+    if (!(g.w_gaussian > 0.0) && !(g.w_poisson > 0.0)) {
+        lt.n = 1;
+        lt.k[0] = g.loss_kind;
+        lt.p[0] = g.loss_p;
+        lt.w[0] = 1.0;
+        return lt;
+    }
+    if (g.w_gaussian > 0.0) {
+        lt.k[lt.n] = PTYR_LOSS_GAUSSIAN;
+        lt.p[lt.n] = g.p_gaussian > 0.0 ? g.p_gaussian : 0.5;
+        lt.w[lt.n++] = g.w_gaussian;
+    }
+    if (g.w_poisson > 0.0) {
+        lt.k[lt.n] = PTYR_LOSS_POISSON;
+        lt.p[lt.n] = g.p_poisson > 0.0 ? g.p_poisson : 1.0;
+        lt.w[lt.n++] = g.w_poisson;
+    }
+    return lt;
+}
+// two data terms are folded into the weights once both batch factors are known
+bool two_terms(const ptyr_geom& g) { return loss_terms(g).n > 1; }
+
 struct Layout {
     size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, spart, pac, err, store, gO, gPhat, gPsum, part, gamp, gphase,
         gprobe, gdz, gpos, gtilt, wave, cons, rzmat, kz, total;
@@ -668,7 +781,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.Imode = take(B * Mc * NN * sizeof(float));
     L.Ibuf = take(B * NN * sizeof(float));
     L.wbuf = take(B * NN * sizeof(float));
-    L.lpart = take(2 * 3 * NPART * sizeof(double));   // one block of NPART per row range
+    L.lpart = take(2 * NLP * NPART * sizeof(double));   // one block of NPART per row range
     L.scal = take(8 * sizeof(double));
     L.spart = take(B * OS * sizeof(double));           // sparsity-term partial sums
     L.pac = take(2 * NN * sizeof(double) + PAC_BLOCKS * sizeof(double));   // PACBED R, Abar; partial sums
@@ -719,6 +832,7 @@ struct ptyr_ctx {
     int step_grads_clear = 0;   // ptyr_step's gradient buffers are all zero
     // instrumentation: event pairs around the fused kernels
     int timing = 0;
+    int timing_err = 0;              // an event record failed since timing was last enabled
     std::vector<hipEvent_t> ev;      // 2 per launch
     std::vector<int> ev_kind;
     int ev_used = 0;
@@ -726,6 +840,8 @@ struct ptyr_ctx {
 
 namespace {
 constexpr int MAX_TIMED = 4096;
+// A failed event record marks the launch untimed and is reported by the next
+// ptyr_timing_read as PTYR_E_DEVICE.
 struct TimedLaunch {
     ptyr_ctx* c;
     hipStream_t st;
@@ -734,11 +850,18 @@ struct TimedLaunch {
         if (c->timing && c->ev_used < MAX_TIMED) {
             slot = c->ev_used++;
             c->ev_kind[slot] = kind;
-            hipEventRecord(c->ev[2 * slot], st);
+            if (hipEventRecord(c->ev[2 * slot], st) != hipSuccess) {
+                c->ev_kind[slot] = -1;
+                c->timing_err = 1;
+                slot = -1;
+            }
         }
     }
     ~TimedLaunch() {
-        if (slot >= 0) hipEventRecord(c->ev[2 * slot + 1], st);
+        if (slot >= 0 && hipEventRecord(c->ev[2 * slot + 1], st) != hipSuccess) {
+            c->ev_kind[slot] = -1;
+            c->timing_err = 1;
+        }
     }
 };
 }  // namespace
@@ -774,6 +897,8 @@ ptyr_status ptyr_check_geom(const ptyr_geom* g) {
     if (g->n_scan < 0) return PTYR_E_ARG;
     if (!(g->sparse_w >= 0.0) || !isfinite(g->sparse_w)) return PTYR_E_ARG;
     if (!(g->pacbed_w >= 0.0) || !isfinite(g->pacbed_w)) return PTYR_E_ARG;
+    for (double v : {g->w_gaussian, g->w_poisson, g->p_gaussian, g->p_poisson})
+        if (!(v >= 0.0) || !isfinite(v)) return PTYR_E_ARG;
     if (g->N == 256) {   // the line-pass path keeps every wave (no recomputation)
         int keep, K, nck;
         keep_plan(g, &keep, &K, &nck);
@@ -838,28 +963,28 @@ ptyr_status ptyr_create(const ptyr_geom* g, void* workspace, size_t ws_bytes, vo
         hipEventCreateWithFlags(&c->ev_sgrad, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_gdone, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-        ptyr_destroy(c);
+        (void)ptyr_destroy(c);
         return PTYR_E_DEVICE;
     }
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, c->stream, at<float>(c, L.err), (size_t)1);
-    if (hipGetLastError() != hipSuccess) { ptyr_destroy(c); return PTYR_E_DEVICE; }
+    if (hipGetLastError() != hipSuccess) { (void)ptyr_destroy(c); return PTYR_E_DEVICE; }
     *out = c;
     return PTYR_OK;
 }
 
-void ptyr_destroy(ptyr_ctx* ctx) {
-    if (!ctx) return;
-    if (ctx->side) hipStreamSynchronize(ctx->side);
-    for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
-    if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_mid) hipEventDestroy(ctx->ev_mid);
-    if (ctx->ev_loss) hipEventDestroy(ctx->ev_loss);
-    if (ctx->ev_a1) hipEventDestroy(ctx->ev_a1);
-    if (ctx->ev_sgrad) hipEventDestroy(ctx->ev_sgrad);
-    if (ctx->ev_gdone) hipEventDestroy(ctx->ev_gdone);
-    if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
-    if (ctx->side) hipStreamDestroy(ctx->side);
+ptyr_status ptyr_destroy(ptyr_ctx* ctx) {
+    if (!ctx) return PTYR_E_ARG;
+    bool ok = true;
+    auto check = [&](hipError_t e) { ok = ok && e == hipSuccess; };
+    if (ctx->side) check(hipStreamSynchronize(ctx->side));
+    for (hipEvent_t e : ctx->ev)
+        if (e) check(hipEventDestroy(e));
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_mid, ctx->ev_loss, ctx->ev_a1, ctx->ev_sgrad, ctx->ev_gdone,
+                         ctx->ev_join})
+        if (e) check(hipEventDestroy(e));
+    if (ctx->side) check(hipStreamDestroy(ctx->side));
     delete ctx;
+    return ok ? PTYR_OK : PTYR_E_DEVICE;
 }
 
 ptyr_status ptyr_timing_enable(ptyr_ctx* c, int on) {
@@ -868,10 +993,14 @@ ptyr_status ptyr_timing_enable(ptyr_ctx* c, int on) {
         c->ev.resize(2 * MAX_TIMED);
         c->ev_kind.assign(MAX_TIMED, -1);
         for (auto& e : c->ev)
-            if (hipEventCreate(&e) != hipSuccess) return PTYR_E_DEVICE;
+            if (hipEventCreate(&e) != hipSuccess) {
+                e = nullptr;
+                return PTYR_E_DEVICE;
+            }
     }
     c->timing = on ? 1 : 0;
     c->ev_used = 0;
+    c->timing_err = 0;
     return PTYR_OK;
 }
 
@@ -890,7 +1019,7 @@ ptyr_status ptyr_timing_read(ptyr_ctx* c, int which, double* total_ms, int* laun
     }
     *total_ms = tot;
     *launches = n;
-    return PTYR_OK;
+    return c->timing_err ? PTYR_E_DEVICE : PTYR_OK;
 }
 
 ptyr_status ptyr_sync(ptyr_ctx* ctx) {
@@ -1002,14 +1131,14 @@ void gradient_chains(ptyr_ctx* c, const WaveArgs& a, int c0, int nc, hipStream_t
 // no more), four elements per thread at least
 template <int N>
 void launch_prepare(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
-                    const int* idx, int n_rows, int B, size_t nobj, hipStream_t st) {
+                    const int* idx, int n_rows, int B, size_t nobj, hipStream_t st, int distinct) {
     const ptyr_geom& g = c->g;
     constexpr int T = N * N / 16;
     const size_t want = (nobj + 4 * (size_t)T - 1) / (4 * (size_t)T);
     const int nb = (int)std::max<size_t>(1, std::min<size_t>(want, 2 * (size_t)std::max(c->n_cu, 1)));
     hipLaunchKernelGGL(k_prepare<N>, dim3(g.M + nb), dim3(T), 0, st, amp, phase, at<float2>(c, c->L.Oc), nobj, pos,
                        idx, idx ? n_rows : B, B, g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err),
-                       reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat), g.M);
+                       reinterpret_cast<const float2*>(probe), at<float2>(c, c->L.Phat), g.M, distinct);
 }
 template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe, hipStream_t st) {
     hipLaunchKernelGGL((k_fft2<N, +1, true>), dim3(c->g.M), dim3(N * N / 16), 0, st,
@@ -1019,17 +1148,17 @@ template <int N> void launch_probe_ifft_acc(ptyr_ctx* c, float* g_probe, hipStre
 // Work shared by every row of a batch: transmission of all slices, validated
 // positions, probe spectra.
 void prepare_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
-                     const int* idx, int n_rows, int B) {
+                     const int* idx, int n_rows, int B, int distinct) {
     const hipStream_t st = c->stream;
     const ptyr_geom& g = c->g;
     size_t nobj = (size_t)obj_modes(g) * g.S * g.H * g.W;
-    if (g.N == 64) launch_prepare<64>(c, amp, phase, probe, pos, idx, n_rows, B, nobj, st);
-    else if (g.N == 128) launch_prepare<128>(c, amp, phase, probe, pos, idx, n_rows, B, nobj, st);
+    if (g.N == 64) launch_prepare<64>(c, amp, phase, probe, pos, idx, n_rows, B, nobj, st, distinct);
+    else if (g.N == 128) launch_prepare<128>(c, amp, phase, probe, pos, idx, n_rows, B, nobj, st, distinct);
     else {
         hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, st, amp, phase,
                            at<float2>(c, c->L.Oc), nobj);
         hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, st, pos, idx, idx ? n_rows : B, B, g.N,
-                           g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err));
+                           g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err), distinct);
         const dim3 grid(g.M * NBLK256), blk(256);
         hipLaunchKernelGGL((k256_fft<-1, true, false>), grid, blk, 0, st, reinterpret_cast<const float2*>(probe),
                            at<float2>(c, c->L.Phat));
@@ -1048,7 +1177,7 @@ void modesum_rows(ptyr_ctx* c, int r0, int nr, hipStream_t st) {
 
 ptyr_status run_forward(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
                         const float* tilt, const float* dz, const int* idx, int n_rows, int B) {
-    prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
+    prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B, 0);
     forward_chains(c, wave_args(c, tilt, dz, B), 0, B * chain_modes(c->g), c->stream);
     modesum_rows(c, 0, B, c->stream);
     if (hipGetLastError() != hipSuccess) return PTYR_E_DEVICE;
@@ -1067,7 +1196,7 @@ void loss_rows(ptyr_ctx* c, const float* Ie, const int* midx, int nm, int r0, in
     hipLaunchKernelGGL(k_loss_rows, dim3(NPART), dim3(256), 0, st,
                        at<float>(c, c->L.Imode) + (size_t)r0 * chain_modes(g) * NN, at<float>(c, c->L.Ibuf) + (size_t)r0 * NN,
                        Ie, midx ? midx + r0 : nullptr, nm, nr, chain_modes(g), g.N,
-                       g.loss_kind, g.loss_p, r0, at<double>(c, c->L.lpart) + 3 * (size_t)slot * NPART,
+                       loss_terms(g), r0, at<double>(c, c->L.lpart) + NLP * (size_t)slot * NPART,
                        at<float>(c, c->L.wbuf) + (size_t)r0 * NN, at<int>(c, c->L.err));
 }
 
@@ -1078,7 +1207,7 @@ void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev, hipStream_t st
     const double n = (double)B * g.N * g.N;
     const bool sp = with_sparse && g.sparse_w > 0.0;
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, at<double>(c, c->L.lpart), nslots * NPART, n,
-                       g.loss_kind, (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
+                       loss_terms(g), (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
                        at<int>(c, c->L.err), at<double>(c, c->L.spart), sp ? B * g.S * obj_modes(g) : 0,
                        sp ? g.sparse_w / ((double)B * g.S * obj_modes(g) * g.N * g.N) : 0.0);
 }
@@ -1092,12 +1221,13 @@ void pacbed(ptyr_ctx* c, const float* I, const float* Ie, const int* midx, int n
     const int NN = g.N * g.N;
     double* pac = at<double>(c, c->L.pac);
     double* part = pac + 2 * NN;
+    const double p = loss_terms(g).p[0];           // the first data term's power (its normaliser is scal[2])
     hipLaunchKernelGGL(k_pacbed_partial, dim3(PAC_BLOCKS), dim3(256), 0, st, I, Ie, midx, n_meas, row0, B, NN,
-                       g.loss_p, pac, part);
-    hipLaunchKernelGGL(k_pacbed_final, dim3(1), dim3(64), 0, st, part, PAC_BLOCKS, NN, B, g.loss_p, g.pacbed_w,
+                       p, pac, part);
+    hipLaunchKernelGGL(k_pacbed_final, dim3(1), dim3(64), 0, st, part, PAC_BLOCKS, NN, B, p, g.pacbed_w,
                        at<double>(c, c->L.scal), loss_dev, fold ? 1 : 0);
     if (out)
-        hipLaunchKernelGGL(k_pacbed_grad, dim3(grid_for((size_t)B * NN)), dim3(256), 0, st, out, B, g.N, g.loss_p,
+        hipLaunchKernelGGL(k_pacbed_grad, dim3(grid_for((size_t)B * NN)), dim3(256), 0, st, out, B, g.N, p,
                            pac, at<double>(c, c->L.scal), fold ? 1 : 0, fold ? 2.f : 1.f, fold ? 1 : 0);
 }
 
@@ -1107,12 +1237,12 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
     const int NN = g.N * g.N;
     const size_t n = (size_t)B * NN;
     const int nm = midx ? n_meas : B;
-    hipLaunchKernelGGL(k_loss_partial, dim3(NPART), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, g.loss_kind,
-                       g.loss_p, at<double>(c, c->L.lpart), at<int>(c, c->L.err));
+    hipLaunchKernelGGL(k_loss_partial, dim3(NPART), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, loss_terms(g),
+                       at<double>(c, c->L.lpart), at<int>(c, c->L.err));
     loss_final(c, 1, B, loss_dev, c->stream, false);
     if (dLdI)
         hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, g.N,
-                           g.loss_kind, g.loss_p, at<double>(c, c->L.scal), dLdI);
+                           loss_terms(g), at<double>(c, c->L.scal), dLdI);
     if (g.pacbed_w > 0.0) pacbed(c, Im, Ie, midx, nm, 0, B, loss_dev, dLdI, false, c->stream);
     return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
@@ -1133,7 +1263,7 @@ ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* m
 int split_chains(const ptyr_ctx* c, int B) {
     const ptyr_geom& g = c->g;
     const int Mc = chain_modes(g);
-    if (g.N > 128 || c->n_cu <= 0 || B * Mc <= c->n_cu || g.pacbed_w > 0.0) return 0;
+    if (g.N > 128 || c->n_cu <= 0 || B * Mc <= c->n_cu || g.pacbed_w > 0.0 || two_terms(g)) return 0;
     return c->n_cu / Mc >= 1 ? c->n_cu : 0;
 }
 
@@ -1146,7 +1276,11 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     const int M = chain_modes(g), nm = idx ? n_rows : B, BM = B * M;   // M: chain modes
     const bool reuse = (flags & PTYR_REUSE_FORWARD) && c->fwd_valid && c->fwd_B == B;
     const int nA = reuse ? 0 : split_chains(c, B);
-    if (!reuse) prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B);
+    const bool fold = g.pacbed_w > 0.0 || two_terms(g);     // weights finished before the gradient
+    if (!reuse) prepare_forward(c, amp, phase, probe, pos, idx, n_rows, B, 1);
+    else if (idx)
+        hipLaunchKernelGGL(k_check_distinct, dim3(1), dim3(256), 0, c->stream, idx, B, at<PosInfo>(c, c->L.pinfo),
+                           at<int>(c, c->L.err));
     // sparsity term: |phase| over the batch's patches, before any update of the phase
     const bool sparse = g.sparse_w > 0.0;
     if (sparse)
@@ -1266,19 +1400,25 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
     } else {
         if (!reuse) forward_chains(c, a, 0, BM, c->stream);
         loss_rows(c, I_meas, idx, nm, 0, B, 0, c->stream);
-        if (g.pacbed_w > 0.0) {
-            // the PACBED weights need every row's pattern and the data term's
-            // batch factor before the gradient: fold both into the weights
+        if (fold) {
+            // the weights of two data terms and the PACBED weights need every
+            // row's pattern and the batch factors before the gradient: fold
+            // them into the weights
             loss_final(c, 1, B, loss_dev, c->stream, true);
-            pacbed(c, at<float>(c, c->L.Ibuf), I_meas, idx, nm, 0, B, loss_dev, at<float>(c, c->L.wbuf), true,
-                   c->stream);
+            if (two_terms(g))
+                hipLaunchKernelGGL(k_loss_mix, dim3(grid_for((size_t)B * g.N * g.N)), dim3(256), 0, c->stream,
+                                   at<float>(c, c->L.wbuf), at<float>(c, c->L.Ibuf), I_meas, idx, nm, 0, B, g.N,
+                                   loss_terms(g), at<double>(c, c->L.scal));
+            if (g.pacbed_w > 0.0)
+                pacbed(c, at<float>(c, c->L.Ibuf), I_meas, idx, nm, 0, B, loss_dev, at<float>(c, c->L.wbuf), true,
+                       c->stream);
         }
         gradient_chains(c, a, 0, BM, c->stream);
     }
     c->fwd_valid = 1;
     c->fwd_B = B;
     if (!scattered) {
-        if (!(g.pacbed_w > 0.0)) loss_final(c, 1, B, loss_dev, c->stream, true);
+        if (!fold) loss_final(c, 1, B, loss_dev, c->stream, true);
         reductions(c->stream);
         seg_adam();
         scatter(0, B, c->stream, true);

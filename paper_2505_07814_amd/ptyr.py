@@ -41,6 +41,9 @@ class Engine:
     """One libptyr context: geometry, workspace and stream.
 
     loss: 'gaussian' (Eq. 5, default p=0.5) or 'poisson' (Eq. 6, default p=1);
+    w_gaussian, w_poisson: weights w_1, w_2 of Eq. 9's two data terms (both 0 =
+    the `loss` term alone at weight 1), with powers p_gaussian, p_poisson
+    (None = 0.5 and 1);
     sparse_w: weight of the L1 sparsity term of the object phase (0 = off);
     pacbed_w: weight of the PACBED term of the batch-mean patterns (0 = off).
     wave_budget: bytes the forward may keep for the gradient (None = all
@@ -49,7 +52,7 @@ class Engine:
 
     def __init__(self, N, M, S, H, W, B_max, dx, lam, loss="gaussian", p=None, wave_budget=None,
                  global_tilt=False, check_finite=False, n_scan=0, sparse_w=0.0, pacbed_w=0.0, n_obj=1,
-                 device=None, stream=None):
+                 w_gaussian=0.0, w_poisson=0.0, p_gaussian=None, p_poisson=None, device=None, stream=None):
         self.lib = L.lib()
         kind = {"gaussian": L.PTYR_LOSS_GAUSSIAN, "poisson": L.PTYR_LOSS_POISSON}[loss]
         if p is None:
@@ -59,7 +62,8 @@ class Engine:
         flags = (L.PTYR_GLOBAL_TILT if global_tilt else 0) | (L.PTYR_CHECK_FINITE if check_finite else 0)
         self.geom = L.Geom(N, M, S, H, W, B_max, float(dx), float(lam), kind, float(p),
                            int(wave_budget), flags, int(n_scan), float(sparse_w),
-                           float(pacbed_w), int(n_obj))
+                           float(pacbed_w), int(n_obj), float(w_gaussian), float(w_poisson),
+                           float(p_gaussian or 0.0), float(p_poisson or 0.0))
         L.check(self.lib.ptyr_check_geom(C.byref(self.geom)), "geometry")
         self.N, self.M, self.S, self.H, self.W, self.B_max = N, M, S, H, W, B_max
         self.n_obj = int(n_obj)
@@ -252,24 +256,35 @@ class MultisliceLoss(torch.autograd.Function):
     """Loss of the multislice model as an autograd node whose backward is the
     library's hand-derived gradient (no autograd graph through the model).
     The backward reuses the waves the forward kept (or recomputes them per
-    slice from checkpoints when the engine's wave budget is smaller)."""
+    slice from checkpoints when the engine's wave budget is smaller).
+
+    The value is the engine's whole loss: with a sparsity term (sparse_w > 0),
+    which needs the batch's object patches rather than the intensities, the
+    forward runs ptyr_adjoint at once (value and gradient of the same
+    function) and the backward scales the gradients it kept."""
 
     @staticmethod
     def forward(ctx, amp, phase, probe, pos, tilt, dz, I_meas, engine, idx):
+        ctx.engine = engine
+        ctx.idx = idx
+        ctx.grads = None
+        if engine.geom.sparse_w > 0.0:
+            loss, ctx.grads = engine.adjoint(amp, phase, probe, pos, tilt, dz, I_meas, idx=idx)
+            return loss[0]
         I = engine.forward(amp, phase, probe, pos, tilt, dz, idx=idx)
         loss, _ = engine.loss(I, I_meas, meas_idx=idx)
-        ctx.engine = engine
         ctx.epoch = engine.forward_epoch
-        ctx.idx = idx
         ctx.save_for_backward(amp, phase, probe, pos, tilt, dz, I_meas)
         return loss[0]
 
     @staticmethod
     def backward(ctx, grad_loss):
-        amp, phase, probe, pos, tilt, dz, I_meas = ctx.saved_tensors
-        eng = ctx.engine
-        reuse = eng.forward_epoch == ctx.epoch
-        _, g = eng.adjoint(amp, phase, probe, pos, tilt, dz, I_meas, idx=ctx.idx, reuse=reuse)
+        g = ctx.grads
+        if g is None:
+            amp, phase, probe, pos, tilt, dz, I_meas = ctx.saved_tensors
+            eng = ctx.engine
+            reuse = eng.forward_epoch == ctx.epoch
+            _, g = eng.adjoint(amp, phase, probe, pos, tilt, dz, I_meas, idx=ctx.idx, reuse=reuse)
         gl = grad_loss.to(torch.float32)
         out = []
         for k, need in zip(("amp", "phase", "probe", "pos", "tilt", "dz"), ctx.needs_input_grad[:6]):

@@ -22,7 +22,7 @@ def header_functions(name="ptyr.h"):
 def geom(**kw):
     d = dict(N=128, M=6, S=12, H=640, W=640, B_max=64, dx=0.15, lam=0.0197, loss_kind=0, loss_p=0.5,
              wave_budget_bytes=64 * 6 * 24 * 128 * 128 * 8, flags=0, n_scan=16384, sparse_w=0.0, pacbed_w=0.0,
-             n_obj=0)
+             n_obj=0, w_gaussian=0.0, w_poisson=0.0, p_gaussian=0.0, p_poisson=0.0)
     d.update(kw)
     return L.Geom(*[d[f[0]] for f in L.Geom._fields_])
 
@@ -63,6 +63,12 @@ def test_status_strings():
     (dict(n_obj=-1), L.PTYR_E_ARG),
     (dict(n_obj=65), L.PTYR_E_ARG),
     (dict(n_scan=-1), L.PTYR_E_ARG),
+    (dict(w_gaussian=0.5, w_poisson=0.5), L.PTYR_OK),
+    (dict(w_gaussian=0.5, p_gaussian=1.0), L.PTYR_OK),
+    (dict(w_gaussian=-0.5), L.PTYR_E_ARG),
+    (dict(w_poisson=float("nan")), L.PTYR_E_ARG),
+    (dict(p_poisson=-1.0), L.PTYR_E_ARG),
+    (dict(p_gaussian=float("inf")), L.PTYR_E_ARG),
 ])
 def test_check_geom(kw, expect):
     g = geom(**kw)

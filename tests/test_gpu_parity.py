@@ -144,7 +144,7 @@ def _check_grads(c, eng, kind="gaussian", p=None, tol=1e-4, **kw):
         errs["tilt"] = rel(g["tilt"].cpu().numpy(), ref.tilt)
     print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for k, v in errs.items():
-        assert v < (1e-5 if k == "loss" else tol), (k, v)
+        assert v < (1e-6 if k == "loss" else tol), (k, v)
     return g
 
 
@@ -312,7 +312,7 @@ def test_adam_step_parity():
         assert err < 1e-3, (k, err)
 
 
-@pytest.mark.parametrize("which", ["all", "phase_only", "sparse", "pacbed"])
+@pytest.mark.parametrize("which", ["all", "phase_only", "sparse", "pacbed", "terms"])
 def test_step_split_batch_matches_adjoint_then_adam(which):
     """ptyr_step on a batch of more chains than compute units (two-stream
     schedule, the object's Adam fused into the batch's last scatter) equals
@@ -330,8 +330,9 @@ def test_step_split_batch_matches_adjoint_then_adam(which):
         lr = dict(amp=0.0, phase=2e-3, probe=0.0, pos=0.0, tilt=0.0, dz=0.0)
     sw = 0.1 if which == "sparse" else 0.0
     pw = 0.5 if which == "pacbed" else 0.0              # one stream: the batch means couple the rows
-    eng = Engine(64, 3, 3, w.H, w.W, 90, w.dx, c.lam, device=DEV, n_scan=90, sparse_w=sw, pacbed_w=pw)
-    ref_eng = c.engine(sparse_w=sw, pacbed_w=pw)
+    kw = _mix_engine_kw() if which == "terms" else {}     # one stream: the weights need both batch factors
+    eng = Engine(64, 3, 3, w.H, w.W, 90, w.dx, c.lam, device=DEV, n_scan=90, sparse_w=sw, pacbed_w=pw, **kw)
+    ref_eng = c.engine(sparse_w=sw, pacbed_w=pw, **kw)
     st = AdamState(*[t.clone() for t in c.gpu_args()])
     meas = T(c.meas)
     b1, b2, eps = float(np.float32(0.9)), float(np.float32(0.999)), float(np.float32(1e-8))
@@ -493,10 +494,32 @@ def test_autograd_function_matches_adjoint():
     loss = multislice_loss(eng, *args, T(c.meas))
     (2.0 * loss).backward()
     ref = c.oracle_grad()
-    assert abs(float(loss.detach().cpu()) - ref.loss) < 1e-5 * abs(ref.loss)
+    assert abs(float(loss.detach().cpu()) - ref.loss) < 1e-6 * abs(ref.loss)
     assert rel(args[1].grad.cpu().numpy(), 2 * ref.phase) < 1e-4
     assert rel(args[2].grad.cpu().numpy(), 2 * ref.probe) < 1e-4
     assert rel(args[3].grad.cpu().numpy(), 2 * ref.pos) < 1e-4
+
+
+def test_autograd_function_with_sparsity_matches_oracle():
+    """With the sparsity term the autograd node's value and gradient are those
+    of the same loss (data term + 0.1 x L1 of the phase over the batch's
+    patches): both against the oracle's gradients(..., sparse_w=0.1)."""
+    from paper_2505_07814_amd.ptyr import multislice_loss
+    c = Case(small(64, 3, 2, 4, 28))
+    eng = c.engine(sparse_w=0.1)
+    args = [t.clone().requires_grad_(True) for t in c.gpu_args()]
+    loss = multislice_loss(eng, *args, T(c.meas))
+    (3.0 * loss).backward()
+    ref = ms.gradients(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, c.w.dx, c.lam, c.meas, sparse_w=0.1)
+    el = abs(float(loss.detach().cpu()) - ref.loss) / abs(ref.loss)
+    errs = {k: rel(a.grad.cpu().numpy(), 3 * getattr(ref, k)) for k, a in
+            zip(("amp", "phase", "probe", "pos", "tilt"), args[:5])}
+    print(f"loss {el:.2e}", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert el < 1e-6
+    for k, v in errs.items():
+        assert v < 1e-4, (k, v)
+    Ls, _ = ms.sparse_term(c.phase, c.pos, 64)
+    assert 0.1 * Ls > 1e-3 * abs(ref.loss)            # the term is really in the value
 
 
 # ---------------------------------------------------------------- N = 256 (line passes through HBM)
@@ -535,3 +558,222 @@ def test_gradient_parity_large_256():
     print("gradient large_256 B=2", flush=True)
     c = Case(synth.workload("large_256", scan=2))
     _check_grads(c, c.engine())
+
+
+def test_gradient_parity_large_256_launch_batch():
+    """The N=256 / 30-slice / 8-mode workload at its launch batch of 16 (the
+    configuration the benchmark times): loss and all six gradients against the
+    oracle, which runs one position per worker process.  The object gradient
+    is compared on the window the batch's patches cover and must be exactly
+    zero outside it."""
+    from tests import oracle_pool
+    print("gradient large_256 B=16", flush=True)
+    w = synth.workload("large_256", scan=16)
+    lam = synth.wavelength_A(w.kv)
+    rng = np.random.default_rng(1000)
+    amp_t, ph_t = w.amp.astype(np.float32), w.phase.astype(np.float32)
+    probe, pos, tilt, dz = w.probe.astype(np.complex64), w.pos.astype(np.float32), w.tilt.astype(np.float32), \
+        np.float32(w.dz)
+    I_true = oracle_pool.intensities(amp_t, ph_t, probe, pos, tilt, dz, w.dx, lam)
+    print("oracle intensities done", flush=True)
+    meas = rng.poisson(I_true).astype(np.float32)
+    amp = (1.0 + 0.9 * (amp_t - 1.0)).astype(np.float32)
+    phase = (0.8 * ph_t + 0.02 * rng.standard_normal(ph_t.shape)).astype(np.float32)
+    ref = oracle_pool.gradients(amp, phase, probe, pos, tilt, dz, w.dx, lam, meas)
+    print("oracle gradients done", flush=True)
+    from paper_2505_07814_amd.ptyr import Engine
+    eng = Engine(w.N, w.M, w.S, w.H, w.W, 16, w.dx, lam, device=DEV)
+    args = (T(amp), T(phase), T(probe), T(pos), T(tilt), T(np.array([dz], np.float32)))
+    loss, g = eng.adjoint(*args, T(meas))
+    eng.sync()
+    (y0, y1), (x0, x1) = ref["window"]
+    errs = {"loss": abs(float(loss.cpu()[0]) - ref["loss"]) / abs(ref["loss"])}
+    for k in ("amp", "phase"):
+        full = g[k].cpu().numpy()
+        errs[k] = rel(full[:, y0:y1, x0:x1], ref[k])
+        full[:, y0:y1, x0:x1] = 0
+        assert not full.any(), k
+    for k in ("probe", "pos", "tilt"):
+        errs[k] = rel(g[k].cpu().numpy(), ref[k])
+    errs["dz"] = rel(g["dz"].cpu().numpy(), [ref["dz"]])
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < (1e-6 if k == "loss" else 1e-4), (k, v)
+
+
+# ---------------------------------------------------------------- global tilt, error paths
+@pytest.mark.parametrize("N,S,M,B,seed", [(64, 4, 2, 5, 51), (128, 3, 2, 3, 52)])
+def test_global_tilt_parity(N, S, M, B, seed):
+    """PTYR_GLOBAL_TILT: one (th_y, th_x) pair for every position.  The forward
+    equals the oracle's with that pair repeated for each position; the tilt
+    gradient is the sum of the oracle's per-position tilt gradients; the other
+    five gradients match as usual."""
+    print(f"global tilt N={N} S={S} M={M} B={B}", flush=True)
+    c = Case(small(N, S, M, B, seed))
+    th = np.array([1.5e-3, -2.5e-3], np.float32)
+    tilt_rows = np.tile(th, (B, 1))
+    I_ref = ms.forward(c.amp, c.phase, c.probe, c.pos, tilt_rows, c.dz, c.w.dx, c.lam)
+    ref = ms.gradients(c.amp, c.phase, c.probe, c.pos, tilt_rows, c.dz, c.w.dx, c.lam, c.meas)
+    eng = c.engine(global_tilt=True)
+    args = list(c.gpu_args())
+    args[4] = T(th)
+    I = eng.forward(*args)
+    loss, g = eng.adjoint(*args, T(c.meas))
+    eng.sync()
+    errs = {"I": rel(I.cpu().numpy(), I_ref),
+            "loss": abs(float(loss.cpu()[0]) - ref.loss) / abs(ref.loss),
+            "amp": rel(g["amp"].cpu().numpy(), ref.amp), "phase": rel(g["phase"].cpu().numpy(), ref.phase),
+            "probe": rel(g["probe"].cpu().numpy(), ref.probe), "pos": rel(g["pos"].cpu().numpy(), ref.pos),
+            "tilt": rel(g["tilt"].cpu().numpy(), ref.tilt.sum(axis=0)),
+            "dz": rel(g["dz"].cpu().numpy(), [ref.dz])}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert tuple(g["tilt"].shape) == (2,)
+    for k, v in errs.items():
+        assert v < {"I": 1e-5, "loss": 1e-6}.get(k, 1e-4), (k, v)
+
+
+def test_global_tilt_step_parity():
+    """ptyr_step with a global tilt: the tilt's Adam sees the summed gradient."""
+    from paper_2505_07814_amd.ptyr import AdamState, Engine
+    w = small(64, 3, 2, 6, 53)
+    c = Case(w)
+    th = np.array([1e-3, 2e-3], np.float32)
+    eng = Engine(64, 2, 3, w.H, w.W, 6, w.dx, c.lam, device=DEV, n_scan=6, global_tilt=True)
+    args = list(c.gpu_args())
+    args[4] = T(th)
+    st = AdamState(*[t.clone() for t in args])
+    lr = dict(tilt=1e-4)
+    idx = torch.arange(6, dtype=torch.int32, device=DEV)
+    eng.step(st, idx, T(c.meas), lr)
+    eng.sync()
+    ref = ms.gradients(c.amp, c.phase, c.probe, c.pos, np.tile(th, (6, 1)), c.dz, w.dx, c.lam, c.meas)
+    rp, _, _ = adam_step(th.astype(np.float64), ref.tilt.sum(axis=0), np.zeros(2), np.zeros(2), 0, 1e-4)
+    got = st.tilt.cpu().numpy().astype(np.float64)
+    # the first Adam step moves each entry by lr * sign(g) (to eps): the sign is what matters
+    assert np.allclose(got, rp, rtol=0, atol=1e-8), (got, rp)
+    for k in ("amp", "phase", "probe", "pos", "dz"):
+        assert torch.equal(getattr(st, k), args[("amp", "phase", "probe", "pos", "tilt", "dz").index(k)]), k
+
+
+def test_nonfinite_pattern_is_reported():
+    """PTYR_CHECK_FINITE: a NaN in the measured batch is reported by ptyr_sync
+    as PTYR_E_NONFINITE (the same batch without the flag is not checked)."""
+    from paper_2505_07814_amd import _lib as L
+    c = Case(small(64, 2, 1, 3, 54))
+    meas = c.meas.copy()
+    meas[1, 5, 7] = np.nan
+    eng = c.engine(check_finite=True)
+    eng.adjoint(*c.gpu_args(), T(meas))
+    with pytest.raises(L.PtyrError) as e:
+        eng.sync()
+    assert e.value.status == L.PTYR_E_NONFINITE
+    eng.adjoint(*c.gpu_args(), T(c.meas))
+    eng.sync()                                             # flag cleared, finite data pass
+    I = T(np.abs(c.I_true).astype(np.float32))
+    eng.loss(I, T(meas))
+    with pytest.raises(L.PtyrError) as e:
+        eng.sync()
+    assert e.value.status == L.PTYR_E_NONFINITE
+
+
+def test_zero_measured_batch_is_reported():
+    """A measured batch that is zero everywhere has no loss normaliser (Eq. 5-6
+    divide by its mean): ptyr_sync reports PTYR_E_ARG, and the loss and the
+    gradients stay zero instead of NaN."""
+    from paper_2505_07814_amd import _lib as L
+    c = Case(small(64, 2, 1, 3, 55))
+    eng = c.engine()
+    zero = np.zeros_like(c.meas)
+    loss, g = eng.adjoint(*c.gpu_args(), T(zero))
+    with pytest.raises(L.PtyrError) as e:
+        eng.sync()
+    assert e.value.status == L.PTYR_E_ARG
+    assert float(loss.cpu()[0]) == 0.0
+    for k, v in g.items():
+        assert torch.isfinite(v).all() and not v.any(), k
+    L0, _ = eng.loss(T(c.I_true.astype(np.float32)), T(zero))
+    with pytest.raises(L.PtyrError) as e:
+        eng.sync()
+    assert e.value.status == L.PTYR_E_ARG
+
+
+@pytest.mark.parametrize("reuse", [False, True])
+def test_repeated_row_is_reported(reuse):
+    """A gradient batch must hold distinct rows: a row met again is skipped and
+    reported by ptyr_sync as PTYR_E_ARG; the gradient is that of the batch
+    without the repeat."""
+    from paper_2505_07814_amd import _lib as L
+    c = Case(small(64, 2, 1, 4, 56))
+    eng = c.engine()
+    idx = torch.tensor([0, 2, 2, 3], dtype=torch.int32, device=DEV)
+    if reuse:
+        eng.forward(*c.gpu_args(), idx=idx)
+        eng.sync()                                       # the forward allows repeats
+    loss, g = eng.adjoint(*c.gpu_args(), T(c.meas), idx=idx, reuse=reuse)
+    with pytest.raises(L.PtyrError) as e:
+        eng.sync()
+    assert e.value.status == L.PTYR_E_ARG
+    rows = [0, 2, 3]
+    ref = ms.gradients(c.amp, c.phase, c.probe, c.pos[rows], c.tilt[rows], c.dz, c.w.dx, c.lam, c.meas[rows])
+    # the skipped row's detector values are left out of the gradient and of the
+    # loss sums but still count in the batch size of the means: compare what
+    # does not depend on that normalisation, the direction of the phase gradient
+    gp = g["phase"].cpu().numpy()
+    cos = float(np.vdot(gp, ref.phase) / (np.linalg.norm(gp) * np.linalg.norm(ref.phase)))
+    assert cos > 1 - 1e-6, cos
+    gpos = g["pos"].cpu().numpy()
+    assert not gpos[1].any()                              # row 1 never used
+    eng.adjoint(*c.gpu_args(), T(c.meas), idx=torch.tensor([0, 1, 2, 3], dtype=torch.int32, device=DEV))
+    eng.sync()
+
+
+# ---------------------------------------------------------------- weighted data terms (Eq. 9)
+TERMS = [("gaussian", 0.7, 0.5), ("poisson", 0.4, 1.0)]
+
+
+def _mix_engine_kw():
+    return dict(w_gaussian=0.7, w_poisson=0.4, p_gaussian=0.5, p_poisson=1.0)
+
+
+def test_loss_terms_parity():
+    """ptyr_loss with w_1 L_Gaussian(p=0.5) + w_2 L_Poisson(p=1), alone and with
+    the PACBED term: loss and dL/dI against the oracle."""
+    rng = np.random.default_rng(57)
+    Im = rng.gamma(2.0, 20.0, (5, 64, 64)).astype(np.float32)
+    Im[:, :3, :3] = 0.0
+    Ie = rng.poisson(Im + 0.5).astype(np.float32)
+    from paper_2505_07814_amd.ptyr import Engine
+    for pw in (0.0, 0.5):
+        eng = Engine(64, 1, 1, 64, 64, 5, 0.2, 0.02, pacbed_w=pw, device=DEV, **_mix_engine_kw())
+        L, g = eng.loss(T(Im), T(Ie), want_grad=True)
+        eng.sync()
+        L0, g0 = ms.loss(Im, Ie, terms=TERMS, pacbed_w=pw)
+        el, eg = abs(float(L.cpu()[0]) - L0) / abs(L0), rel(g.cpu().numpy(), g0)
+        print(f"pacbed_w={pw}: loss {el:.2e} dL/dI {eg:.2e}", flush=True)
+        assert el <= 1e-6 and eg < 1e-6
+
+
+@pytest.mark.parametrize("B", [5, 90])
+def test_loss_terms_gradient_parity(B):
+    """Loss and all six gradients with both data terms weighted (one stream:
+    the weights need both batch factors); B = 90 would otherwise take the
+    two-stream schedule."""
+    print(f"weighted data terms B={B}", flush=True)
+    if B == 90:
+        w = synth.small_case(N=64, S=3, M=3, B=90, H=64 + 60, W=64 + 70, seed=31)
+    else:
+        w = small(64, 3, 2, 5, 12)
+    c = Case(w)
+    eng = c.engine(**_mix_engine_kw())
+    loss, g = eng.adjoint(*c.gpu_args(), T(c.meas))
+    eng.sync()
+    ref = ms.gradients(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, w.dx, c.lam, c.meas, terms=TERMS)
+    errs = {"loss": abs(float(loss.cpu()[0]) - ref.loss) / abs(ref.loss)}
+    for k in ("amp", "phase", "probe", "pos", "tilt"):
+        errs[k] = rel(g[k].cpu().numpy(), getattr(ref, k))
+    errs["dz"] = rel(g["dz"].cpu().numpy(), [ref.dz])
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < (1e-6 if k == "loss" else 1e-4), (k, v)
+    ref1 = ms.gradients(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, w.dx, c.lam, c.meas, terms=TERMS[:1])
+    assert rel(ref.phase, ref1.phase) > 1e-3            # the second term is really there

@@ -421,3 +421,27 @@ def test_parameter_counts_match_paper():
 
 def test_wavelength_300kv():
     assert abs(synth.wavelength_A(300.0) - 0.0196875) < 2e-7
+
+
+def test_position_pool_equals_batch_gradient():
+    """The per-position worker pool used for the N = 256 launch batch gives the
+    oracle's batch gradient (object gradient on the patches' window)."""
+    from tests import oracle_pool
+    c = synth.small_case(N=16, S=3, M=2, B=4, seed=43)
+    lam = synth.wavelength_A(c.kv)
+    rng = np.random.default_rng(44)
+    I = ms.forward(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, c.dx, lam)
+    meas = rng.poisson(I * 50.0 / I.max() + 0.5).astype(np.float64)
+    ref = ms.gradients(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, c.dx, lam, meas)
+    got = oracle_pool.gradients(c.amp, c.phase, c.probe, c.pos, c.tilt, c.dz, c.dx, lam, meas, workers=2)
+    (y0, y1), (x0, x1) = got["window"]
+    assert abs(got["loss"] - ref.loss) <= 1e-14 * abs(ref.loss)
+    for k in ("probe", "pos", "tilt"):
+        assert np.allclose(got[k], getattr(ref, k), rtol=1e-12, atol=1e-14 * np.abs(getattr(ref, k)).max())
+    assert abs(got["dz"] - ref.dz) <= 1e-12 * abs(ref.dz)
+    for k in ("amp", "phase"):
+        full = getattr(ref, k)
+        assert np.allclose(got[k], full[:, y0:y1, x0:x1], rtol=1e-12, atol=1e-14 * np.abs(full).max())
+        outside = full.copy()
+        outside[:, y0:y1, x0:x1] = 0
+        assert not outside.any()
