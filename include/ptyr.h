@@ -205,6 +205,38 @@ ptyr_status ptyr_loss(ptyr_ctx* ctx, const float* I_model, const float* I_meas,
                       const int* meas_idx, int n_meas, int B, double* loss_dev,
                       float* dLdI);
 
+/* Allocation-free ptyr_loss, for callers that cannot allocate device memory
+ * while they run (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same kernels and results as ptyr_loss
+ * (bit for bit, same launch shapes), but no context: the loss geometry comes
+ * from g (N, loss_kind / loss_p or the Eq. 9 weights, pacbed_w,
+ * PTYR_CHECK_FINITE; the whole struct must pass ptyr_check_geom), the work
+ * is enqueued on `stream` (hipStream_t as void*, NULL = default) of the
+ * current device, and the loss passes' scratch (partial sums, batch scalars,
+ * PACBED buffers: PTYR_NOALLOC_SCRATCH_BYTES) lives in a static device array
+ * of the library, one per GPU, held until the process ends.  The call makes
+ * no hipMalloc / hipFree and no allocating library call; the first call on a
+ * device looks the array's address up (hipGetSymbolAddress).
+ *  err_dev: one device int (required) that the kernels OR their error bits
+ *    into (PTYR_ERRBIT_*: a measured-row index outside [0, n_meas), a zero
+ *    data mean, NaN/Inf with PTYR_CHECK_FINITE); the caller clears it and
+ *    reads it after synchronising the stream.
+ *  Calls on one GPU share that GPU's scratch: calls that overlap in time
+ *    (several streams or host threads) race and must be serialised by the
+ *    caller.  The scratch is never read before the call writes it, so
+ *    nothing needs clearing between calls.
+ * Returns PTYR_E_ARG as ptyr_loss (and for err_dev NULL), PTYR_E_NOMEM if
+ * the geometry needs more scratch than the array holds (not reachable with
+ * N <= 256), PTYR_E_DEVICE if the array's address cannot be found. */
+#define PTYR_NOALLOC_SCRATCH_BYTES ((5 * 512 + 8 + 2 * 256 * 256 + 64) * 8)
+#define PTYR_ERRBIT_BOUNDS    0x1
+#define PTYR_ERRBIT_NONFINITE 0x2
+#define PTYR_ERRBIT_ZERO_MEAN 0x4
+#define PTYR_ERRBIT_INDEX     0x8
+ptyr_status ptyr_loss_noalloc(const ptyr_geom* g, const float* I_model, const float* I_meas,
+                              const int* meas_idx, int n_meas, int B, double* loss_dev,
+                              float* dLdI, int* err_dev, void* stream);
+
 /* Loss and its gradient with respect to object amplitude and phase, probe,
  * positions, tilts and dz (chain rule through Eq. 1-6).  Runs the forward
  * itself unless flags has PTYR_REUSE_FORWARD.  idx (nullable, B device ints in

@@ -12,6 +12,8 @@ PTYR_LOSS_GAUSSIAN, PTYR_LOSS_POISSON = 0, 1
 PTYR_GLOBAL_TILT = 0x1
 PTYR_CHECK_FINITE = 0x2
 PTYR_REUSE_FORWARD = 0x1
+PTYR_ERRBIT_BOUNDS, PTYR_ERRBIT_NONFINITE, PTYR_ERRBIT_ZERO_MEAN, PTYR_ERRBIT_INDEX = 0x1, 0x2, 0x4, 0x8
+PTYR_NOALLOC_SCRATCH_BYTES = (5 * 512 + 8 + 2 * 256 * 256 + 64) * 8
 
 STATUS_NAMES = {0: "PTYR_OK", 1: "PTYR_E_ARG", 2: "PTYR_E_BOUNDS", 3: "PTYR_E_NOMEM",
                 4: "PTYR_E_DEVICE", 5: "PTYR_E_NONFINITE"}
@@ -78,6 +80,7 @@ def lib():
         "ptyr_sync": (st, [vp]),
         "ptyr_forward": (st, [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, vp]),
         "ptyr_loss": (st, [vp, vp, vp, vp, C.c_int, C.c_int, vp, vp]),
+        "ptyr_loss_noalloc": (st, [C.POINTER(Geom), vp, vp, vp, C.c_int, C.c_int, vp, vp, vp, vp]),
         "ptyr_adjoint": (st, [vp, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, vp,
                               vp, vp, vp, vp, vp, vp, vp, C.c_uint]),
         "ptyr_step": (st, [vp, C.POINTER(Params), vp, C.c_int, vp, C.POINTER(LR), vp]),
@@ -110,7 +113,7 @@ def check(status, what):
 
 HEADER_SYMBOLS = ["ptyr_status_str", "ptyr_check_geom", "ptyr_check_args", "ptyr_workspace_bytes",
                   "ptyr_checkpoint_plan", "ptyr_create", "ptyr_destroy", "ptyr_sync", "ptyr_forward",
-                  "ptyr_loss", "ptyr_adjoint", "ptyr_step", "ptyr_constrain", "ptyr_timing_enable",
+                  "ptyr_loss", "ptyr_loss_noalloc", "ptyr_adjoint", "ptyr_step", "ptyr_constrain", "ptyr_timing_enable",
                   "ptyr_timing_read"]
 
 CNN_HEADER_SYMBOLS = ["ptyr_cnn_param_count", "ptyr_cnn_workspace_bytes", "ptyr_cnn_create", "ptyr_cnn_destroy",

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1200,51 +1201,114 @@ void loss_rows(ptyr_ctx* c, const float* Ie, const int* midx, int nm, int r0, in
                        at<float>(c, c->L.wbuf) + (size_t)r0 * NN, at<int>(c, c->L.err));
 }
 
+// Device buffers of the loss passes: partial sums (NLP per block, one range
+// of NPART blocks per row range), batch scalars (8 doubles), PACBED buffers
+// (2 N^2 + PAC_BLOCKS doubles), the error flag, and the sparsity partial sums
+// (nullable).  A context takes them from its workspace; ptyr_loss_noalloc
+// from the library's static device scratch.
+struct LossBufs {
+    double* lpart;
+    double* scal;
+    double* pac;
+    int* err;
+    const double* spart;
+};
+LossBufs loss_bufs(ptyr_ctx* c) {
+    return LossBufs{at<double>(c, c->L.lpart), at<double>(c, c->L.scal), at<double>(c, c->L.pac),
+                    at<int>(c, c->L.err), at<double>(c, c->L.spart)};
+}
+
 // with_sparse: add the sparsity term of the batch (its partial sums come
 // from k_sparse_partial) to the loss
-void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev, hipStream_t st, bool with_sparse) {
-    const ptyr_geom& g = c->g;
+void loss_final_with(const ptyr_geom& g, const LossBufs& b, int nslots, int B, double* loss_dev, hipStream_t st,
+                     bool with_sparse) {
     const double n = (double)B * g.N * g.N;
-    const bool sp = with_sparse && g.sparse_w > 0.0;
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, at<double>(c, c->L.lpart), nslots * NPART, n,
-                       loss_terms(g), (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, at<double>(c, c->L.scal), loss_dev,
-                       at<int>(c, c->L.err), at<double>(c, c->L.spart), sp ? B * g.S * obj_modes(g) : 0,
+    const bool sp = with_sparse && g.sparse_w > 0.0 && b.spart;
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, b.lpart, nslots * NPART, n, loss_terms(g),
+                       (g.flags & PTYR_CHECK_FINITE) ? 1 : 0, b.scal, loss_dev, b.err, b.spart,
+                       sp ? B * g.S * obj_modes(g) : 0,
                        sp ? g.sparse_w / ((double)B * g.S * obj_modes(g) * g.N * g.N) : 0.0);
+}
+void loss_final(ptyr_ctx* c, int nslots, int B, double* loss_dev, hipStream_t st, bool with_sparse) {
+    loss_final_with(c->g, loss_bufs(c), nslots, B, loss_dev, st, with_sparse);
 }
 
 // PACBED term of a batch (after loss_final): adds it to the loss and its
 // gradient to `out` (fold: the adjoint's unscaled weights, which then carry
 // the data term's batch factor too; else ptyr_loss's dL/dI).
-void pacbed(ptyr_ctx* c, const float* I, const float* Ie, const int* midx, int n_meas, int row0, int B,
-            double* loss_dev, float* out, bool fold, hipStream_t st) {
-    const ptyr_geom& g = c->g;
+void pacbed_with(const ptyr_geom& g, const LossBufs& b, const float* I, const float* Ie, const int* midx,
+                 int n_meas, int row0, int B, double* loss_dev, float* out, bool fold, hipStream_t st) {
     const int NN = g.N * g.N;
-    double* pac = at<double>(c, c->L.pac);
+    double* pac = b.pac;
     double* part = pac + 2 * NN;
     const double p = loss_terms(g).p[0];           // the first data term's power (its normaliser is scal[2])
     hipLaunchKernelGGL(k_pacbed_partial, dim3(PAC_BLOCKS), dim3(256), 0, st, I, Ie, midx, n_meas, row0, B, NN,
                        p, pac, part);
-    hipLaunchKernelGGL(k_pacbed_final, dim3(1), dim3(64), 0, st, part, PAC_BLOCKS, NN, B, p, g.pacbed_w,
-                       at<double>(c, c->L.scal), loss_dev, fold ? 1 : 0);
+    hipLaunchKernelGGL(k_pacbed_final, dim3(1), dim3(64), 0, st, part, PAC_BLOCKS, NN, B, p, g.pacbed_w, b.scal,
+                       loss_dev, fold ? 1 : 0);
     if (out)
-        hipLaunchKernelGGL(k_pacbed_grad, dim3(grid_for((size_t)B * NN)), dim3(256), 0, st, out, B, g.N, p,
-                           pac, at<double>(c, c->L.scal), fold ? 1 : 0, fold ? 2.f : 1.f, fold ? 1 : 0);
+        hipLaunchKernelGGL(k_pacbed_grad, dim3(grid_for((size_t)B * NN)), dim3(256), 0, st, out, B, g.N, p, pac,
+                           b.scal, fold ? 1 : 0, fold ? 2.f : 1.f, fold ? 1 : 0);
+}
+void pacbed(ptyr_ctx* c, const float* I, const float* Ie, const int* midx, int n_meas, int row0, int B,
+            double* loss_dev, float* out, bool fold, hipStream_t st) {
+    pacbed_with(c->g, loss_bufs(c), I, Ie, midx, n_meas, row0, B, loss_dev, out, fold, st);
+}
+
+// ptyr_loss on explicit buffers: partial sums, final pass, dL/dI, PACBED term
+ptyr_status loss_pass(const ptyr_geom& g, const LossBufs& b, const float* Im, const float* Ie, const int* midx,
+                      int n_meas, int B, double* loss_dev, float* dLdI, hipStream_t st) {
+    const int NN = g.N * g.N;
+    const size_t n = (size_t)B * NN;
+    const int nm = midx ? n_meas : B;
+    hipLaunchKernelGGL(k_loss_partial, dim3(NPART), dim3(256), 0, st, Im, Ie, midx, nm, B, NN, loss_terms(g),
+                       b.lpart, b.err);
+    loss_final_with(g, b, 1, B, loss_dev, st, false);
+    if (dLdI)
+        hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, st, Im, Ie, midx, nm, B, g.N,
+                           loss_terms(g), b.scal, dLdI);
+    if (g.pacbed_w > 0.0) pacbed_with(g, b, Im, Ie, midx, nm, 0, B, loss_dev, dLdI, false, st);
+    return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
 }
 
 ptyr_status run_loss(ptyr_ctx* c, const float* Im, const float* Ie, const int* midx, int n_meas, int B,
                      double* loss_dev, float* dLdI) {
-    const ptyr_geom& g = c->g;
-    const int NN = g.N * g.N;
-    const size_t n = (size_t)B * NN;
-    const int nm = midx ? n_meas : B;
-    hipLaunchKernelGGL(k_loss_partial, dim3(NPART), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, NN, loss_terms(g),
-                       at<double>(c, c->L.lpart), at<int>(c, c->L.err));
-    loss_final(c, 1, B, loss_dev, c->stream, false);
-    if (dLdI)
-        hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(n)), dim3(256), 0, c->stream, Im, Ie, midx, nm, B, g.N,
-                           loss_terms(g), at<double>(c, c->L.scal), dLdI);
-    if (g.pacbed_w > 0.0) pacbed(c, Im, Ie, midx, nm, 0, B, loss_dev, dLdI, false, c->stream);
-    return hipGetLastError() == hipSuccess ? PTYR_OK : PTYR_E_DEVICE;
+    return loss_pass(c->g, loss_bufs(c), Im, Ie, midx, n_meas, B, loss_dev, dLdI, c->stream);
+}
+
+// ------------------------------------------------------------------ allocation-free loss
+// The scratch of ptyr_loss_noalloc: one set of loss buffers (LossBufs) for
+// any N <= 256, in a file-scope device array (each device holds its own copy
+// until the process ends).  Host code never uses the array's name as an
+// address: its device address is looked up once per device.
+constexpr size_t NOALLOC_PART = (size_t)NLP * NPART;                   // doubles
+constexpr size_t NOALLOC_SCAL = 8;
+constexpr size_t NOALLOC_PAC = 2 * 256 * 256 + PAC_BLOCKS;
+constexpr size_t NOALLOC_DOUBLES = NOALLOC_PART + NOALLOC_SCAL + NOALLOC_PAC;
+static_assert(NOALLOC_DOUBLES * sizeof(double) == PTYR_NOALLOC_SCRATCH_BYTES, "scratch size in ptyr.h");
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+static_assert(ERR_BOUNDS == PTYR_ERRBIT_BOUNDS && ERR_NONFINITE == PTYR_ERRBIT_NONFINITE &&
+                  ERR_ZERO_MEAN == PTYR_ERRBIT_ZERO_MEAN && ERR_INDEX == PTYR_ERRBIT_INDEX,
+              "error bits in ptyr.h");
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_dev[MAX_DEVICES] = {};
+
+// the current device's address of `scratch` (looked up on the first call on
+// each device, with that device current)
+ptyr_status scratch_address(double** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return PTYR_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PTYR_E_DEVICE;
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return PTYR_OK;
 }
 
 // A batch of more chains (one workgroup each, one workgroup per compute unit)
@@ -1459,6 +1523,25 @@ ptyr_status ptyr_loss(ptyr_ctx* c, const float* I_model, const float* I_meas, co
     if (!I_model || !I_meas || !loss_dev) return PTYR_E_ARG;
     if (meas_idx && n_meas < 1) return PTYR_E_ARG;
     return run_loss(c, I_model, I_meas, meas_idx, n_meas, B, loss_dev, dLdI);
+}
+
+ptyr_status ptyr_loss_noalloc(const ptyr_geom* g, const float* I_model, const float* I_meas, const int* meas_idx,
+                              int n_meas, int B, double* loss_dev, float* dLdI, int* err_dev, void* stream) {
+    ptyr_status st = ptyr_check_geom(g);
+    if (st != PTYR_OK) return st;
+    if (B < 1 || !I_model || !I_meas || !loss_dev || !err_dev) return PTYR_E_ARG;
+    if (meas_idx && n_meas < 1) return PTYR_E_ARG;
+    const size_t NN = (size_t)g->N * g->N;
+    if (NOALLOC_PART + NOALLOC_SCAL + 2 * NN + PAC_BLOCKS > NOALLOC_DOUBLES) return PTYR_E_NOMEM;
+    double* base = nullptr;
+    st = scratch_address(&base);
+    if (st != PTYR_OK) return st;
+    // every buffer is written before it is read (partial sums by all NPART
+    // blocks, scalars by the final pass, PACBED sums by its first pass), so
+    // what an earlier call left needs no clearing
+    const LossBufs b{base, base + NOALLOC_PART, base + NOALLOC_PART + NOALLOC_SCAL, err_dev, nullptr};
+    return loss_pass(*g, b, I_model, I_meas, meas_idx, n_meas, B, loss_dev, dLdI,
+                     static_cast<hipStream_t>(stream));
 }
 
 ptyr_status ptyr_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const float* probe, const float* pos,
