@@ -142,7 +142,8 @@ typedef struct ptyr_ctx ptyr_ctx;
 const char* ptyr_status_str(ptyr_status s);
 
 /* Pure host: validate a geometry (N in {64,128,256}, M,S,B_max >= 1,
- * H,W >= N, dx, lambda > 0, loss kind and p). */
+ * H,W >= N, dx, lambda > 0, loss kind and p, non-negative finite weights,
+ * B_max * M * n_obj <= 2^30, at most 2^40 object elements). */
 ptyr_status ptyr_check_geom(const ptyr_geom* g);
 
 /* Pure host: validate a batch size and, when pos_host is not NULL, that every
@@ -319,7 +320,8 @@ enum { PTYR_K_FORWARD = 0, PTYR_K_GRADIENT = 1, PTYR_K_RZ = 2 };
 ptyr_status ptyr_timing_enable(ptyr_ctx* ctx, int on);
 /* Synchronise the stream and write the summed kernel time in milliseconds and
  * the number of timed launches of kernel `which` since timing was last
- * enabled (ptyr_timing_enable clears the record). */
+ * enabled (ptyr_timing_enable clears the record).  PTYR_E_DEVICE if an event
+ * could not be recorded since then (those launches are left out). */
 ptyr_status ptyr_timing_read(ptyr_ctx* ctx, int which, double* total_ms, int* launches);
 
 #ifdef __cplusplus

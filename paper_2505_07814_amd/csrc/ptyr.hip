@@ -895,6 +895,9 @@ ptyr_status ptyr_check_geom(const ptyr_geom* g) {
     // grid and index limits of the kernels
     if (g->n_obj < 0 || g->n_obj > 64) return PTYR_E_ARG;
     if ((double)g->B_max * g->M * (g->n_obj > 0 ? g->n_obj : 1) > 2147483647.0 / 2) return PTYR_E_ARG;
+    // object elements (all modes and slices) at most 2^40: keeps every byte
+    // count of the workspace layout far from size_t overflow
+    if ((double)g->S * (g->n_obj > 0 ? g->n_obj : 1) * g->H * g->W > 1099511627776.0) return PTYR_E_ARG;
     if (g->n_scan < 0) return PTYR_E_ARG;
     if (!(g->sparse_w >= 0.0) || !isfinite(g->sparse_w)) return PTYR_E_ARG;
     if (!(g->pacbed_w >= 0.0) || !isfinite(g->pacbed_w)) return PTYR_E_ARG;
