@@ -240,7 +240,8 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     constexpr int L = N / 16;
     __shared__ float2 lds[fwd_lds_slots<N>()];
     __shared__ Tables<N> tab;
-    const int l = threadIdx.x / L, c = threadIdx.x % L;
+    int l, c;
+    line_of<N>(threadIdx.x, l, c);
     const int wg = a.chain0 + xcd_remap(blockIdx.x, gridDim.x);
     const int j = wg / a.M, m = wg % a.M;
     const PosInfo pi = a.pinfo[j];
@@ -325,7 +326,8 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     constexpr int L = N / 16;
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ Tables<N> tab;
-    const int l = threadIdx.x / L, c = threadIdx.x % L;
+    int l, c;
+    line_of<N>(threadIdx.x, l, c);
     const int wg = a.chain0 + xcd_remap(blockIdx.x, gridDim.x);
     const int j = wg / a.M, m = wg % a.M;
     const PosInfo pi = a.pinfo[j];
@@ -466,7 +468,8 @@ __device__ __forceinline__ void fft2_block(const float2* src, float2* dst) {
     constexpr int L = N / 16;
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ float4 tw[N];
-    const int l = threadIdx.x / L, c = threadIdx.x % L;
+    int l, c;
+    line_of<N>(threadIdx.x, l, c);
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
         double s, co;
         sincos(-2.0 * 3.14159265358979323846 * (double)((n / (N / 16)) * (n % (N / 16))) / N, &s, &co);

@@ -9,15 +9,22 @@
 //   MID : register r = beta*L + a holds  n = (c + L*beta) + 16*a
 //
 // A length-N DFT along the lines is split as N = 16 * L:
-//   nat2mid: 16-point DFT in registers, twiddle W_N^{c b}, LDS exchange,
+//   nat2mid: 16-point DFT in registers, twiddle W_N^{c b}, exchange,
 //            L-point DFT in registers            (NAT in -> MID out)
 //   mid2nat: the same factors in reverse order   (MID in -> NAT out)
+// The exchange between the two DFTs transposes, in every line, L x L blocks
+// of registers against the line's L lanes.  For N = 64 and 128 the L lanes of
+// a line sit 64 / L lanes apart in one wave (line_of), so the transpose's
+// butterfly stages pair lanes 16 and 32 (and, for L = 8, 8) apart and run as
+// cross-lane register swaps (v_permlane16_swap / v_permlane32_swap, and a
+// masked DPP row rotation): no LDS traffic and no wait.  Line geometries
+// without that placement (the N = 256 line passes) exchange through LDS.
 // Either direction can carry either sign, so a line FFT, a pointwise
 // multiply in frequency and a line IFFT keep the field in place.  A
-// transpose (rows <-> columns) is one more LDS exchange.  LDS slots are
-// padded linear maps (slot = base(thread) + constant(register)), so every
-// access is one base register plus an immediate offset; the paddings make the
-// line exchanges bank-conflict free for each 32-lane half-wave and leave the
+// transpose (rows <-> columns) goes through LDS.  LDS slots are padded
+// linear maps (slot = base(thread) + constant(register)), so every access is
+// one base register plus an immediate offset; the paddings make LDS line
+// exchanges bank-conflict free for each 32-lane half-wave and leave the
 // transpose reads at most 2-way conflicted.  Transforms are unnormalised;
 // callers fold the 1/N factors into their pointwise factors.
 #pragma once
@@ -180,8 +187,18 @@ template <int N> struct WaveGeo {
     static constexpr int XCH_SLOTS = (N - 1) * SL + (HALF ? 7 : 15) * SB + L;
     static constexpr int T_SLOTS = HALF ? (N * SYF + 1) / 2 : N * SY;
     static constexpr int LDS_SLOTS = XCH_SLOTS > T_SLOTS ? XCH_SLOTS : T_SLOTS;
-    static constexpr bool WAVE_LOCAL = true;      // thread = line * L + lane: a line's lanes share a wave
+    static constexpr bool WAVE_LOCAL = true;      // a line's lanes share a wave
+    static constexpr bool XLANE = true;           // line exchanges by cross-lane swaps (line_of placement)
 };
+
+// (line l, lane c within the line) of thread tid for WaveGeo<N>: the wave
+// holds 64 / L lines, and lane c of its k-th line is wave lane k + (64 / L) c
+template <int N> __device__ __forceinline__ void line_of(int tid, int& l, int& c) {
+    constexpr int L = N / 16, LPW = 64 / L;
+    const int w = tid >> 6, ln = tid & 63;
+    l = w * LPW + ln % LPW;
+    c = ln / LPW;
+}
 
 // geometry traits with defaults for line geometries that do not set them
 template <class GEO, class = void> struct HalfX {
@@ -189,6 +206,12 @@ template <class GEO, class = void> struct HalfX {
 };
 template <class GEO> struct HalfX<GEO, decltype(void(GEO::HALF))> {
     static constexpr bool value = GEO::HALF;
+};
+template <class GEO, class = void> struct XLaneX {
+    static constexpr bool value = false;
+};
+template <class GEO> struct XLaneX<GEO, decltype(void(GEO::XLANE))> {
+    static constexpr bool value = GEO::XLANE;
 };
 
 // position along the line of register r
@@ -290,6 +313,54 @@ template <class GEO> __device__ __forceinline__ void exchange_sync() {
     else __syncthreads();
 }
 
+// ------------------------------------------------------------ cross-lane exchange
+// One butterfly stage of the block transpose: for the register pair
+// (x = v[a], y = v[a + 2^j]) the lanes whose lane-in-line index c has bit j
+// clear ("lower") hand y to, and take x from, the lanes with bit j set that
+// sit D = (64 / L) 2^j wave lanes higher: lower.y <-> upper.x.
+template <int D> __device__ __forceinline__ void xstage(float& x, float& y) {
+    if constexpr (D == 32) {
+        // swaps lanes 32-63 of the first operand with lanes 0-31 of the second
+        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+        x = __uint_as_float(r[0]);
+        y = __uint_as_float(r[1]);
+    } else if constexpr (D == 16) {
+        // swaps the odd 16-lane rows of the first operand with the even rows of the second
+        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+        x = __uint_as_float(r[0]);
+        y = __uint_as_float(r[1]);
+    } else {
+        static_assert(D == 8, "lane distance 8, 16 or 32");
+        // rotation by 8 within each 16-lane row (row_ror:8, control 0x128);
+        // bank mask 0x3 writes lanes 0-7 of each row (lower), 0xC lanes 8-15
+        const int xi = __float_as_int(x), yi = __float_as_int(y);
+        const int yn = __builtin_amdgcn_update_dpp(yi, xi, 0x128, 0xF, 0x3, false);
+        const int xn = __builtin_amdgcn_update_dpp(xi, yi, 0x128, 0xF, 0xC, false);
+        x = __int_as_float(xn);
+        y = __int_as_float(yn);
+    }
+}
+
+// Transpose, in every line, each L x L block of registers against the line's
+// L lanes (register B0 + a of lane c <-> register B0 + c of lane a): one
+// stage per bit of the lane index, lanes placed as in line_of.
+template <int L> __device__ __forceinline__ void xlane_transpose(float2 (&v)[16]) {
+    constexpr int LPW = 64 / L;
+#pragma unroll
+    for (int j = 0; (1 << j) < L; ++j) {
+        const int e = 1 << j;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            if (a & e) continue;
+            switch (LPW * e) {
+                case 8: xstage<8>(v[a].x, v[a + e].x); xstage<8>(v[a].y, v[a + e].y); break;
+                case 16: xstage<16>(v[a].x, v[a + e].x); xstage<16>(v[a].y, v[a + e].y); break;
+                default: xstage<32>(v[a].x, v[a + e].x); xstage<32>(v[a].y, v[a + e].y); break;
+            }
+        }
+    }
+}
+
 // NAT -> MID, DFT of sign SG along every line.
 // With HALF the exchange runs in two rounds through the slots of b < 8: the
 // first moves registers 0..7 (read back by the blocks be < G/2, whose
@@ -300,6 +371,12 @@ __device__ __forceinline__ void nat2mid(float2 (&v)[16], float2* lds, const floa
     constexpr int R = HalfX<GEO>::value ? 2 : 1;      // rounds
     dft16<SG>(v);
     twiddle_pass<L, SG>(v, tw + c);
+    if constexpr (XLaneX<GEO>::value) {
+        xlane_transpose<L>(v);
+#pragma unroll
+        for (int be = 0; be < G; ++be) dftL<L, SG>(&v[be * L]);
+        return;
+    }
 #pragma unroll
     for (int h = 0; h < R; ++h) {
         constexpr int NB = 16 / R, NBE = G / R;
@@ -323,6 +400,12 @@ __device__ __forceinline__ void mid2nat(float2 (&v)[16], float2* lds, const floa
     constexpr int R = HalfX<GEO>::value ? 2 : 1;      // rounds, as in nat2mid
 #pragma unroll
     for (int be = 0; be < G; ++be) dftL<L, SG>(&v[be * L]);
+    if constexpr (XLaneX<GEO>::value) {
+        xlane_transpose<L>(v);
+        twiddle_pass<L, SG>(v, tw + c);
+        dft16<SG>(v);
+        return;
+    }
 #pragma unroll
     for (int h = 0; h < R; ++h) {
         constexpr int NB = 16 / R, NBE = G / R;
