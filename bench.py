@@ -102,25 +102,57 @@ def read_traffic(kernel, workload):
         return None
 
 
-def cpu_baseline(w, B, min_seconds=10.0, max_batches=8):
-    """The FP64 oracle on consecutive batches of the same workload (forward,
-    loss, gradient of all six parameters and the Adam update, on the host),
-    until at least min_seconds of timed work."""
+def read_activity(kernel, workload):
+    """VALU / LDS busy fractions of a kernel from a committed rocprofv3 counter
+    summary taken on the current kernel sources ({} if none)."""
+    path = os.path.join(ROOT, "profiles", f"activity_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    from paper_2505_07814_amd.profile_summary import source_hash
+    if vals.get("source_hash") != source_hash():
+        return {}
+    out = {}
+    for k in ("valu_busy", "lds_busy", "lds_bank_conflict"):
+        try:
+            out[k] = float(vals[k])
+        except (KeyError, ValueError):
+            pass
+    return out
+
+
+def cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (None if unreadable)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_batch(w, nb, B, amp0, ph0):
+    """Measured patterns of batch nb (untimed), then the timed oracle work of
+    one step: forward, loss, gradient of all six parameters and Adam."""
     import numpy as np
     from oracle import multislice as ms
     from oracle.adam import adam_step
     from paper_2505_07814_amd import synth
 
     lam = synth.wavelength_A(w.kv)
-    amp0, ph0 = synth.plain_init(w.S, w.H, w.W, w.seed_base + 5)
     z = np.zeros
-    dt, nb = 0.0, 0
-    while nb < max_batches and (nb == 0 or dt < min_seconds) and (nb + 1) * B <= w.pos.shape[0]:
-        sl = slice(nb * B, (nb + 1) * B)
-        pos, tilt = w.pos[sl], w.tilt[sl]
-        # measured patterns for the sample come from the oracle itself (untimed)
-        I = ms.forward(w.amp, w.phase, w.probe, pos, tilt, w.dz, w.dx, lam)
-        meas = synth.poisson(I, w.seed_base + 4 + nb).astype(np.float64)
+    sl = slice(nb * B, (nb + 1) * B)
+    pos, tilt = w.pos[sl], w.tilt[sl]
+    # measured patterns for the sample come from the oracle itself (untimed)
+    I = ms.forward(w.amp, w.phase, w.probe, pos, tilt, w.dz, w.dx, lam)
+    meas = synth.poisson(I, w.seed_base + 4 + nb).astype(np.float64)
+
+    def work():
         t0 = time.perf_counter()
         g = ms.gradients(amp0, ph0, w.probe, pos, tilt, w.dz, w.dx, lam, meas)
         adam_step(amp0, g.amp, z(amp0.shape), z(amp0.shape), 0, 1e-3)
@@ -128,14 +160,66 @@ def cpu_baseline(w, B, min_seconds=10.0, max_batches=8):
         adam_step(w.probe, g.probe, z(w.probe.shape, complex), z(w.probe.shape, complex), 0, 1e-3)
         adam_step(pos, g.pos, z(pos.shape), z(pos.shape), 0, 1e-3)
         adam_step(tilt, g.tilt, z(tilt.shape), z(tilt.shape), 0, 1e-3)
-        dt += time.perf_counter() - t0
+        return t0, time.perf_counter()
+    return work
+
+
+def _oracle_worker(workload, positions, nb, B, barrier, queue):
+    """One all-core worker (a fresh interpreter): its own batch of the
+    workload, started together with the others."""
+    import numpy as np  # noqa: F401
+    from paper_2505_07814_amd import synth
+    w = synth.workload(workload, scan=positions or None)
+    amp0, ph0 = synth.plain_init(w.S, w.H, w.W, w.seed_base + 5)
+    work = _oracle_batch(w, nb, B, amp0, ph0)
+    barrier.wait()
+    queue.put(work())
+
+
+def cpu_baseline(w, B, workload, positions, min_seconds=10.0, max_batches=8, max_workers=16):
+    """The FP64 oracle on consecutive batches of the same workload (forward,
+    loss, gradient of all six parameters and the Adam update, on the host):
+    on one thread until at least min_seconds of timed work, then one batch
+    per core on every core this process may run on (capped at max_workers),
+    started together, timed from the first start to the last finish."""
+    from paper_2505_07814_amd import synth
+
+    amp0, ph0 = synth.plain_init(w.S, w.H, w.W, w.seed_base + 5)
+    dt, nb = 0.0, 0
+    while nb < max_batches and (nb == 0 or dt < min_seconds) and (nb + 1) * B <= w.pos.shape[0]:
+        t0, t1 = _oracle_batch(w, nb, B, amp0, ph0)()
+        dt += t1 - t0
         nb += 1
-    return {"value": nb * B / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nb} batches of {B} positions of the same workload (forward, loss, gradient of all six "
-                      f"parameters and Adam, FP64 NumPy, single thread), {dt:.1f} s timed"}
+    out = {"value": nb * B / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{nb} batches of {B} positions of the same workload (forward, loss, gradient of all six "
+                     f"parameters and Adam, FP64 NumPy with the oracle's own radix-2 FFT, single thread), "
+                     f"{dt:.1f} s timed"}
+    cores = len(os.sched_getaffinity(0))
+    n = min(cores, max_workers, w.pos.shape[0] // B)
+    if n > 1:
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")                  # fresh interpreters: nothing of the GPU runtime
+        barrier, queue = ctx.Barrier(n), ctx.Queue()
+        procs = [ctx.Process(target=_oracle_worker, args=(workload, positions, k, B, barrier, queue))
+                 for k in range(n)]
+        for p in procs:
+            p.start()
+        spans = [queue.get() for _ in range(n)]
+        for p in procs:
+            p.join()
+        wall = max(t1 for _, t1 in spans) - min(t0 for t0, _ in spans)
+        out["all_cores"] = {"value": n * B / wall, "unit": "patterns/s", "cores": n,
+                            "sample": f"{n} batches of {B} positions, one per process (NumPy single-threaded in "
+                                      f"each), {wall:.1f} s from the first start to the last finish; "
+                                      f"{cores} cores available to this process"}
+    return out
 
 
-def learned_init_bench(args):
+def learned_init_run(objects, epochs, iterations, dev):
+    """Train the conv net on `objects` simulated objects (64 neighbourhoods
+    each), then reconstruct the held-out object from the learned and from the
+    plain initial guess: (learned result, plain result, training result,
+    inference seconds, number of pairs, data seconds)."""
     import numpy as np
     import torch
 
@@ -143,14 +227,12 @@ def learned_init_bench(args):
     from paper_2505_07814_amd import synth
     from paper_2505_07814_amd.cnn import ConvInit
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    data = li.make_dataset(args.objects, dev)
+    data = li.make_dataset(objects, dev)
     data_s, n_pairs = data.seconds, data.nbr.shape[0]
-    log(f"data: {n_pairs} pairs from {args.objects} objects in {data_s:.1f} s")
+    log(f"data: {n_pairs} pairs from {objects} objects in {data_s:.1f} s")
     net = ConvInit(256, device=dev)
-    res = li.train(data, epochs=args.epochs, batch=256, lr=1e-3, net=net, log=log)
+    res = li.train(data, epochs=epochs, batch=256, lr=1e-3, net=net, log=log)
     del data
     case = li.eval_case(dev)
     plain = torch.from_numpy(synth.plain_init(1, synth.LI_H, synth.LI_H, 5)[1][0].astype(np.float32)).to(dev)
@@ -161,26 +243,52 @@ def learned_init_bench(args):
     init = li.learned_phase(net, res.params, case, plain)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
-    iters = args.iterations
-    r_plain = li.reconstruct(case, plain, iters)
-    r_learn = li.reconstruct(case, init, iters, setup_seconds=setup)
+    r_plain = li.reconstruct(case, plain, iterations)
+    r_learn = li.reconstruct(case, init, iterations, setup_seconds=setup)
+    return r_learn, r_plain, res, setup, n_pairs, data_s
+
+
+def learned_init_block(objects, epochs, iterations, dev, errors=False):
+    """Metric 2 as a JSON object: iterations and wall seconds to 0.02 rad RMS
+    phase error from either start, and the (uncounted) training time."""
+    r_learn, r_plain, res, setup, n_pairs, data_s = learned_init_run(objects, epochs, iterations, dev)
+    rnd = lambda x: None if x is None else round(x, 5)
+    blk = {
+        "target_rad": 0.02,
+        "learned_init": {"iterations": r_learn.iterations_to_target, "seconds": rnd(r_learn.seconds_to_target),
+                         "inference_seconds": round(setup, 5)},
+        "plain_init": {"iterations": r_plain.iterations_to_target, "seconds": rnd(r_plain.seconds_to_target)},
+        "training": {"seconds": round(res.seconds, 2), "data_seconds": round(data_s, 2), "pairs": int(n_pairs),
+                     "objects": objects, "epochs": epochs},
+        "note": "held-out single-slice object (seed 999), 64 x 64 patterns, 10 x 10 scan, Adam lr 1e-2 on "
+                "amplitude and phase, 20 positions per step; seconds include the net's inference and stitching "
+                "for the learned start; training and data simulation are reported, not counted",
+    }
+    if errors:
+        blk["learned_init"]["errors"] = [round(e, 5) for e in r_learn.errors]
+        blk["plain_init"]["errors"] = [round(e, 5) for e in r_plain.errors]
+        blk["training"]["epoch_losses"] = [float(f"{x:.4e}") for x in res.losses]
+    return blk
+
+
+def learned_init_bench(args):
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    blk = learned_init_block(args.objects, args.epochs, args.iterations, dev, errors=True)
     out = {
         "metric": "wall time to 0.02 rad RMS phase error (learned init + hand adjoint)",
-        "value": None if r_learn.seconds_to_target is None else round(r_learn.seconds_to_target, 5),
+        "value": blk["learned_init"]["seconds"],
         "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
         "dtype": "bf16 net / f32 reconstruction", "data": "synthetic",
         "config": {"workload": "single-slice 64x64 at 0.2 A/px, 300 kV, 20 mrad, 100 A defocus, 1e5 e/pattern; "
                                "objects 144x144 with 51 random Gaussian atoms (0.5 rad); 10x10 raster, step 8 px; "
                                "eval object seed 999; reconstruction: Adam lr 1e-2 on amplitude and phase, "
                                "20 positions per step, Gaussian amplitude loss",
-                   "train_pairs": int(n_pairs), "train_objects": args.objects,
+                   "train_pairs": blk["training"]["pairs"], "train_objects": args.objects,
                    "epochs": args.epochs},
-        "learned_init": {"iterations": r_learn.iterations_to_target, "seconds": r_learn.seconds_to_target,
-                         "inference_seconds": round(setup, 5), "errors": [round(e, 5) for e in r_learn.errors]},
-        "plain_init": {"iterations": r_plain.iterations_to_target, "seconds": r_plain.seconds_to_target,
-                       "errors": [round(e, 5) for e in r_plain.errors]},
-        "training": {"seconds": round(res.seconds, 2), "data_seconds": round(data_s, 2),
-                     "epoch_losses": [float(f"{x:.4e}") for x in res.losses]},
+        **{k: blk[k] for k in ("learned_init", "plain_init", "training")},
     }
     print(json.dumps(out), flush=True)
 
@@ -335,6 +443,8 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD, choices=["multislice_128", "large_256"],
                     help="multislice_128 is the headline configuration; large_256 measures the N=256 line passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned-init", action="store_true",
+                    help="leave the learned-init block (metric 2) out of the default line")
     ap.add_argument("--positions", type=int, default=0,
                     help="use only the first P scan positions (profiling runs; 0 = all)")
     ap.add_argument("--sweep", action="store_true", help="time the step over B, M and S around the N=128 point")
@@ -458,6 +568,7 @@ def main():
             "bound": "alu", "kernel": f"k_{dom}<{w.N}>", "achieved": round(achieved, 3),
             "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
             "traffic": read_traffic(dom, workload) if K == 1 else None,
+            **(read_activity(dom, workload) if K == 1 else {}),
             "launch_ms": round(per_launch[dom], 4),
             "launches_per_step": launches / args.steps,
             "flops_per_launch": flops_step * args.steps / launches,
@@ -502,8 +613,12 @@ def main():
                              "note": "ptyr_adjoint on the first batches of the timed ones: forward, loss, all six "
                                      "gradients, no Adam"},
     }
+    if not args.no_learned_init and workload == "multislice_128" and K == 1:
+        del st, eng, meas, batches, grads, params
+        torch.cuda.empty_cache()
+        out["learned_init"] = learned_init_block(args.objects, args.epochs, args.iterations, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, B)
+        out["cpu_baseline"] = cpu_baseline(w, B, workload, args.positions)
     if args.copy_calibration:
         copy_calibration(out, dev)
     print(json.dumps(out), flush=True)

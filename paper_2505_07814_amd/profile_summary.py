@@ -7,6 +7,8 @@ so that bench.py can tell whether they still describe the current kernels.
 
 usage: python -m paper_2505_07814_amd.profile_summary FETCH_CSV WRITE_CSV
            KERNELS OUT_TXT [--launches K] [--grids G1,G2,...] COMMAND...
+       python -m paper_2505_07814_amd.profile_summary --activity CSV[,CSV...]
+           KERNELS OUT_TXT [--grids G1,G2,...] COMMAND...
 
 KERNELS is a comma-separated list of kernel-name substrings.  Without
 --launches the figure is the average per matching dispatch; with it, the
@@ -15,6 +17,16 @@ several dispatches, such as the N=256 line passes of one gradient).  With
 --grids only dispatches of those grid sizes (work-items) count, which keeps
 the launches of a timed step apart from other launches of the same kernel in
 the profiled run (such as data generation).
+
+--activity summarises SQ / GRBM counter runs (one CSV per pass) of the same
+command: each counter's average per matching dispatch, and the busy
+fractions rocprofv3 derives per dispatch (over the dispatch's GPU-active
+cycles, the largest GRBM_GUI_ACTIVE of the XCDs, and all compute units):
+  valu_busy = VALUBusy / 100  (sum of SQ_ACTIVE_INST_VALU / CUs / cycles)
+  lds_busy  = LdsUtil / 100   (sum of SQ_LDS_IDX_ACTIVE / CUs / cycles)
+  lds_bank_conflict = LDSBankConflict / 100 (sum of SQ_LDS_BANK_CONFLICT / CUs / cycles)
+and, where the raw counters were taken, the shares of the resident waves'
+cycles spent issuing VALU or waiting for an LDS issue.
 """
 import csv
 import hashlib
@@ -51,7 +63,47 @@ def per_kernel(path, counter, grids=None):
     return out
 
 
+def activity(argv):
+    csvs, knames, out_txt = argv[:3]
+    rest = argv[3:]
+    grids = None
+    if rest and rest[0] == "--grids":
+        grids = {g for g in rest[1].split(",") if g}
+        rest = rest[2:]
+    keys = [k for k in knames.split(",") if k]
+    vals = {}
+    for path in csvs.split(","):
+        for r in csv.DictReader(open(path)):
+            if not any(q in r["Kernel_Name"] for q in keys):
+                continue
+            if grids and r.get("Grid_Size") not in grids:
+                continue
+            vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg = {k: sum(v) / len(v) for k, v in sorted(vals.items())}
+    lines = [f"# VALU / LDS activity of {knames} (rocprofv3 --pmc, one pass per CSV)",
+             f"# command: {' '.join(rest)}"]
+    if grids:
+        lines.append(f"# dispatches of grid sizes {','.join(sorted(grids, key=int))} only")
+    lines.append("# dispatches per counter: " + ", ".join(f"{k} {len(v)}" for k, v in sorted(vals.items())))
+    lines += [f"{k} = {v:.6g}" for k, v in avg.items()]
+    for derived, key in (("VALUBusy", "valu_busy"), ("LdsUtil", "lds_busy"), ("LDSBankConflict", "lds_bank_conflict")):
+        if derived in avg:
+            lines.append(f"{key} = {avg[derived] / 100.0:.4f}")
+    if "SQ_ACTIVE_INST_VALU" in avg and "SQ_WAVE_CYCLES" in avg:
+        lines.append(f"valu_wave_share = {avg['SQ_ACTIVE_INST_VALU'] / avg['SQ_WAVE_CYCLES']:.4f}")
+    if "SQ_WAIT_INST_LDS" in avg and "SQ_WAVE_CYCLES" in avg:
+        lines.append(f"lds_wait_wave_share = {avg['SQ_WAIT_INST_LDS'] / avg['SQ_WAVE_CYCLES']:.4f}")
+    if "SQ_WAIT_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
+        lines.append(f"wait_any_wave_share = {avg['SQ_WAIT_ANY'] / avg['SQ_WAVE_CYCLES']:.4f}")
+    lines.append(f"source_hash = {source_hash()}")
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv):
+    if argv and argv[0] == "--activity":
+        return activity(argv[1:])
     fetch_csv, write_csv, knames, out_txt = argv[:4]
     rest = argv[4:]
     launches = None

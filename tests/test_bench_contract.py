@@ -34,7 +34,8 @@ def test_more_than_one_gpu_exits_with_a_message(capsys):
 
 @pytest.mark.gpu
 def test_short_run_prints_the_contract_line(capsys):
-    code, out, err = run_main(["--positions", "512", "--steps", "4", "--warmup", "1", "--no-cpu-baseline"], capsys)
+    code, out, err = run_main(["--positions", "512", "--steps", "4", "--warmup", "1", "--no-cpu-baseline",
+                               "--no-learned-init"], capsys)
     assert code in (0, None), err[-2000:]
     lines = [l for l in out.splitlines() if l.strip()]
     assert len(lines) == 1
@@ -50,3 +51,17 @@ def test_short_run_prints_the_contract_line(capsys):
         assert k in rf, k
     assert rf["bound"] in ("hbm", "mfma", "alu") and 0 < rf["frac"] < 1
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-3
+
+
+@pytest.mark.gpu
+def test_default_line_carries_learned_init(capsys):
+    """The default line's learned-init block (metric 2), with a tiny training
+    set: iterations and seconds to the target from both starts."""
+    code, out, err = run_main(["--positions", "512", "--steps", "2", "--warmup", "1", "--no-cpu-baseline",
+                               "--objects", "40", "--epochs", "2", "--iterations", "30"], capsys)
+    assert code in (0, None), err[-2000:]
+    d = json.loads([l for l in out.splitlines() if l.strip()][-1])
+    blk = d["learned_init"]
+    for side in ("learned_init", "plain_init"):
+        assert set(blk[side]) >= {"iterations", "seconds"}, blk[side]
+    assert blk["training"]["pairs"] == 40 * 64 and blk["training"]["seconds"] > 0
