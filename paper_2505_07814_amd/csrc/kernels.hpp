@@ -53,7 +53,7 @@ struct WaveArgs {
     const float* wgt;      // B x N x N, 2 dL/dI, zero frequency at (0, 0)
     float2* gO;            // B x M x S x N x N object-patch gradients
     float2* gPhat;         // B x M x N x N probe-spectrum gradients
-    float* part;           // B x M x 8 scalar partial sums
+    double* part;          // B x M x 8 scalar partial sums (N = 256: per line block)
 };
 
 // probe spectrum and object transmission (all slices) of chain mode e
@@ -199,9 +199,9 @@ __device__ __forceinline__ void slice_step(float2 (&v)[16], const float2* Os, in
     ifft2_to_col<N>(v, lds, t.tw, l, c);
 }
 
-// block-wide sum of NV floats, result valid in thread 0
-template <int NV>
-__device__ __forceinline__ void block_sum(float (&x)[NV], float* red) {
+// block-wide sum of NV values, result valid in thread 0
+template <int NV, typename T>
+__device__ __forceinline__ void block_sum(T (&x)[NV], T* red) {
 #pragma unroll
     for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -214,7 +214,7 @@ __device__ __forceinline__ void block_sum(float (&x)[NV], float* red) {
     __syncthreads();
     if (threadIdx.x == 0)
         for (int k = 0; k < NV; ++k) {
-            float s = 0.f;
+            T s = 0;
             for (int q = 0; q < nw; ++q) s += red[q * NV + k];
             x[k] = s;
         }
@@ -331,11 +331,11 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     const int wg = a.chain0 + xcd_remap(blockIdx.x, gridDim.x);
     const int j = wg / a.M, m = wg % a.M;
     const PosInfo pi = a.pinfo[j];
-    float* part = a.part + (size_t)(j * a.M + m) * 8;
+    double* part = a.part + (size_t)(j * a.M + m) * 8;
     float2* gP = a.gPhat + (size_t)(j * a.M + m) * N * N;
     if (pi.ty < 0) {
         for (int i = threadIdx.x; i < N * N; i += blockDim.x) gP[i] = make_float2(0.f, 0.f);
-        if (threadIdx.x < 8) part[threadIdx.x] = 0.f;
+        if (threadIdx.x < 8) part[threadIdx.x] = 0.0;
         return;   // the object-gradient scatter skips such rows
     }
     const float* th = a.global_tilt ? a.tilt : a.tilt + 2 * pi.row;
@@ -407,9 +407,13 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
         return Y_s;
     };
 
-    float acc_k2 = 0.f, acc_kx = 0.f, acc_ky = 0.f;
-    const float dk = (float)(1.0 / (N * a.dx));
-    const float ky = sfreq<N>(l) * dk;
+    // dz / tilt / position partial sums in double: Im(G^ conj(Y)) is formed
+    // from the exact double products of the float values, and the sums over
+    // registers, slices and threads carry no float rounding (the dz gradient
+    // is a sum of terms of both signs)
+    double acc_k2 = 0.0, acc_kx = 0.0, acc_ky = 0.0;
+    const double dk = 1.0 / (N * a.dx);
+    const double ky = sfreq<N>(l) * dk, ky2 = ky * ky;
     for (int s = a.S - 1; s >= 1; --s) {
         const float2* Y_s = slice_back(s);
         // dL/d(dz, th) += sum_k dPhi/dt(k) Im(G^ conj(Y)), Y = F phi_s (raw G^ x Y')
@@ -424,22 +428,22 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const float2 y = yv[r];
-            const float e = g[r].y * y.x - g[r].x * y.y;
-            const float kx = sfreq<N>(line_pos<N, MID>(cc, r)) * dk;
-            acc_k2 = fmaf(e, kx * kx + ky * ky, acc_k2);
-            acc_kx = fmaf(e, kx, acc_kx);
-            acc_ky = fmaf(e, ky, acc_ky);
+            const double e = fma((double)g[r].y, (double)y.x, -((double)g[r].x * (double)y.y));
+            const double kx = sfreq<N>(line_pos<N, MID>(cc, r)) * dk;
+            acc_k2 = fma(e, fma(kx, kx, ky2), acc_k2);
+            acc_kx = fma(e, kx, acc_kx);
+            acc_ky = fma(e, ky, acc_ky);
         }
         apply_h<N, true>(g, tab, l, c);                                       // conj(H) G^ / N^2
         ifft2_to_col<N>(g, lds, tab.tw, l, c);                                // G_chi_{s-1}
     }
     slice_back(0);
     // probe spectrum and position: phi_0 = F^-1[Phat R]
-    float acc_py = 0.f, acc_px = 0.f;
+    double acc_py = 0.0, acc_px = 0.0;
     {
         const float2* Pm = chain_probe(a, m, N * N);
         const float2 ry = tab.ry[l];
-        const float qy = (float)sfreq<N>(l) * inv_n;
+        const double qy = (double)sfreq<N>(l) / N;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int x = line_pos<N, MID>(c, r);
@@ -447,17 +451,17 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
             const float2 R = cmul(ry, tab.rx[x]);
             g[r] = cmulc(G0, R);                                               // conj(R) G^_0
             const float2 z = cmulc(cmul((Pm + YR::dx(r))[oM], R), G0);         // Phat R conj(G^_0)
-            acc_py = fmaf(z.y, qy, acc_py);
-            acc_px = fmaf(z.y, (float)sfreq<N>(x) * inv_n, acc_px);
+            acc_py = fma((double)z.y, qy, acc_py);
+            acc_px = fma((double)z.y, (double)sfreq<N>(x) / N, acc_px);
             if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
         wstore<N, ROW, MID>(g, gP, N, l, c);
     }
-    float sums[5] = {acc_k2, acc_kx, acc_ky, acc_py, acc_px};
-    block_sum<5>(sums, reinterpret_cast<float*>(lds));   // the exchange buffer is free again
+    double sums[5] = {acc_k2, acc_kx, acc_ky, acc_py, acc_px};
+    block_sum<5>(sums, reinterpret_cast<double*>(lds));  // the transpose buffer is free again
     if (threadIdx.x == 0) {
         for (int k = 0; k < 5; ++k) part[k] = sums[k];
-        part[5] = part[6] = part[7] = 0.f;
+        part[5] = part[6] = part[7] = 0.0;
     }
 }
 

@@ -202,13 +202,13 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
     const int j = ch / a.M, m = ch % a.M;
     const PosInfo pi = a.pinfo[j];
     const int l = threadIdx.x % 16, c = threadIdx.x / 16, x = blk * LINES256 + l;
-    float* part = a.part + ((size_t)ch * NBLK256 + blk) * 8;
+    double* part = a.part + ((size_t)ch * NBLK256 + blk) * 8;
     if (pi.ty < 0) {
         if (P.s == 0) {
             float2* gP = a.gPhat + (size_t)ch * N256 * N256;
 #pragma unroll
             for (int r = 0; r < 16; ++r) gP[(c + 16 * r) * N256 + x] = make_float2(0.f, 0.f);
-            if (threadIdx.x < 8) part[threadIdx.x] = 0.f;
+            if (threadIdx.x < 8) part[threadIdx.x] = 0.0;
         }
         return;
     }
@@ -224,27 +224,28 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
         for (int r = 0; r < 16; ++r) v[r] = cscale(v[r], wj[(c + 16 * r) * N256 + x] * inv_n2);
         mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
         cols_store(v, w, x, c);
-        if (threadIdx.x < 8) part[threadIdx.x] = 0.f;
+        if (threadIdx.x < 8) part[threadIdx.x] = 0.0;
         return;
     }
     cols_load(v, w, x, c);
     float2 yv_[16];                      // Y'_s, read now so that its latency overlaps the DFT
     if (P.s > 0) cols_load(yv_, sl.spec(P.s), x, c);
     nat2mid<ColGeo256, -1>(v, lds, tab.tw, l, c);                       // G^ (raw), (k_y, k_x)
-    const float dk = (float)(1.0 / (N256 * a.dx));
-    const float kx = sfreq<N256>(x) * dk;
-    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    // partial sums in double (see k_gradient)
+    const double dk = 1.0 / (N256 * a.dx);
+    const double kx = sfreq<N256>(x) * dk, kx2 = kx * kx;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (P.s > 0) {
         const float4 hx = tab.hl[l];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int ky_i = c + 16 * r;
             const float2 yv = yv_[r];
-            const float e = v[r].y * yv.x - v[r].x * yv.y;               // Im(G^ conj(Y))
-            const float ky = sfreq<N256>(ky_i) * dk;
-            acc[0] = fmaf(e, kx * kx + ky * ky, acc[0]);
-            acc[1] = fmaf(e, kx, acc[1]);
-            acc[2] = fmaf(e, ky, acc[2]);
+            const double e = fma((double)v[r].y, (double)yv.x, -((double)v[r].x * (double)yv.y));   // Im(G^ conj(Y))
+            const double ky = sfreq<N256>(ky_i) * dk;
+            acc[0] = fma(e, fma(ky, ky, kx2), acc[0]);
+            acc[1] = fma(e, kx, acc[1]);
+            acc[2] = fma(e, ky, acc[2]);
             v[r] = cscale(tmul<true>(tmul<true>(v[r], tab.h[ky_i]), hx), inv_n2);
         }
         mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
         const float2* Pm = chain_probe(a, m, N256 * N256);
         float2* gP = a.gPhat + (size_t)ch * N256 * N256;
         const float2 rx = tab.rl[l];
-        const float qx = (float)sfreq<N256>(x) * inv_n;
+        const double qx = (double)sfreq<N256>(x) / N256;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int ky_i = c + 16 * r;
@@ -261,11 +262,11 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
             const float2 R = cmul(tab.r[ky_i], rx);
             gP[ky_i * N256 + x] = cmulc(G0, R);                          // conj(R) G^_0
             const float2 z = cmulc(cmul(Pm[ky_i * N256 + x], R), G0);    // Phat R conj(G^_0)
-            acc[3] = fmaf(z.y, (float)sfreq<N256>(ky_i) * inv_n, acc[3]);
-            acc[4] = fmaf(z.y, qx, acc[4]);
+            acc[3] = fma((double)z.y, (double)sfreq<N256>(ky_i) / N256, acc[3]);
+            acc[4] = fma((double)z.y, qx, acc[4]);
         }
     }
-    block_sum<5>(acc, reinterpret_cast<float*>(lds));
+    block_sum<5>(acc, reinterpret_cast<double*>(lds));
     if (threadIdx.x == 0)
         for (int k = 0; k < 5; ++k) part[k] += acc[k];
 }

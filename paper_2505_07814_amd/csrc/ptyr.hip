@@ -628,7 +628,7 @@ __global__ void k_sum_rows(const float2* src, float2* dst, int B, int M, int NN,
 // One thread per batch row (rows of a batch are distinct, so the row
 // updates do not collide); dz and a global tilt are summed over rows in
 // fixed order by a block tree.
-__global__ __launch_bounds__(256) void k_param_grads(const float* part, int nblk, const PosInfo* pinfo, int B,
+__global__ __launch_bounds__(256) void k_param_grads(const double* part, int nblk, const PosInfo* pinfo, int B,
                                                      int M, const float* tilt, int global_tilt, const float* dzp,
                                                      double lam, const double* scale, float* g_pos, float* g_tilt,
                                                      float* g_dz) {
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(256) void k_param_grads(const float* part, int nblk
         double k2 = 0, kx = 0, ky = 0, py = 0, px = 0;
         for (int m = 0; m < M; ++m)
             for (int b = 0; b < nblk; ++b) {
-                const float* q = part + ((size_t)(j * M + m) * nblk + b) * 8;
+                const double* q = part + ((size_t)(j * M + m) * nblk + b) * 8;
                 k2 += q[0]; kx += q[1]; ky += q[2]; py += q[3]; px += q[4];
             }
         const float* th = global_tilt ? tilt : tilt + 2 * row;
@@ -791,7 +791,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.gO = take(B * Mc * S * NN * sizeof(float2));
     L.gPhat = take(B * Mc * NN * sizeof(float2));
     L.gPsum = take(M * NN * sizeof(float2));
-    L.part = take(B * Mc * (g->N == 256 ? NBLK256 : 1) * 8 * sizeof(float));
+    L.part = take(B * Mc * (g->N == 256 ? NBLK256 : 1) * 8 * sizeof(double));
     L.gamp = take(OS * HW * sizeof(float));
     L.gphase = take(OS * HW * sizeof(float));
     L.gprobe = take(M * NN * sizeof(float2));
@@ -1070,7 +1070,7 @@ WaveArgs wave_args(ptyr_ctx* c, const float* tilt, const float* dz, int B) {
     a.wgt = at<float>(c, c->L.wbuf);
     a.gO = at<float2>(c, c->L.gO);
     a.gPhat = at<float2>(c, c->L.gPhat);
-    a.part = at<float>(c, c->L.part);
+    a.part = at<double>(c, c->L.part);
     return a;
 }
 
@@ -1403,7 +1403,7 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
             }
         }
         if (g_pos || g_tilt || g_dz)
-            hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(256), 0, st, at<float>(c, c->L.part),
+            hipLaunchKernelGGL(k_param_grads, dim3(1), dim3(256), 0, st, at<double>(c, c->L.part),
                                g.N == 256 ? NBLK256 : 1, at<PosInfo>(c, c->L.pinfo), B, M, tilt, a.global_tilt, dz,
                                g.lambda, scale, g_pos, g_tilt, g_dz);
     };
