@@ -84,14 +84,16 @@ __global__ __launch_bounds__(256) void k_rz_filter_reg(float* v0, float* v1, int
     float x[RZ_REG_S];
 #pragma unroll
     for (int s = 0; s < RZ_REG_S; ++s) x[s] = s < S ? v[(size_t)s * HW + px] : 0.f;
+    // a guarded body rather than a break, so that the loop unrolls fully
 #pragma unroll
     for (int s = 0; s < RZ_REG_S; ++s) {
-        if (s >= S) break;
-        float acc = 0.f;
+        if (s < S) {
+            float acc = 0.f;
 #pragma unroll
-        for (int s2 = 0; s2 < RZ_REG_S; ++s2)
-            if (s2 < S) acc = fmaf(Bm[s * S + s2], x[s2], acc);
-        v[(size_t)s * HW + px] = positive ? fmaxf(acc, 0.f) : acc;
+            for (int s2 = 0; s2 < RZ_REG_S; ++s2)
+                if (s2 < S) acc = fmaf(Bm[s * S + s2], x[s2], acc);
+            v[(size_t)s * HW + px] = positive ? fmaxf(acc, 0.f) : acc;
+        }
     }
 }
 
@@ -109,19 +111,21 @@ __global__ __launch_bounds__(256) void k_rz_filter_reg4(float* v0, float* v1, in
         x[s] = s < S ? *reinterpret_cast<const float4*>(v + (size_t)s * HW + px) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int s = 0; s < RZ_REG_S; ++s) {
-        if (s >= S) break;
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (s < S) {
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int s2 = 0; s2 < RZ_REG_S; ++s2)
-            if (s2 < S) {
-                const float b = Bm[s * S + s2];
-                acc.x = fmaf(b, x[s2].x, acc.x);
-                acc.y = fmaf(b, x[s2].y, acc.y);
-                acc.z = fmaf(b, x[s2].z, acc.z);
-                acc.w = fmaf(b, x[s2].w, acc.w);
-            }
-        if (positive) acc = make_float4(fmaxf(acc.x, 0.f), fmaxf(acc.y, 0.f), fmaxf(acc.z, 0.f), fmaxf(acc.w, 0.f));
-        *reinterpret_cast<float4*>(v + (size_t)s * HW + px) = acc;
+            for (int s2 = 0; s2 < RZ_REG_S; ++s2)
+                if (s2 < S) {
+                    const float b = Bm[s * S + s2];
+                    acc.x = fmaf(b, x[s2].x, acc.x);
+                    acc.y = fmaf(b, x[s2].y, acc.y);
+                    acc.z = fmaf(b, x[s2].z, acc.z);
+                    acc.w = fmaf(b, x[s2].w, acc.w);
+                }
+            if (positive)
+                acc = make_float4(fmaxf(acc.x, 0.f), fmaxf(acc.y, 0.f), fmaxf(acc.z, 0.f), fmaxf(acc.w, 0.f));
+            *reinterpret_cast<float4*>(v + (size_t)s * HW + px) = acc;
+        }
     }
 }
 
