@@ -9,6 +9,8 @@ usage: python -m paper_2505_07814_amd.profile_summary FETCH_CSV WRITE_CSV
            KERNELS OUT_TXT [--launches K] [--grids G1,G2,...] COMMAND...
        python -m paper_2505_07814_amd.profile_summary --activity CSV[,CSV...]
            KERNELS OUT_TXT [--grids G1,G2,...] COMMAND...
+       python -m paper_2505_07814_amd.profile_summary --stats STATS_CSV TITLE
+           OUT_TXT COMMAND...
 
 KERNELS is a comma-separated list of kernel-name substrings.  Without
 --launches the figure is the average per matching dispatch; with it, the
@@ -27,6 +29,10 @@ cycles, the largest GRBM_GUI_ACTIVE of the XCDs, and all compute units):
   lds_bank_conflict = LDSBankConflict / 100 (sum of SQ_LDS_BANK_CONFLICT / CUs / cycles)
 and, where the raw counters were taken, the shares of the resident waves'
 cycles spent issuing VALU or waiting for an LDS issue.
+
+--stats turns rocprofv3's kernel statistics (--kernel-trace --stats) into a
+table of calls and average / min / max durations per kernel, with the
+command and the source hash.
 """
 import csv
 import hashlib
@@ -101,9 +107,36 @@ def activity(argv):
     print("\n".join(lines))
 
 
+def short_name(n):
+    n = n.replace("(anonymous namespace)::", "").replace("void ", "")
+    if n.startswith("__amd_rocclr"):
+        return n.split("(")[0]
+    if "at::native" in n or "at::" in n:
+        return "torch " + n.split("(")[0].split("::")[-1][:30]
+    return n.split("(")[0][:48]
+
+
+def stats(argv):
+    path, title, out_txt = argv[:3]
+    cmd = " ".join(argv[3:])
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics, {title}", f"# command: {cmd}",
+             f"{'kernel':48s} {'calls':>7s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    for r in rows:
+        lines.append(f"{short_name(r['Name']):48s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.1f} "
+                     f"{float(r['MinNs']) / 1e3:10.1f} {float(r['MaxNs']) / 1e3:10.1f} {float(r['Percentage']):6.2f}")
+    lines.append(f"source_hash = {source_hash()}")
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:12]))
+
+
 def main(argv):
     if argv and argv[0] == "--activity":
         return activity(argv[1:])
+    if argv and argv[0] == "--stats":
+        return stats(argv[1:])
     fetch_csv, write_csv, knames, out_txt = argv[:4]
     rest = argv[4:]
     launches = None
