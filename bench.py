@@ -402,9 +402,9 @@ def constraints_bench(args):
         out["cpu_baseline"] = {"value": round(1.0 / dt, 3), "unit": "calls/s", "cores": 1, "kind": "oracle",
                                "sample": "one call on the full object and probe (numpy, float64)"}
     out["roofline"]["traffic"] = read_traffic("rz", "constraints_128")
-    # k_z filter (beta 0.1, alpha 1 A^2) alone: amplitude + i phase through a
-    # mixed-radix 3-D transform and back, every pass reading and writing the
-    # complex field once (640 = 5 x 8 x 8 x 2, 12 = 3 x 4)
+    # k_z filter (beta 0.1, alpha 1 A^2) alone: amplitude + i phase through
+    # five line passes (forward x, forward y, z forward + weight + inverse,
+    # inverse y, inverse x), each reading and writing 8 bytes per voxel
     kz = dict(kz_beta=0.1, kz_alpha=1.0, kz_dz=float(w.dz))
     for _ in range(4):
         eng.constrain(amp, ph, **kz)
@@ -417,15 +417,8 @@ def constraints_bench(args):
     torch.cuda.synchronize()
     ms_kz = e0.elapsed_time(e1) / n_kz
 
-    def npass(n):
-        k = 0
-        for r in (5, 3, 8, 4, 2):
-            while n % r == 0:
-                n //= r
-                k += 1
-        return k
-    passes = 2 * (npass(w.W) + npass(w.H) + npass(w.S))
-    kz_bytes = 16 * (passes + 3) * w.S * w.H * w.W          # pack, passes, weight, unpack: 16 B per element each
+    passes = 5
+    kz_bytes = 16 * passes * w.S * w.H * w.W
     out["kz_filter"] = {"ms_per_call": round(ms_kz, 4), "passes": passes, "bytes_per_call": kz_bytes,
                         "achieved_GBs": round(kz_bytes / (ms_kz * 1e-3) / 1e9, 1),
                         "frac_of_hbm_peak": round(kz_bytes / (ms_kz * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}

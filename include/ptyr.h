@@ -274,7 +274,8 @@ ptyr_status ptyr_step(ptyr_ctx* ctx, ptyr_params* p, const int* idx, int B,
  *    3-D Fourier space by W_a(k) = (1 - (2/pi) atan(beta^2 k_z^2 /
  *    (k_x^2 + k_y^2 + 1e-3))) exp(-alpha (k_x^2 + k_y^2)), k in 1/angstrom
  *    from the geometry's dx and kz_dz (periodic in all three directions).
- *    S, H and W must have no prime factor other than 2, 3 and 5.
+ *    S, H and W must have no prime factor other than 2, 3 and 5 and be at
+ *    most 4096.
  *  rz_sigma > 0: the r_z filter (Sec. "Real-space depth regularization"): the
  *    amplitude and the phase are each convolved along the slice axis with a
  *    Gaussian of standard deviation rz_sigma slices, truncated at
@@ -303,8 +304,8 @@ typedef struct {
  * own), probe (M x N x N complex); the pointer of a constraint that is
  * off may be NULL.  PTYR_E_ARG for rz_sigma outside [0, 16], S > 256 with the
  * r_z filter, M > 24 with probe_orthogonal, negative k_z parameters, kz_dz <= 0
- * or a side with another prime factor with the k_z filter, or a needed NULL
- * pointer. */
+ * or a side with another prime factor or longer than 4096 with the k_z filter,
+ * or a needed NULL pointer. */
 ptyr_status ptyr_constrain(ptyr_ctx* ctx, float* amp, float* phase, float* probe,
                            const ptyr_constraints* cfg);
 

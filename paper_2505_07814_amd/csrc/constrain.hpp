@@ -139,102 +139,285 @@ __global__ void k_clip_negative(float* v, size_t n) {
 }
 
 // ------------------------------------------------------------ k_z filter
-// Mixed-radix (2, 3, 4, 5, 8) Stockham passes through device memory for the
-// 3-D transform of the S x H x W object (sides not powers of two, e.g.
-// 12 x 640 x 640).  Amplitude and phase travel together as one complex field
-// a + i phase: the weight W_a is real and even, so the filtered real and
-// imaginary parts are the two filtered fields.
+// The 3-D transform of one S x H x W object stack (sides with no prime factor
+// other than 2, 3 and 5, e.g. 12 x 640 x 640) runs as line passes, each one
+// round trip through device memory: a workgroup loads a tile of lines into
+// LDS, runs every radix stage of their DFTs there (Stockham stages in place,
+// each butterfly's values held in registers across a barrier) and writes the
+// tile back.  Amplitude and phase travel as one complex field a + i phase:
+// the weight W_a is real and even in k, so the filtered real and imaginary
+// parts are the two filtered fields.  Per call: forward x (reading amplitude
+// and phase), forward y, one z pass (forward, weight, inverse), inverse y,
+// inverse x (writing amplitude and phase): five passes, 16 bytes per voxel
+// each.
 
-// the element (line l, index i) of an axis sits at off(l) + i * stride with
-// off(l) = (l / L1) * P1 + (l % L1) * P0
-struct Axis {
-    int n;              // transform length
-    size_t lines;       // independent lines
-    size_t stride;      // element stride along the line
-    size_t L1, P1, P0;
-    int lines_fast;     // consecutive threads take consecutive lines (else consecutive j)
+constexpr int KZ_THREADS = 1024;
+constexpr int KZ_LDS = 8192;        // complex values of LDS per workgroup (64 KiB): tile + twiddles
+constexpr int KZ_EPT = KZ_LDS / KZ_THREADS;
+constexpr int KZ_MAX_SIDE = KZ_LDS / 2;
+constexpr int KZ_MAX_RAD = 16;
+constexpr int KZ_BATCH = 8;        // loads in flight per thread
+
+enum : int { KZ_IN_FIELDS = 1, KZ_OUT_FIELDS = 2, KZ_FILTER = 4 };
+
+// One axis: the lines form `groups` groups of lpg lines; line c of group q
+// starts at q * gs + c * gc and its element i sits i * gi further.  A tile is
+// nl consecutive lines of one group (the last tile of a group may hold fewer);
+// tile t covers group t / tpg.
+struct KzPass {
+    int n, lg, ls, lpg, tpg;    // line length, log2 lines per tile, LDS row pitch (rows), lines per group, tiles per group
+    int tiles;                  // tiles of the pass (the grid is rounded up to a multiple of 8)
+    size_t gs, gc, gi;
+    int nrad;
+    unsigned long long rads;    // radix k in bits 4k .. 4k + 3
+    const float2* tw;           // exp(-2 pi i k / n), k < n
+};
+struct KzWeight {
+    int S, H, W;
+    double beta, alpha, dx, dz;
 };
 
-__device__ __forceinline__ float2 cmul_f(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+__device__ __forceinline__ float2 kz_mul_i(float2 a, int sg) {       // a * (sg i)
+    return sg > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
-// One radix-R pass with Ns = product of the radices before it: thread (l, j),
-// j < n / R, reads the R elements j + r n / R, multiplies element r by
-// exp(sign 2 pi i r (j mod Ns) / (Ns R)), takes their R-point DFT and writes
-// output r to (j / Ns) Ns R + (j mod Ns) + r Ns.
-template <int R>
-__global__ __launch_bounds__(256) void k_fft_pass(const float2* __restrict__ src, float2* __restrict__ dst, Axis a,
-                                                  int Ns, float sign) {
-    const int m = a.n / R;
-    const size_t total = a.lines * m;
-    float2 wr[R];                              // exp(sign 2 pi i q / R)
+// R-point DFT X_b = sum_q x_q exp(SG 2 pi i q b / R) in place
+template <int R, int SG> __device__ __forceinline__ void kz_dft(float2* x) {
+    if constexpr (R == 2) {
+        const float2 a = x[0], b = x[1];
+        x[0] = make_float2(a.x + b.x, a.y + b.y);
+        x[1] = make_float2(a.x - b.x, a.y - b.y);
+    } else if constexpr (R == 4) {
+        const float2 y0 = make_float2(x[0].x + x[2].x, x[0].y + x[2].y);
+        const float2 y1 = make_float2(x[0].x - x[2].x, x[0].y - x[2].y);
+        const float2 y2 = make_float2(x[1].x + x[3].x, x[1].y + x[3].y);
+        const float2 y3 = kz_mul_i(make_float2(x[1].x - x[3].x, x[1].y - x[3].y), SG);
+        x[0] = make_float2(y0.x + y2.x, y0.y + y2.y);
+        x[2] = make_float2(y0.x - y2.x, y0.y - y2.y);
+        x[1] = make_float2(y1.x + y3.x, y1.y + y3.y);
+        x[3] = make_float2(y1.x - y3.x, y1.y - y3.y);
+    } else if constexpr (R == 8) {
+        float2 e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
+        kz_dft<4, SG>(e);
+        kz_dft<4, SG>(o);
+        // exp(SG 2 pi i k / 8) for k = 1, 2, 3
+        constexpr float r = 0.70710678118654752440f;
+        o[1] = make_float2(r * (o[1].x - SG * o[1].y), r * (o[1].y + SG * o[1].x));
+        o[2] = kz_mul_i(o[2], SG);
+        o[3] = make_float2(r * (-o[3].x - SG * o[3].y), r * (-o[3].y + SG * o[3].x));
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        float sn, cs;
-        sincospif(sign * 2.0f * (float)q / (float)R, &sn, &cs);
-        wr[q] = make_float2(cs, sn);
-    }
-    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-        size_t l;
-        int j;
-        if (a.lines_fast) { l = t % a.lines; j = (int)(t / a.lines); }
-        else { j = (int)(t % m); l = t / m; }
-        const size_t off = (l / a.L1) * a.P1 + (l % a.L1) * a.P0;
-        const int k = j % Ns;
-        float2 v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float2 x = src[off + (size_t)(j + r * m) * a.stride];
-            float sn, cs;
-            sincospif(sign * 2.0f * (float)(r * k) / (float)(Ns * R), &sn, &cs);
-            v[r] = cmul_f(x, make_float2(cs, sn));
+        for (int k = 0; k < 4; ++k) {
+            x[k] = make_float2(e[k].x + o[k].x, e[k].y + o[k].y);
+            x[k + 4] = make_float2(e[k].x - o[k].x, e[k].y - o[k].y);
         }
-        float2 o[R];
+    } else if constexpr (R == 3) {
+        constexpr float h = 0.86602540378443864676f;          // sin(2 pi / 3)
+        const float2 s = make_float2(x[1].x + x[2].x, x[1].y + x[2].y);
+        const float2 t = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
+        const float2 u = kz_mul_i(make_float2(h * (x[1].x - x[2].x), h * (x[1].y - x[2].y)), SG);
+        x[0] = make_float2(x[0].x + s.x, x[0].y + s.y);
+        x[1] = make_float2(t.x + u.x, t.y + u.y);
+        x[2] = make_float2(t.x - u.x, t.y - u.y);
+    } else {
+        static_assert(R == 5, "radix 2, 3, 4, 5 or 8");
+        constexpr float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;   // cos(2 pi / 5), cos(4 pi / 5)
+        constexpr float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;    // sin(2 pi / 5), sin(4 pi / 5)
+        const float2 t1 = make_float2(x[1].x + x[4].x, x[1].y + x[4].y);
+        const float2 t2 = make_float2(x[2].x + x[3].x, x[2].y + x[3].y);
+        const float2 d1 = make_float2(x[1].x - x[4].x, x[1].y - x[4].y);
+        const float2 d2 = make_float2(x[2].x - x[3].x, x[2].y - x[3].y);
+        const float2 a1 = make_float2(x[0].x + c1 * t1.x + c2 * t2.x, x[0].y + c1 * t1.y + c2 * t2.y);
+        const float2 a2 = make_float2(x[0].x + c2 * t1.x + c1 * t2.x, x[0].y + c2 * t1.y + c1 * t2.y);
+        const float2 b1 = kz_mul_i(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y), SG);
+        const float2 b2 = kz_mul_i(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y), SG);
+        x[0] = make_float2(x[0].x + t1.x + t2.x, x[0].y + t1.y + t2.y);
+        x[1] = make_float2(a1.x + b1.x, a1.y + b1.y);
+        x[4] = make_float2(a1.x - b1.x, a1.y - b1.y);
+        x[2] = make_float2(a2.x + b2.x, a2.y + b2.y);
+        x[3] = make_float2(a2.x - b2.x, a2.y - b2.y);
+    }
+}
+
+// j / d for 0 <= j < 2^13 and 1 <= d < 2^13 from a float reciprocal: the
+// product (j + 1/2) (1/d) is within 2^-23 (j + 1/2) / d of the exact quotient,
+// less than its distance 1 / (2 d) to the nearest integer
+__device__ __forceinline__ int kz_div(int j, float inv_d) { return (int)(((float)j + 0.5f) * inv_d); }
+
+// One Stockham stage over the tile's lines of length n in LDS (element i of
+// line c at c * ls + i * es; lines c >= cnt of a short tile are skipped),
+// Ns = product of the earlier radices: butterfly (c, j), j < n / R, takes
+// elements j + r n / R, multiplies element r by exp(SG 2 pi i r (j mod Ns) /
+// (Ns R)), takes their R-point DFT and puts output r at (j / Ns) Ns R +
+// (j mod Ns) + r Ns.  tw[k] = exp(-2 pi i k / n).  Butterfly b of the tile is
+// (c, j) = (b mod nl, b / nl) (nl = 2^lg lines per tile).  Every thread reads
+// all its butterflies before the barrier and writes them after it, so the
+// stage runs in place.
+template <int R, int SG>
+__device__ void kz_stage(float2* z, const float2* tw, int n, int lg, int cnt, int ls, int es, int Ns) {
+    constexpr int Q = (KZ_EPT + R - 1) / R;
+    const int nl = 1 << lg, m = n / R, total = m << lg, tstep = n / (Ns * R);
+    const float inv_ns = 1.0f / (float)Ns;
+    float2 v[Q][R];
+    int out[Q];
 #pragma unroll
-        for (int b = 0; b < R; ++b) {
-            float2 acc = make_float2(0.f, 0.f);
+    for (int q = 0; q < Q; ++q) {
+        const int b = (int)threadIdx.x + q * KZ_THREADS;
+        const int c = b & (nl - 1), j = b >> lg;
+        out[q] = -1;
+        if (b < total && c < cnt) {
+            const int jd = kz_div(j, inv_ns), k = j - jd * Ns;
+            const int base = c * ls;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const float2 t2 = cmul_f(v[r], wr[(r * b) % R]);
-                acc.x += t2.x;
-                acc.y += t2.y;
+                const float2 x = z[base + (j + r * m) * es];
+                if (r == 0) {
+                    v[q][0] = x;
+                } else {
+                    const float2 w = tw[r * k * tstep];
+                    const float wy = SG < 0 ? w.y : -w.y;
+                    v[q][r] = make_float2(x.x * w.x - x.y * wy, x.x * wy + x.y * w.x);
+                }
             }
-            o[b] = acc;
+            kz_dft<R, SG>(v[q]);
+            out[q] = base + (jd * Ns * R + k) * es;
         }
-        const size_t d = (size_t)(j / Ns) * Ns * R + k;
+    }
+    __syncthreads();
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[off + (d + (size_t)r * Ns) * a.stride] = o[r];
+    for (int q = 0; q < Q; ++q)
+        if (out[q] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) z[out[q] + r * Ns * es] = v[q][r];
+        }
+    __syncthreads();
+}
+
+template <int SG>
+__device__ void kz_line_dft(float2* z, const float2* tw, const KzPass& a, int cnt, int ls, int es) {
+    int Ns = 1;
+    for (int p = 0; p < a.nrad; ++p) {
+        const int R = (int)((a.rads >> (4 * p)) & 15);
+        switch (R) {
+            case 2: kz_stage<2, SG>(z, tw, a.n, a.lg, cnt, ls, es, Ns); break;
+            case 3: kz_stage<3, SG>(z, tw, a.n, a.lg, cnt, ls, es, Ns); break;
+            case 4: kz_stage<4, SG>(z, tw, a.n, a.lg, cnt, ls, es, Ns); break;
+            case 5: kz_stage<5, SG>(z, tw, a.n, a.lg, cnt, ls, es, Ns); break;
+            default: kz_stage<8, SG>(z, tw, a.n, a.lg, cnt, ls, es, Ns); break;
+        }
+        Ns *= R;
     }
 }
 
-__global__ void k_kz_pack(const float* amp, const float* phase, size_t n, float2* z) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        z[i] = make_float2(amp[i], phase[i]);
-}
-__global__ void k_kz_unpack(const float2* z, size_t n, float* amp, float* phase) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const float2 v = z[i];
-        amp[i] = v.x;
-        phase[i] = v.y;
+// One line pass.  F: KZ_IN_FIELDS reads amplitude and phase instead of z,
+// KZ_OUT_FIELDS writes them instead of z, KZ_FILTER runs the forward
+// transform, the weight and the inverse transform (the z pass: its lines are
+// the H W pixels, line p at spectral (y, x) = (p / W, p mod W)); otherwise one
+// transform of sign SG.  Rows (x: lines contiguous in memory) sit in LDS as
+// [c][i] with row pitch a.ls; columns (y, z) as [i][c] with pitch nl.
+// Dynamic LDS: kz_lds_bytes(a).
+template <int F, int SG>
+__global__ __launch_bounds__(KZ_THREADS) void k_kz_lines(float2* z, float* amp, float* phase, KzPass a, KzWeight w) {
+    extern __shared__ float2 kz_lds[];
+    // workgroups are dealt to the 8 XCDs in turn; tile t runs as workgroup
+    // (t mod G8) * 8 + t / G8, so neighbouring tiles (which share cache lines
+    // along a row in the column passes) run side by side on one XCD's L2
+    const int g8 = (int)gridDim.x >> 3, tt = ((int)blockIdx.x & 7) * g8 + ((int)blockIdx.x >> 3);
+    if (tt >= a.tiles) return;
+    const int q = tt / a.tpg, u = tt % a.tpg;
+    const int nl = 1 << a.lg, c0 = u * nl, cnt = min(nl, a.lpg - c0);
+    const int n = a.n;
+    const bool rows = a.gi == 1;
+    const int ls = rows ? a.ls : 1, es = rows ? 1 : nl;
+    float2* t = kz_lds;
+    float2* tw = kz_lds + (size_t)nl * (rows ? a.ls : n);
+    for (int k = threadIdx.x; k < n; k += KZ_THREADS) tw[k] = a.tw[k];
+    const size_t base = (size_t)q * a.gs + (size_t)c0 * a.gc;
+    // tile element e: rows e = c n + i (contiguous in memory), columns
+    // e = i nl + c; returns the LDS slot, or -1 past the tile
+    const float inv_n = 1.0f / (float)n;
+    auto slot = [&](int e, size_t& g) -> int {
+        if (rows) {
+            if (e >= cnt * n) return -1;
+            const int c = kz_div(e, inv_n), i = e - c * n;
+            g = base + (size_t)e;
+            return c * ls + i;
+        }
+        const int c = e & (nl - 1), i = e >> a.lg;
+        if (i >= n || c >= cnt) return -1;
+        g = base + (size_t)c + (size_t)i * a.gi;
+        return e;
+    };
+    // loads in batches of KZ_BATCH per thread, all in flight before the
+    // batch is put into LDS
+    const int ne = rows ? cnt * n : n << a.lg;
+    for (int e0 = 0; e0 < ne; e0 += KZ_BATCH * KZ_THREADS) {
+        float2 v[KZ_BATCH];
+        int sl[KZ_BATCH];
+#pragma unroll
+        for (int r = 0; r < KZ_BATCH; ++r) {
+            size_t g = 0;
+            sl[r] = slot(e0 + (int)threadIdx.x + r * KZ_THREADS, g);
+            if (sl[r] >= 0) {
+                if constexpr ((F & KZ_IN_FIELDS) != 0) v[r] = make_float2(amp[g], phase[g]);
+                else v[r] = z[g];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KZ_BATCH; ++r)
+            if (sl[r] >= 0) t[sl[r]] = v[r];
+    }
+    __syncthreads();
+    if constexpr ((F & KZ_FILTER) != 0) {
+        kz_line_dft<-1>(t, tw, a, cnt, ls, es);
+        // W_a(k) / (S H W): per pixel A = beta^2 / (k_r^2 + 1e-3) and
+        // E = exp(-alpha k_r^2) / (S H W) (k_r^2 in double), per element
+        // (1 - (2 / pi) atan(A k_z^2)) E; k from fftfreq with the pixel size
+        // dx and the slice spacing dz (1/angstrom).  nl divides KZ_THREADS,
+        // so every element a thread visits belongs to its pixel c.
+        const int c = (int)threadIdx.x & (nl - 1);
+        float fa = 0.f, fe = 0.f;
+        if (c < cnt) {
+            const int p = c0 + c, y = p / w.W, x = p - y * w.W;
+            const double kx = (x < (w.W + 1) / 2 ? x : x - w.W) / (w.W * w.dx);
+            const double ky = (y < (w.H + 1) / 2 ? y : y - w.H) / (w.H * w.dx);
+            const double kr2 = kx * kx + ky * ky;
+            fa = (float)(w.beta * w.beta / (kr2 + 1e-3));
+            fe = (float)(exp(-w.alpha * kr2) / ((double)w.S * w.H * w.W));
+        }
+        for (int e = threadIdx.x; e < (n << a.lg); e += KZ_THREADS) {
+            const int s = e >> a.lg;
+            if (c < cnt) {
+                const float kz = (float)((s < (w.S + 1) / 2 ? s : s - w.S) / (w.S * w.dz));
+                const float wt = (1.0f - 0.63661977236758134308f * atanf(fa * kz * kz)) * fe;
+                float2& v = t[c * ls + s * es];
+                v = make_float2(v.x * wt, v.y * wt);
+            }
+        }
+        __syncthreads();
+        kz_line_dft<+1>(t, tw, a, cnt, ls, es);
+    } else {
+        kz_line_dft<SG>(t, tw, a, cnt, ls, es);
+    }
+    for (int e = threadIdx.x; e < ne; e += KZ_THREADS) {
+        size_t g = 0;
+        const int sl = slot(e, g);
+        if (sl < 0) continue;
+        const float2 x = t[sl];
+        if constexpr ((F & KZ_OUT_FIELDS) != 0) {
+            amp[g] = x.x;
+            phase[g] = x.y;
+        } else {
+            z[g] = x;
+        }
     }
 }
 
-// multiply the 3-D spectrum by W_a(k) / (S H W) (the inverse transform's
-// normalisation folded in); k from fftfreq with the pixel size dx and the
-// slice spacing dz (1/angstrom), weight evaluated in double
-__global__ void k_kz_weight(float2* z, int S, int H, int W, double beta, double alpha, double dx, double dz) {
-    const size_t n = (size_t)S * H * W;
-    const double norm = 1.0 / (double)n;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % W), y = (int)((i / W) % H), s = (int)(i / ((size_t)W * H));
-        const double kx = (x < (W + 1) / 2 ? x : x - W) / (W * dx);
-        const double ky = (y < (H + 1) / 2 ? y : y - H) / (H * dx);
-        const double kz = (s < (S + 1) / 2 ? s : s - S) / (S * dz);
-        const double kr2 = kx * kx + ky * ky;
-        const double w = (1.0 - (2.0 / 3.14159265358979323846) * atan(beta * beta * kz * kz / (kr2 + 1e-3))) *
-                         exp(-alpha * kr2) * norm;
-        z[i] = make_float2((float)(z[i].x * w), (float)(z[i].y * w));
+// exp(-2 pi i k / n) for k < n (in double, rounded to float)
+__global__ void k_kz_twiddles(float2* tw, int n) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * k / n, &sn, &cs);
+        tw[k] = make_float2((float)cs, (float)-sn);
     }
 }
 
@@ -247,6 +430,38 @@ inline int fft_radices(int n, int* rs) {
     while (n % 4 == 0) { rs[k++] = 4; n /= 4; }
     while (n % 2 == 0) { rs[k++] = 2; n /= 2; }
     return n == 1 ? k : -1;
+}
+
+// the line pass over `groups` groups of lpg lines of length n with the radices
+// rad[0..nrad): 2^lg lines per tile, the most up to nl_max (at most
+// KZ_THREADS) whose tile and twiddle table fit in KZ_LDS; rows
+// (gi == 1) get a row pitch of n + 8 where it fits (LDS reads of the lines'
+// elements side by side then fall in different banks); *grid = the tiles
+inline KzPass kz_pass(int n, int groups, int lpg, size_t gs, size_t gc, size_t gi, const int* rad, int nrad,
+                      int nl_max, const float2* tw, int* grid) {
+    KzPass a{};
+    a.tw = tw;
+    a.n = n;
+    a.lpg = lpg;
+    a.gs = gs;
+    a.gc = gc;
+    a.gi = gi;
+    a.nrad = nrad;
+    for (int k = 0; k < nrad && k < KZ_MAX_RAD; ++k) a.rads |= (unsigned long long)rad[k] << (4 * k);
+    const bool rows = gi == 1;
+    auto fits = [&](int nl, int pitch) { return nl * pitch + n <= KZ_LDS; };
+    a.ls = rows && fits(1, n + 8) ? n + 8 : n;
+    a.lg = 0;
+    while ((2 << a.lg) <= nl_max && fits(2 << a.lg, a.ls)) ++a.lg;
+    a.tpg = (lpg + (1 << a.lg) - 1) >> a.lg;
+    a.tiles = groups * a.tpg;
+    *grid = (a.tiles + 7) & ~7;
+    return a;
+}
+// tile and twiddles
+inline size_t kz_lds_bytes(const KzPass& a) {
+    const size_t nl = (size_t)1 << a.lg;
+    return (nl * (a.gi == 1 ? a.ls : a.n) + a.n) * sizeof(float2);
 }
 
 // ------------------------------------------------------------ probe modes

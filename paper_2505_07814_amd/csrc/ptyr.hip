@@ -804,7 +804,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.cons = take((size_t)ORTH_MAX_M * (ORTH_MAX_M + 1) / 2 * GRAM_MAX_CHUNKS * sizeof(cd) +
                   (size_t)ORTH_MAX_M * ORTH_MAX_M * sizeof(float2) + ORTH_MAX_M * sizeof(double));
     L.rzmat = take((size_t)RZ_REG_S * RZ_REG_S * sizeof(float));     // depth-filter matrix
-    L.kz = take(2 * S * HW * sizeof(float2));                         // k_z filter: two complex fields
+    L.kz = take((S * HW + g->W + g->H + S) * sizeof(float2));       // k_z filter: the complex field, twiddles
     L.total = o;
     return L;
 }
@@ -1575,6 +1575,7 @@ ptyr_status ptyr_constrain(ptyr_ctx* c, float* amp, float* phase, float* probe, 
         return PTYR_E_ARG;
     if (kz) {
         if (!amp || !phase || !(cfg->kz_dz > 0.f) || !isfinite(cfg->kz_dz)) return PTYR_E_ARG;
+        if (std::max(g.S, std::max(g.H, g.W)) > KZ_MAX_SIDE) return PTYR_E_ARG;
         nrad[0] = fft_radices(g.W, rad[0]);
         nrad[1] = fft_radices(g.H, rad[1]);
         nrad[2] = fft_radices(g.S, rad[2]);
@@ -1588,42 +1589,29 @@ ptyr_status ptyr_constrain(ptyr_ctx* c, float* amp, float* phase, float* probe, 
         float* const amp_o = amp ? amp + (size_t)ob * g.S * HW : nullptr;
         float* const phase_o = phase ? phase + (size_t)ob * g.S * HW : nullptr;
         if (kz) {
-            // amplitude + i phase, 3-D transform, weight, inverse, back
-            const size_t n = (size_t)g.S * HW;
-            float2* buf[2] = {at<float2>(c, c->L.kz), at<float2>(c, c->L.kz) + n};
-            hipLaunchKernelGGL(k_kz_pack, dim3(grid_for(n)), dim3(256), 0, st, amp_o, phase_o, n, buf[0]);
-            const Axis axes[3] = {
-                {g.W, (size_t)g.S * g.H, 1, 1, (size_t)g.W, 0, 0},        // x: rows of W
-                {g.H, (size_t)g.S * g.W, (size_t)g.W, (size_t)g.W, HW, 1, 1},   // y: columns, lines = (s, x)
-                {g.S, HW, HW, HW, 0, 1, 1}};                                   // z: depth columns, lines = (y, x)
-            int cur = 0;
-            for (int dir = 0; dir < 2; ++dir) {
-                const float sign = dir == 0 ? -1.f : 1.f;
-                for (int ax = 0; ax < 3; ++ax) {
-                    const Axis& A = axes[ax];
-                    int Ns = 1;
-                    for (int k = 0; k < nrad[ax]; ++k) {
-                        const int R = rad[ax][k];
-                        const size_t total = A.lines * (size_t)(A.n / R);
-                        const dim3 grid(grid_for(total)), blk(256);
-                        const float2* sp = buf[cur];
-                        float2* dp = buf[cur ^ 1];
-                        switch (R) {
-                            case 2: hipLaunchKernelGGL(k_fft_pass<2>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                            case 3: hipLaunchKernelGGL(k_fft_pass<3>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                            case 4: hipLaunchKernelGGL(k_fft_pass<4>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                            case 5: hipLaunchKernelGGL(k_fft_pass<5>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                            default: hipLaunchKernelGGL(k_fft_pass<8>, grid, blk, 0, st, sp, dp, A, Ns, sign); break;
-                        }
-                        cur ^= 1;
-                        Ns *= R;
-                    }
-                }
-                if (dir == 0)
-                    hipLaunchKernelGGL(k_kz_weight, dim3(grid_for(n)), dim3(256), 0, st, buf[cur], g.S, g.H, g.W,
-                                       (double)cfg->kz_beta, (double)cfg->kz_alpha, g.dx, (double)cfg->kz_dz);
-            }
-            hipLaunchKernelGGL(k_kz_unpack, dim3(grid_for(n)), dim3(256), 0, st, buf[cur], n, amp_o, phase_o);
+            // amplitude + i phase: forward x and y passes, the z pass (forward,
+            // weight, inverse), inverse y and x passes
+            float2* zb = at<float2>(c, c->L.kz);
+            float2* twx = zb + (size_t)g.S * HW;           // twiddle tables of the three line lengths
+            float2* twy = twx + g.W;
+            float2* twz = twy + g.H;
+            hipLaunchKernelGGL(k_kz_twiddles, dim3(grid_for(g.W)), dim3(256), 0, st, twx, g.W);
+            hipLaunchKernelGGL(k_kz_twiddles, dim3(grid_for(g.H)), dim3(256), 0, st, twy, g.H);
+            hipLaunchKernelGGL(k_kz_twiddles, dim3(grid_for(g.S)), dim3(256), 0, st, twz, g.S);
+            int gx, gy, gz;
+            const KzPass px = kz_pass(g.W, 1, g.S * g.H, 0, (size_t)g.W, 1, rad[0], nrad[0], 16, twx, &gx);
+            const KzPass py = kz_pass(g.H, g.S, g.W, HW, 1, (size_t)g.W, rad[1], nrad[1], 16, twy, &gy);
+            const KzPass pz = kz_pass(g.S, 1, g.H * g.W, 0, 1, HW, rad[2], nrad[2], 256, twz, &gz);
+            const KzWeight kw{g.S, g.H, g.W, (double)cfg->kz_beta, (double)cfg->kz_alpha, g.dx, (double)cfg->kz_dz};
+            const dim3 blk(KZ_THREADS);
+            hipLaunchKernelGGL((k_kz_lines<KZ_IN_FIELDS, -1>), dim3(gx), blk, kz_lds_bytes(px), st, zb, amp_o, phase_o,
+                               px, kw);
+            hipLaunchKernelGGL((k_kz_lines<0, -1>), dim3(gy), blk, kz_lds_bytes(py), st, zb, amp_o, phase_o, py, kw);
+            hipLaunchKernelGGL((k_kz_lines<KZ_FILTER, 0>), dim3(gz), blk, kz_lds_bytes(pz), st, zb, amp_o, phase_o, pz,
+                               kw);
+            hipLaunchKernelGGL((k_kz_lines<0, +1>), dim3(gy), blk, kz_lds_bytes(py), st, zb, amp_o, phase_o, py, kw);
+            hipLaunchKernelGGL((k_kz_lines<KZ_OUT_FIELDS, +1>), dim3(gx), blk, kz_lds_bytes(px), st, zb, amp_o,
+                               phase_o, px, kw);
         }
         if (rz && g.S > 1) {
             // taps in double, normalised, then rounded (the same on every call)

@@ -179,10 +179,15 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("S,H,W", [(12, 80, 75), (1, 64, 90), (30, 72, 72), (6, 64, 64)])
+@pytest.mark.parametrize("S,H,W", [(12, 80, 75), (1, 64, 90), (30, 72, 72), (6, 64, 64), (45, 64, 72),
+                                   (2, 2048, 64), (2, 4096, 64)])
 def test_kz_filter_matches_oracle(S, H, W):
     """Mixed-radix 3-D transform, weight, inverse: relative L2 <= 1e-5 of the
-    oracle for each field (float transforms of ~log2(SHW) stages each way)."""
+    oracle for each field (float transforms of ~log2(SHW) stages each way).
+    The shapes give short last tiles of rows, columns and depth columns,
+    three radices along depth and along x (45 = 5 x 3 x 3, 72 = 3 x 3 x 8),
+    and columns of 2048 and 4096 (the longest line: one column per tile,
+    filling the 64 KiB of LDS)."""
     print(f"kz filter {S}x{H}x{W}", flush=True)
     rng = np.random.default_rng(S + H + W)
     amp = rng.uniform(0.5, 1.5, (S, H, W)).astype(np.float32)
@@ -233,6 +238,10 @@ def test_kz_bad_arguments():
     a = torch.ones((3, 70, 64), device=DEV)
     with pytest.raises(L.PtyrError):
         eng.constrain(a, a.clone(), kz_beta=1.0, kz_dz=5.0)
+    eng3 = Engine(64, 1, 1, 64, 4320, 1, 0.2, 0.02, device=DEV)      # 4320 = 2^5 3^3 5 > 4096
+    c = torch.ones((1, 64, 4320), device=DEV)
+    with pytest.raises(L.PtyrError):
+        eng3.constrain(c, c.clone(), kz_beta=1.0, kz_dz=5.0)
     eng2 = engine(3, 64, 64)
     b = torch.ones((3, 64, 64), device=DEV)
     for kw in (dict(kz_beta=1.0, kz_dz=0.0), dict(kz_beta=-1.0, kz_dz=1.0), dict(kz_alpha=1.0, kz_dz=-2.0)):
