@@ -76,9 +76,9 @@ void fwd_layer(ptyr_cnn* c, const float* params, int B, float* out) {
 
 template <int L>
 void bwd_layer(ptyr_cnn* c, int B, float* grad) {
-    constexpr int MT = COUTP[L] / 16, NT = kp(L) / 16, PW = w_size(L) + COUTP[L];
+    constexpr int NT = kp(L) / 16, PW = w_size(L) + COUTP[L];
     const int nchunk = (B * HOUT[L] * HOUT[L] + WCHUNK - 1) / WCHUNK;
-    hipLaunchKernelGGL(k_wgrad<L>, dim3(nchunk, (MT * NT + 3) / 4), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(k_wgrad<L>, dim3(nchunk, (NT + wg_nt<L>() - 1) / wg_nt<L>()), dim3(256), 0, c->stream,
                        at<__bf16>(c, c->G[L]), at<__bf16>(c, c->X[L]), at<float>(c, c->wpart), B);
     // weights and bias are contiguous in the parameter vector: one reduction
     hipLaunchKernelGGL(k_wreduce, dim3((PW + 31) / 32), dim3(256), 0, c->stream, at<float>(c, c->wpart), nchunk, PW,

@@ -32,6 +32,7 @@ namespace cnn {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 typedef __attribute__((ext_vector_type(4))) float floatx4;
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 
 constexpr int NLAYER = 5;
 constexpr int NB = 9;             // patterns per neighbourhood
@@ -198,51 +199,124 @@ __global__ void k_mse_grad(const float* out, const float* target, int n, __bf16*
 // Weight and bias gradient of layer L over one chunk of WCHUNK output pixels:
 //   part[chunk][o * K + k] = sum_{p in chunk} G[p][o] Xcol[k][p]
 //   part[chunk][Cout_p * K + o] = sum_{p in chunk} G[p][o]        (bias)
-// One wave per (16 o x 16 k) tile of a chunk; the pixel sum is the MFMA
-// reduction.  The waves of the k = 0..15 tiles also add up their G operands
-// for the bias, in a fixed order (own pixels, then lanes 16 and 32 apart).
+// A workgroup covers one chunk and WG_NT(L) consecutive 16-wide reduction
+// tiles (blockIdx.y) for all output channels.  For every 32 pixels it stages
+// G^T and the im2col rows Xcol of its reduction range in LDS, pixel-fastest
+// (16-byte global loads of 8 channels, written out per channel), so each MFMA
+// operand, 8 consecutive pixels of one row, is one 16-byte LDS read; the pixel
+// sum is the MFMA reduction.  The waves holding the k = 0..15 tiles also add up
+// their G operands for the bias, in a fixed order (own pixels, then lanes 16
+// and 32 apart).
+template <int L> constexpr int wg_nt() { return (kp(L) / 16 + 2) / 3; }
+
 template <int L>
 __global__ __launch_bounds__(256) void k_wgrad(const __bf16* G, const __bf16* X, float* part, int B) {
     constexpr int cinp = CINP[L], coutp = COUTP[L], s = STRIDE[L], hin = HIN[L], hout = HOUT[L], K = kp(L);
-    constexpr int MT = coutp / 16, NT = K / 16, PW = w_size(L) + coutp;
-    const int lane = threadIdx.x % 64, g = lane / 16, n = lane % 16;
-    const int tile = blockIdx.y * 4 + threadIdx.x / 64;
-    if (tile >= MT * NT) return;
-    const int mt = tile / NT, nt = tile % NT;
-    const int chunk = blockIdx.x;
-    const int o = mt * 16 + n;             // A row held by this lane
-    const int k = nt * 16 + n;             // B column held by this lane
-    const bool kreal = k < 9 * cinp;
-    const int tap = k / cinp, c = k % cinp, du = tap / 3 - 1, dv = tap % 3 - 1;
-    const int P = B * hout * hout;         // the last chunk may be partial
-    const int qend = min(WCHUNK, P - chunk * WCHUNK);
-    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;
-    for (int q0 = 0; q0 < qend; q0 += 32) {
-        bf16x8 av, bv;
+    constexpr int MT = coutp / 16, NT = K / 16, NTW = wg_nt<L>(), KW = 16 * NTW;
+    constexpr int TPW = (MT * NTW + 3) / 4;            // tiles per wave
+    constexpr int PITCH = 40;                          // bf16 per staged row: 32 pixels, 80 B (16-B aligned rows)
+    __shared__ __align__(16) __bf16 gs[coutp * PITCH];
+    __shared__ __align__(16) __bf16 xs[KW * PITCH];
+    const int lane = threadIdx.x % 64, g = lane / 16, n = lane % 16, wave = threadIdx.x / 64;
+    const int chunk = blockIdx.x, nt0 = blockIdx.y * NTW, ntw = min(NTW, NT - nt0), k0 = 16 * nt0;
+    const int P = B * hout * hout;                     // the last chunk may be partial
+    const int pbase = chunk * WCHUNK, qend = min(WCHUNK, P - pbase);
+    floatx4 acc[TPW];
+    float bs[TPW];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int p = chunk * WCHUNK + q0 + 8 * g + e;
-            const bool pin = p < P;
-            av[e] = pin ? G[(size_t)p * coutp + o] : (__bf16)0.0f;
-            const int b = p / (hout * hout), yo = (p / hout) % hout, xo = p % hout;
-            const int yi = yo * s + du, xi = xo * s + dv;
-            const bool in = pin && kreal && yi >= 0 && yi < hin && xi >= 0 && xi < hin;
-            bv[e] = in ? X[(((size_t)b * hin + yi) * hin + xi) * cinp + c] : (__bf16)0.0f;
-        }
-        acc = mfma(av, bv, acc);
-        if (nt == 0) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) bsum += (float)av[e];
-        }
+    for (int t = 0; t < TPW; ++t) {
+        acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        bs[t] = 0.f;
     }
-    float* dst = part + (size_t)chunk * PW;
+    // the pieces this thread stages, two pixels each (16 bytes = 8 channels
+    // of each): G^T items it = tid + 256 j (16 pixel pairs x coutp / 8 channel
+    // groups), Xcol items likewise (16 pixel pairs x KW / 8 row groups; 8
+    // consecutive k share a tap, cinp being a multiple of 8).  A pair goes to
+    // LDS as 8 dwords (channel e of both pixels); the next 32 pixels' pieces
+    // are loaded while the MFMAs run.
+    constexpr int NGI = 16 * (coutp / 8), NXI = 16 * (KW / 8);
+    constexpr int NG = (NGI + 255) / 256, NX = (NXI + 255) / 256;
+    bf16x8 gv[NG][2], xv[NX][2];
+    auto xload = [&](int p, int k) -> bf16x8 {
+        const int tap = k / cinp, c = k % cinp;
+        const int b = p / (hout * hout), yo = (p / hout) % hout, xo = p % hout;
+        const int yi = yo * s + tap / 3 - 1, xi = xo * s + tap % 3 - 1;
+        if (p < P && yi >= 0 && yi < hin && xi >= 0 && xi < hin) return ld8(X + (((size_t)b * hin + yi) * hin + xi) * cinp + c);
+        return zero8();
+    };
+    auto fetch = [&](int p0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dst[(mt * 16 + 4 * g + r) * K + nt * 16 + n] = acc[r];
-    if (nt == 0) {
-        bsum += __shfl_xor(bsum, 16, 64);
-        bsum += __shfl_xor(bsum, 32, 64);
-        if (g == 0) dst[w_size(L) + o] = bsum;
+        for (int j = 0; j < NG; ++j) {
+            const int it = threadIdx.x + 256 * j, cg = it / 16, p = p0 + 2 * (it % 16);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                gv[j][h] = it < NGI && p + h < P ? ld8(G + (size_t)(p + h) * coutp + 8 * cg) : zero8();
+        }
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            const int it = threadIdx.x + 256 * j, kg = it / 16, p = p0 + 2 * (it % 16), k = k0 + 8 * kg;
+            const bool use = it < NXI && kg < 2 * ntw && k < 9 * cinp;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) xv[j][h] = use ? xload(p + h, k) : zero8();
+        }
+    };
+    // channel e of a pixel pair (a: first pixel, low half) as one dword
+    auto pair = [](const bf16x8& a, const bf16x8& b, int e) -> uint32_t {
+        const u32x4 ua = __builtin_bit_cast(u32x4, a), ub = __builtin_bit_cast(u32x4, b);
+        const uint32_t x = ua[e >> 1], y = ub[e >> 1];
+        return (e & 1) ? (x >> 16) | (y & 0xffff0000u) : (x & 0xffffu) | (y << 16);
+    };
+    uint32_t* gs32 = reinterpret_cast<uint32_t*>(gs);
+    uint32_t* xs32 = reinterpret_cast<uint32_t*>(xs);
+    fetch(pbase);
+    for (int q0 = 0; q0 < qend; q0 += 32) {
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            const int it = threadIdx.x + 256 * j, cg = it / 16, pq = it % 16;
+            if (it < NGI) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) gs32[(8 * cg + e) * (PITCH / 2) + pq] = pair(gv[j][0], gv[j][1], e);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            const int it = threadIdx.x + 256 * j, kg = it / 16, pq = it % 16;
+            if (it < NXI) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xs32[(8 * kg + e) * (PITCH / 2) + pq] = pair(xv[j][0], xv[j][1], e);
+            }
+        }
+        __syncthreads();
+        if (q0 + 32 < qend) fetch(pbase + q0 + 32);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int i = wave + 4 * t, mt = i / NTW, ntl = i % NTW;
+            if (i < MT * NTW && ntl < ntw) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(gs + (mt * 16 + n) * PITCH + 8 * g);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(xs + (ntl * 16 + n) * PITCH + 8 * g);
+                acc[t] = mfma(av, bv, acc[t]);
+                if (nt0 == 0 && ntl == 0) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) bs[t] += (float)av[e];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float* dst = part + (size_t)chunk * (w_size(L) + coutp);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int i = wave + 4 * t, mt = i / NTW, ntl = i % NTW;
+        if (i < MT * NTW && ntl < ntw) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[(mt * 16 + 4 * g + r) * K + (nt0 + ntl) * 16 + n] = acc[t][r];
+            if (nt0 == 0 && ntl == 0) {
+                float b = bs[t];
+                b += __shfl_xor(b, 16, 64);
+                b += __shfl_xor(b, 32, 64);
+                if (g == 0) dst[w_size(L) + mt * 16 + n] = b;
+            }
+        }
     }
 }
 
