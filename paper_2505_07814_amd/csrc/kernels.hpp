@@ -385,22 +385,40 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
         }
         const float2* Os = chain_object(a, m) + (size_t)s * HW + (size_t)pi.ty * a.W + pi.tx;
         float2* go = a.gO + ((size_t)(j * a.M + m) * a.S + s) * N * N;
-        // The reads of each half are issued before its writes: the
-        // patch-gradient writes could alias the reads as far as the compiler
-        // knows, so interleaved they would serialise every read behind a full
-        // wait; two halves keep the registers in flight at 32.
-#pragma unroll
-        for (int h = 0; h < 16; h += 8) {
+        // The reads run in two halves of 8 registers (32 VGPRs in flight),
+        // each issued before any patch-gradient write that follows it: the
+        // writes could alias the reads as far as the compiler knows, and one
+        // in-order counter covers reads and writes, so a read issued after a
+        // write waits for that write too.  Half 0's patch gradient t0 is
+        // therefore written only after half 1's reads are issued (measured:
+        // gradient launch 0.432 -> 0.417 ms).
+        float2 t0[8];
+        {
             float2 ph[8], ov[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                ph[r] = (phi_s + YC::dy(h + r) * N)[oN];
-                ov[r] = (Os + YC::dy(h + r) * a.W)[oW];
+                ph[r] = (phi_s + YC::dy(r) * N)[oN];
+                ov[r] = (Os + YC::dy(r) * a.W)[oW];
             }
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                (go + YC::dy(h + r) * N)[oN] = cmulc(g[h + r], ph[r]);        // conj(phi) G_chi
-                g[h + r] = cmulc(g[h + r], ov[r]);                             // G_phi = conj(O) G_chi
+                t0[r] = cmulc(g[r], ph[r]);                                    // conj(phi) G_chi
+                g[r] = cmulc(g[r], ov[r]);                                     // G_phi = conj(O) G_chi
+            }
+        }
+        {
+            float2 ph[8], ov[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                ph[r] = (phi_s + YC::dy(8 + r) * N)[oN];
+                ov[r] = (Os + YC::dy(8 + r) * a.W)[oW];
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) (go + YC::dy(r) * N)[oN] = t0[r];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                (go + YC::dy(8 + r) * N)[oN] = cmulc(g[8 + r], ph[r]);
+                g[8 + r] = cmulc(g[8 + r], ov[r]);
             }
         }
         fft2_from_col<N>(g, lds, tab.tw, l, c);                               // G^ = F_raw G_phi
