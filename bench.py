@@ -421,7 +421,8 @@ def constraints_bench(args):
     kz_bytes = 16 * passes * w.S * w.H * w.W
     out["kz_filter"] = {"ms_per_call": round(ms_kz, 4), "passes": passes, "bytes_per_call": kz_bytes,
                         "achieved_GBs": round(kz_bytes / (ms_kz * 1e-3) / 1e9, 1),
-                        "frac_of_hbm_peak": round(kz_bytes / (ms_kz * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+                        "frac_of_hbm_peak": round(kz_bytes / (ms_kz * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                        "traffic": read_traffic("kz", "constraints_128")}
     if args.copy_calibration:
         copy_calibration(out, dev)
     print(json.dumps(out), flush=True)
