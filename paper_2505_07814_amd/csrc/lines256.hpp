@@ -102,6 +102,7 @@ struct Pass256 {
     WaveArgs a;
     float2* wave;          // B x M x 256 x 256 working waves
     int s;                 // slice of the pass
+    int mg;                // gradient row pass: probe modes per workgroup (divides the probe modes)
 };
 
 // Forward row pass of slice s: wave holds (y, k_x) of the previous column
@@ -271,39 +272,53 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
         for (int k = 0; k < 5; ++k) part[k] += acc[k];
 }
 
-// Gradient row pass of slice s: wave holds (y, k_x) of G after the inverse
-// along y; inverse along x gives G_chi_s; writes gO_s = conj(phi_s) G_chi,
-// then G_phi = conj(O_s) G_chi transformed along x.
+// Gradient row pass of slice s for P.mg consecutive chains of one position
+// and object mode (probe modes p0 .. p0 + mg - 1): per chain the wave holds
+// (y, k_x) of G after the inverse along y; the inverse along x gives
+// G_chi_s, the group's patch gradient sum_p conj(phi_s) G_chi (in probe-mode
+// order) is summed in registers, and G_phi = conj(O_s) G_chi is transformed
+// along x.  The object patch is read once for the group and the summed patch
+// gradient written once, mg times less patch-gradient traffic (written here,
+// read by the object scatter) than one per chain.  The next chain's phi_s is
+// read while the current chain's line DFT runs.
 __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
     __shared__ float2 lds[LDS256];
     __shared__ Tables256 tab;
     const WaveArgs& a = P.a;
-    const int ch = a.chain0 + blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
-    const int j = ch / a.M;
+    const int mg = P.mg, grp = a.chain0 / mg + blockIdx.x / NBLK256, blk = blockIdx.x % NBLK256;
+    const int ch0 = grp * mg, j = ch0 / a.M;
     const PosInfo pi = a.pinfo[j];
     if (pi.ty < 0) return;
     const int l = threadIdx.x / 16, c = threadIdx.x % 16, y = blk * LINES256 + l;
     build256<1>(tab, a, pi, blk * LINES256);
-    const Slots<N256> sl(a, ch);
-    float2* w = P.wave + (size_t)ch * N256 * N256;
-    float2 v[16], ph[16], ov[16];
-    rows_load(v, w, y, c);
-    // phi_s and the object patch are read now, so that their latency
-    // overlaps the line DFT
-    rows_load(ph, sl.phi(P.s), y, c);
-    const float2* Os = chain_object(a, ch % a.M) + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) ov[r] = Os[c + 16 * r];
-    mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                      // G_chi_s (space)
-    float2* go = a.gO + (((size_t)ch * a.S + P.s) * N256 + y) * N256;
+    float2 v[16], ph[16], ov[16], acc[16];
+    rows_load(v, P.wave + (size_t)ch0 * N256 * N256, y, c);
+    rows_load(ph, Slots<N256>(a, ch0).phi(P.s), y, c);
+    // the object patch (the same for the group's chains) and the first
+    // chain's G and phi_s are read now, so that their latency overlaps the
+    // line DFT
+    const float2* Os = chain_object(a, ch0 % a.M) + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int xx = c + 16 * r;
-        go[xx] = cmulc(v[r], ph[r]);                                      // conj(phi) G_chi
-        v[r] = cmulc(v[r], ov[r]);                                        // conj(O) G_chi
+        ov[r] = Os[c + 16 * r];
+        acc[r] = make_float2(0.f, 0.f);
     }
-    nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
-    rows_store(v, w, y, c);
+    for (int p = 0; p < mg; ++p) {
+        const int ch = ch0 + p;
+        mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                  // G_chi_s (space)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            acc[r] = cadd(acc[r], cmulc(v[r], ph[r]));                  // conj(phi) G_chi
+            v[r] = cmulc(v[r], ov[r]);                                  // conj(O) G_chi
+        }
+        if (p + 1 < mg) rows_load(ph, Slots<N256>(a, ch + 1).phi(P.s), y, c);
+        nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
+        rows_store(v, P.wave + (size_t)ch * N256 * N256, y, c);
+        if (p + 1 < mg) rows_load(v, P.wave + (size_t)(ch + 1) * N256 * N256, y, c);
+    }
+    float2* go = a.gO + (((size_t)grp * a.S + P.s) * N256 + y) * N256;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) go[c + 16 * r] = acc[r];
 }
 
 // Orthonormal 2-D DFT of `count` 256 x 256 waves as two passes:

@@ -407,7 +407,8 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
                                                         const float* phase, const double* scale, float* g_amp,
                                                         float* g_phase, ObjAdam ad, float sp) {
     const int ntx = (W + 31) / 32;
-    // blockIdx.y = o S + s: object mode o, slice s; chain modes o M .. o M + M - 1
+    // blockIdx.y = o S + s: object mode o, slice s; patch-gradient entries o M .. o M + M - 1 of a
+    // position (Mc per position: one per chain, or one per group of probe modes at N = 256)
     const int tile = blockIdx.x, s = blockIdx.y % S, om = (blockIdx.y / S) * M;
     const int y0 = (tile / ntx) * 32, x0 = (tile % ntx) * 32;
     const int x = x0 + (int)threadIdx.x % 32, yb = y0 + (int)threadIdx.x / 32;
@@ -1097,7 +1098,15 @@ Pass256 pass256(ptyr_ctx* c, const WaveArgs& a, int s) {
     P.a = a;
     P.wave = at<float2>(c, c->L.wave);
     P.s = s;
+    P.mg = 1;
     return P;
+}
+// probe modes whose patch gradients the N = 256 gradient row pass sums per
+// workgroup (a divisor of the probe modes, at most 4: two workgroups per
+// compute unit at the 16-position batch); 1 for N = 64 and 128
+int row_group(const ptyr_geom& g) {
+    if (g.N != 256) return 1;
+    return g.M % 4 == 0 ? 4 : (g.M % 2 == 0 ? 2 : 1);
 }
 void forward256(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
     TimedLaunch t(c, PTYR_K_FORWARD, st);
@@ -1114,8 +1123,14 @@ void gradient256(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
     a.chain0 = c0;
     const dim3 grid(nc * NBLK256), blk(256);
     hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, st, pass256(c, a, a.S));
+    // the row pass takes row_group(g) chains per workgroup (c0 and nc are
+    // multiples of it: N = 256 batches are not split)
+    const int mg = row_group(c->g);
+    const dim3 rgrid(nc / mg * NBLK256);
     for (int s = a.S - 1; s >= 0; --s) {
-        hipLaunchKernelGGL(k256_grad_row, grid, blk, 0, st, pass256(c, a, s));
+        Pass256 P = pass256(c, a, s);
+        P.mg = mg;
+        hipLaunchKernelGGL(k256_grad_row, rgrid, blk, 0, st, P);
         hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, st, pass256(c, a, s));
     }
 }
@@ -1365,24 +1380,27 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
         if (!(g_amp || g_phase)) return;
         const int ntiles = ((g.H + 31) / 32) * ((g.W + 31) / 32);
         const dim3 grid(ntiles, g.S * obj_modes(g));
-        const bool mb8 = g.M % 8 == 0;
+        // patch gradients per position and object mode: one per group of
+        // row_group(g) probe modes (the N = 256 row pass sums each group)
+        const int mg = row_group(g), Mg = g.M / mg, Mcg = M / mg;
+        const bool mb8 = Mg % 8 == 0;
         const float2* gO = at<float2>(c, c->L.gO);
         const PosInfo* pinfo = at<PosInfo>(c, c->L.pinfo);
         if (last && fuse) {
             ObjAdam ad = *fuse;
             ad.gin = j0 > 0 ? 1 : 0;
             if (mb8)
-                hipLaunchKernelGGL((k_scatter_object<true, 8>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, g.M, M,
+                hipLaunchKernelGGL((k_scatter_object<true, 8>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, Mg, Mcg,
                                    g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ad, sp);
             else
-                hipLaunchKernelGGL((k_scatter_object<true, 4>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, g.M, M,
+                hipLaunchKernelGGL((k_scatter_object<true, 4>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, Mg, Mcg,
                                    g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ad, sp);
         } else if (j1 > j0) {
             if (mb8)
-                hipLaunchKernelGGL((k_scatter_object<false, 8>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, g.M, M,
+                hipLaunchKernelGGL((k_scatter_object<false, 8>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, Mg, Mcg,
                                    g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
             else
-                hipLaunchKernelGGL((k_scatter_object<false, 4>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, g.M, M,
+                hipLaunchKernelGGL((k_scatter_object<false, 4>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, Mg, Mcg,
                                    g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
         }
     };
