@@ -55,15 +55,15 @@ def line_pass_bytes(w, B, n_obj=1):
     column pass writing the far field and the mode intensity instead (2.5);
     so 6S + 1.5 waves.  Gradient, per chain: 6S + 1.5 waves (the column pass
     also reads Y, the row pass reads phi), plus the patch gradients, which the
-    row pass sums over groups of mg probe modes (mg = 4 when the probe modes
-    come in fours, else 2 when even, else 1) and writes once per group: S / mg
-    waves per chain.  Object patches are read once per batch row, slice and
+    row pass sums over groups of mg probe modes (mg = the largest divisor of
+    the probe modes up to 8) and writes once per group: S / mg waves per
+    chain.  Object patches are read once per batch row, slice and
     object mode; with n_obj object modes every probe mode meets every object
     mode."""
     wave = w.N * w.N * 8
     chains = B * w.M * n_obj
     patches = B * w.S * wave * n_obj
-    mg = 4 if w.M % 4 == 0 else (2 if w.M % 2 == 0 else 1)
+    mg = max(d for d in range(1, 9) if w.M % d == 0)
     return {"forward": chains * (6 * w.S + 1.5) * wave + patches,
             "gradient": chains * (6 * w.S + w.S / mg + 1.5) * wave + patches}
 

@@ -1102,11 +1102,14 @@ Pass256 pass256(ptyr_ctx* c, const WaveArgs& a, int s) {
     return P;
 }
 // probe modes whose patch gradients the N = 256 gradient row pass sums per
-// workgroup (a divisor of the probe modes, at most 4: two workgroups per
-// compute unit at the 16-position batch); 1 for N = 64 and 128
+// workgroup: the largest divisor of the probe modes up to 8 (measured at the
+// 16-position, 8-mode batch: groups of 8, 4 and 2 give 6.65, 6.76 and
+// 7.08 ms per step); 1 for N = 64 and 128
 int row_group(const ptyr_geom& g) {
     if (g.N != 256) return 1;
-    return g.M % 4 == 0 ? 4 : (g.M % 2 == 0 ? 2 : 1);
+    for (int d = 8; d > 1; --d)
+        if (g.M % d == 0) return d;
+    return 1;
 }
 void forward256(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
     TimedLaunch t(c, PTYR_K_FORWARD, st);
