@@ -260,12 +260,12 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     const float2* Ocm = chain_object(a, m);
     float2 v[16];
     shift_probe<N>(v, chain_probe(a, m, N * N), lds, tab, l, c);
+    // the object patch of a slice is read one slice ahead, so that its
+    // latency overlaps the previous slice's transforms (forward launch
+    // 0.486 -> 0.467 ms)
+    float2 ov[16];
+    if (a.S > 1) load_patch<N>(ov, Ocm, a.W, pi.ty, pi.tx, l, c);
     for (int s = 0; s < a.S - 1; ++s) {
-        // the object patch is read before phi_s is written: waiting for the
-        // reads then does not also wait for those writes (one in-order
-        // counter covers both)
-        float2 ov[16];
-        load_patch<N>(ov, Ocm + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
         // chi_s is formed before phi_s is written: waiting for the patch then
         // cannot wait for those (conditional) writes as well
 #pragma unroll
@@ -274,6 +274,7 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
         else if (ckpt && s % a.ckK == 0) wstore<N, COL, NAT>(v, sl.ckpt(s / a.ckK), N, l, c);
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = ov[r];
+        if (s + 1 < a.S - 1) load_patch<N>(ov, Ocm + (size_t)(s + 1) * HW, a.W, pi.ty, pi.tx, l, c);
         fft2_from_col<N>(v, lds, tab.tw, l, c);
         apply_h<N, false>(v, tab, l, c);
         if (full) wstore<N, ROW, MID>(v, sl.spec(s + 1), N, l, c);
