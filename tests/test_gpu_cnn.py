@@ -66,8 +66,10 @@ def test_forward_matches_oracle(net, B, n_pat, seed):
     assert rel(out, cn.forward(layers, pats[nbr])) < 3e-2
 
 
-@pytest.mark.parametrize("B,n_pat,seed", [(2, 10, 4), (4, 30, 5)])
+@pytest.mark.parametrize("B,n_pat,seed", [(2, 10, 4), (3, 12, 14), (4, 30, 5)])
 def test_gradient_matches_oracle(net, B, n_pat, seed):
+    """B = 3 leaves the weight gradient's second 2048-pixel chunk of layers
+    1-4 half full."""
     layers, vec, pats, nbr, target = make_case(B, n_pat, seed)
     grad = torch.zeros(gcnn.param_count(), dtype=torch.float32, device=DEV)
     loss = torch.zeros(1, dtype=torch.float64, device=DEV)
