@@ -43,37 +43,56 @@ struct Tables256 {
     float2 rl[LINES256];   // shift ramp of each line of the block (column passes)
 };
 
-// Build the twiddles and, for a position, the propagator / ramp factors along
-// the pass direction (AXIS 0: y, 1: x) for all 256 frequencies, and the
-// factors of the block's 16 lines along the other axis.
-template <int AXIS>
-__device__ __forceinline__ void build256(Tables256& t, const WaveArgs& a, const PosInfo& pi, int line0) {
+// The factors of one batch position, both axes (0: y, 1: x), all 256
+// frequencies: propagator h[axis][k] = exp(-i pi lam dz k^2 + 2 pi i dz k
+// tan th_axis) and shift ramp r[axis][k] = exp(-2 pi i q dr_axis), as
+// compensated unit pairs (the ramp's low parts are not used).  Computed once
+// per forward or gradient call by k256_tables instead of in every workgroup
+// of every pass.
+struct PosTab256 {
+    float4 h[2][N256];
+    float2 r[2][N256];
+};
+
+// twiddles (block 0) and the factors of batch position blockIdx.x; 256
+// threads, one per frequency
+__global__ __launch_bounds__(256) void k256_tables(WaveArgs a, float4* tw, PosTab256* tab) {
     const double pi_d = 3.14159265358979323846;
+    const int n = threadIdx.x, j = blockIdx.x;
+    double s, c;
+    if (j == 0) {
+        sincos(-2.0 * pi_d * (double)((n / 16) * (n % 16)) / N256, &s, &c);
+        tw[n] = unit_pair(c, s);
+    }
+    const PosInfo pi = a.pinfo[j];
+    if (pi.ty < 0) return;                           // the passes skip the row
     const float* th = a.global_tilt ? a.tilt : a.tilt + 2 * pi.row;
     const double dz = *a.dz;
-    const double tan_p = tan((double)th[AXIS]), tan_o = tan((double)th[1 - AXIS]);
-    const double dr_p = AXIS == 0 ? pi.dry : pi.drx, dr_o = AXIS == 0 ? pi.drx : pi.dry;
-    const int n = threadIdx.x;                       // blockDim.x == 256
-    {
-        double s, c;
-        sincos(-2.0 * pi_d * (double)((n / 16) * (n % 16)) / N256, &s, &c);
-        t.tw[n] = unit_pair(c, s);
-        const double q = (double)sfreq<N256>(n) / N256, k = q / a.dx;
-        sincos(-pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan_p, &s, &c);
-        t.h[n] = unit_pair(c, s);
-        sincos(-2.0 * pi_d * q * dr_p, &s, &c);
+    const double q = (double)sfreq<N256>(n) / N256, k = q / a.dx;
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        const double tan_a = tan((double)th[ax]), dr = ax == 0 ? pi.dry : pi.drx;
+        sincos(-pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan_a, &s, &c);
+        tab[j].h[ax][n] = unit_pair(c, s);
+        sincos(-2.0 * pi_d * q * dr, &s, &c);
         const float4 r = unit_pair(c, s);
-        t.r[n] = make_float2(r.x, r.y);
+        tab[j].r[ax][n] = make_float2(r.x, r.y);
     }
+}
+
+// A workgroup's tables: the twiddles and, for its position, the factors along
+// the pass direction (AXIS 0: y, 1: x) for all 256 frequencies and those of
+// the block's 16 lines along the other axis.
+template <int AXIS>
+__device__ __forceinline__ void load256(Tables256& t, const float4* tw, const PosTab256* tab, int j, int line0) {
+    const int n = threadIdx.x;                       // blockDim.x == 256
+    const PosTab256& T = tab[j];
+    t.tw[n] = tw[n];
+    t.h[n] = T.h[AXIS][n];
+    t.r[n] = T.r[AXIS][n];
     if (n < LINES256) {
-        const int m = line0 + n;
-        const double q = (double)sfreq<N256>(m) / N256, k = q / a.dx;
-        double s, c;
-        sincos(-pi_d * a.lam * dz * k * k + 2.0 * pi_d * dz * k * tan_o, &s, &c);
-        t.hl[n] = unit_pair(c, s);
-        sincos(-2.0 * pi_d * q * dr_o, &s, &c);
-        const float4 r = unit_pair(c, s);
-        t.rl[n] = make_float2(r.x, r.y);
+        t.hl[n] = T.h[1 - AXIS][line0 + n];
+        t.rl[n] = T.r[1 - AXIS][line0 + n];
     }
     __syncthreads();
 }
@@ -101,6 +120,8 @@ __device__ __forceinline__ void cols_store(const float2 (&v)[16], float2* w, int
 struct Pass256 {
     WaveArgs a;
     float2* wave;          // B x M x 256 x 256 working waves
+    const float4* tw;      // twiddles (k256_tables)
+    const PosTab256* tab;  // per batch position factors (k256_tables)
     int s;                 // slice of the pass
     int mg;                // gradient row pass: probe modes per workgroup (divides the probe modes)
 };
@@ -117,7 +138,7 @@ __global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
     const PosInfo pi = a.pinfo[j];
     if (pi.ty < 0) return;
     const int l = threadIdx.x / 16, c = threadIdx.x % 16, y = blk * LINES256 + l;
-    build256<1>(tab, a, pi, blk * LINES256);
+    load256<1>(tab, P.tw, P.tab, j, blk * LINES256);
     float2* w = P.wave + (size_t)ch * N256 * N256;
     float2 v[16], ov[16];
     rows_load(v, w, y, c);
@@ -159,7 +180,7 @@ __global__ __launch_bounds__(256) void k256_fwd_col(Pass256 P) {
         }
         return;
     }
-    build256<0>(tab, a, pi, blk * LINES256);
+    load256<0>(tab, P.tw, P.tab, j, blk * LINES256);
     float2* w = P.wave + (size_t)ch * N256 * N256;
     float2 v[16];
     if (P.s < 0) {
@@ -213,7 +234,7 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
         }
         return;
     }
-    build256<0>(tab, a, pi, blk * LINES256);
+    load256<0>(tab, P.tw, P.tab, j, blk * LINES256);
     const Slots<N256> sl(a, ch);
     float2* w = P.wave + (size_t)ch * N256 * N256;
     const float inv_n = 1.0f / N256, inv_n2 = 1.0f / ((float)N256 * N256);
@@ -290,7 +311,7 @@ __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
     const PosInfo pi = a.pinfo[j];
     if (pi.ty < 0) return;
     const int l = threadIdx.x / 16, c = threadIdx.x % 16, y = blk * LINES256 + l;
-    build256<1>(tab, a, pi, blk * LINES256);
+    load256<1>(tab, P.tw, P.tab, j, blk * LINES256);
     float2 v[16], ph[16], ov[16], acc[16];
     rows_load(v, P.wave + (size_t)ch0 * N256 * N256, y, c);
     rows_load(ph, Slots<N256>(a, ch0).phi(P.s), y, c);

@@ -742,7 +742,7 @@ bool two_terms(const ptyr_geom& g) { return loss_terms(g).n > 1; }
 
 struct Layout {
     size_t Oc, Phat, pinfo, Imode, Ibuf, wbuf, lpart, scal, spart, pac, err, store, gO, gPhat, gPsum, part, gamp, gphase,
-        gprobe, gdz, gpos, gtilt, wave, cons, rzmat, kz, total;
+        gprobe, gdz, gpos, gtilt, wave, cons, rzmat, kz, total, tab256;
     int keep, ckK, nck, waves_per_chain;
 };
 
@@ -800,6 +800,7 @@ Layout make_layout(const ptyr_geom* g) {
     L.gpos = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
     L.gtilt = take((size_t)std::max(g->n_scan, 1) * 2 * sizeof(float));
     L.wave = take(g->N == 256 ? B * Mc * NN * sizeof(float2) : 0);
+    L.tab256 = take(g->N == 256 ? N256 * sizeof(float4) + B * sizeof(PosTab256) : 0);   // N = 256 pass factors
     // probe orthogonalisation: partial overlap sums (double complex), mixing
     // matrix (float complex), eigenvalues
     L.cons = take((size_t)ORTH_MAX_M * (ORTH_MAX_M + 1) / 2 * GRAM_MAX_CHUNKS * sizeof(cd) +
@@ -1097,9 +1098,16 @@ Pass256 pass256(ptyr_ctx* c, const WaveArgs& a, int s) {
     Pass256 P;
     P.a = a;
     P.wave = at<float2>(c, c->L.wave);
+    P.tw = at<float4>(c, c->L.tab256);
+    P.tab = reinterpret_cast<const PosTab256*>(at<float4>(c, c->L.tab256) + N256);
     P.s = s;
     P.mg = 1;
     return P;
+}
+// the passes' twiddles and per-position factors for the batch of a
+void tables256(ptyr_ctx* c, const WaveArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k256_tables, dim3(a.B), dim3(256), 0, st, a, at<float4>(c, c->L.tab256),
+                       reinterpret_cast<PosTab256*>(at<float4>(c, c->L.tab256) + N256));
 }
 // probe modes whose patch gradients the N = 256 gradient row pass sums per
 // workgroup: the largest divisor of the probe modes up to 8 (measured at the
@@ -1115,6 +1123,7 @@ void forward256(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
     TimedLaunch t(c, PTYR_K_FORWARD, st);
     a.chain0 = c0;
     const dim3 grid(nc * NBLK256), blk(256);
+    tables256(c, a, st);
     hipLaunchKernelGGL(k256_fwd_col, grid, blk, 0, st, pass256(c, a, -1));
     for (int s = 0; s < a.S; ++s) {
         hipLaunchKernelGGL(k256_fwd_row, grid, blk, 0, st, pass256(c, a, s));
@@ -1125,6 +1134,7 @@ void gradient256(ptyr_ctx* c, WaveArgs a, int c0, int nc, hipStream_t st) {
     TimedLaunch t(c, PTYR_K_GRADIENT, st);
     a.chain0 = c0;
     const dim3 grid(nc * NBLK256), blk(256);
+    tables256(c, a, st);
     hipLaunchKernelGGL(k256_grad_col, grid, blk, 0, st, pass256(c, a, a.S));
     // the row pass takes row_group(g) chains per workgroup (c0 and nc are
     // multiples of it: N = 256 batches are not split)
