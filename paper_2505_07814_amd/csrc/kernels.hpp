@@ -324,7 +324,7 @@ __device__ __forceinline__ void recompute_phi(float2 (&v)[16], int s, const Wave
 // tilt and dz gradients.
 template <int N, int KEEP>
 __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
-    constexpr int L = N / 16;
+    constexpr int L = N / 16, T = N * N / 16;
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ Tables<N> tab;
     int l, c;
@@ -386,6 +386,10 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
         }
         const float2* Os = chain_object(a, m) + (size_t)s * HW + (size_t)pi.ty * a.W + pi.tx;
         float2* go = a.gO + ((size_t)(j * a.M + m) * a.S + s) * N * N;
+        // The patch gradient is stored register-major (register r of thread t
+        // at r T + t, T threads: each store instruction writes one contiguous
+        // 512-byte run per wave; the scatter maps pixels to that order,
+        // measured 0.419 -> 0.406 ms per launch against row-major stores).
         // The reads run in two halves of 8 registers (32 VGPRs in flight),
         // each issued before any patch-gradient write that follows it: the
         // writes could alias the reads as far as the compiler knows, and one
@@ -415,10 +419,10 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
                 ov[r] = (Os + YC::dy(8 + r) * a.W)[oW];
             }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) (go + YC::dy(r) * N)[oN] = t0[r];
+            for (int r = 0; r < 8; ++r) go[r * T + threadIdx.x] = t0[r];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                (go + YC::dy(8 + r) * N)[oN] = cmulc(g[8 + r], ph[r]);
+                go[(8 + r) * T + threadIdx.x] = cmulc(g[8 + r], ph[r]);
                 g[8 + r] = cmulc(g[8 + r], ov[r]);
             }
         }

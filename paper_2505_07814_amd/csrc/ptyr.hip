@@ -388,6 +388,18 @@ struct ObjAdam {
                 // (added, then cleared); 0: they are zero (neither read nor written)
 };
 
+// Offset of patch pixel (py, px) in a stored patch gradient.  N = 256 (line
+// passes): row-major.  N = 64, 128: the fused gradient's register-major
+// order, register r of thread t at r T + t (T = N^2 / 16 threads).  There
+// thread t = 64 w + k + P c (line_of: wave w, P = 64 / L lines per wave,
+// L = N / 16 lanes per line) holds column x = P w + k, rows y = c + L r, so
+// pixel (y, x) sits at (y / L) T + 64 (x / P) + x mod P + P (y mod L).
+__device__ __forceinline__ size_t patch_offset(int py, int px, int N) {
+    if (N == 256) return (size_t)py * N + px;
+    const int lgL = N == 128 ? 3 : 2, lgP = 6 - lgL, T = N * N / 16;
+    return (size_t)(py >> lgL) * T + ((px >> lgP) << 6) + (px & ((1 << lgP) - 1)) + ((py & ((1 << lgL) - 1)) << lgP);
+}
+
 // Object gradient: each workgroup owns a 32 x 32 tile of one slice and sums,
 // in batch order, the patch gradients of every (position, mode) of batch rows
 // [j0, j1) covering it;
@@ -453,12 +465,12 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
             const bool live = jc < j1;
             const int px = x - pc.tx;
             const bool xin = live && px >= 0 && px < N;
-            const float2* src = gO + ((size_t)(jc * Mc + om + mc) * S + s) * NN + px;   // read only when xin
+            const float2* src = gO + ((size_t)(jc * Mc + om + mc) * S + s) * NN;   // read only when xin
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int py = yb + 8 * i - pc.ty;
                 const bool in = xin && py >= 0 && py < N;
-                buf[mm][i] = in ? src[(size_t)py * N] : make_float2(0.f, 0.f);
+                buf[mm][i] = in ? src[patch_offset(py, px, N)] : make_float2(0.f, 0.f);
             }
             if (live) advance();
         }
