@@ -77,7 +77,11 @@ def test_gradient_matches_oracle(net, B, n_pat, seed):
     net.sync()
     L_ref, g_ref = cn.gradients(layers, pats[nbr], target, bf16=True)
     g = gcnn.unpack_params(grad.cpu().numpy())
-    assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
+    # the loss is the MSE of outputs that agree to ~1e-3 relative L2 (a
+    # stored BF16 activation may round to the neighbouring value where the
+    # FP32 and FP64 sums straddle a rounding boundary), so it agrees to
+    # 2e-3 at most; 1e-4 is observed to hold with room (5e-5 at B = 3)
+    assert abs(loss.item() - L_ref) <= 1e-4 * L_ref
     for l, ((dW, db), (rW, rb)) in enumerate(zip(g, g_ref)):
         rw, rbias = rel(dW, rW), rel(db, rb)
         print(f"layer {l}: dW rel-L2 {rw:.2e}, db rel-L2 {rbias:.2e}")
