@@ -8,7 +8,10 @@
 // incident wave, Y_s = F[phi_s], is formed on the way.  Kept for the gradient
 // (when the memory budget allows): phi_s (space), Y_s (spectrum) and the
 // far field.  The gradient kernel then holds a single wave in registers and
-// streams those kept arrays element by element.
+// streams those kept arrays element by element.  Kept waves, checkpoints and
+// the recomputation scratch are written and read register-major (kstore /
+// kload: register r of thread t at r T + t), in whatever register layout the
+// wave has at that point, which the reading kernel knows.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -195,7 +198,7 @@ __device__ __forceinline__ void slice_step(float2 (&v)[16], const float2* Os, in
     transmit<N>(v, Os, W, ty, tx, l, c);
     fft2_from_col<N>(v, lds, t.tw, l, c);
     apply_h<N, false>(v, t, l, c);
-    if (spec) wstore<N, ROW, MID>(v, spec, N, l, c);
+    if (spec) kstore<N>(v, spec);
     ifft2_to_col<N>(v, lds, t.tw, l, c);
 }
 
@@ -270,22 +273,22 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
         // cannot wait for those (conditional) writes as well
 #pragma unroll
         for (int r = 0; r < 16; ++r) ov[r] = cmul(v[r], ov[r]);
-        if (full) wstore<N, COL, NAT>(v, sl.phi(s), N, l, c);
-        else if (ckpt && s % a.ckK == 0) wstore<N, COL, NAT>(v, sl.ckpt(s / a.ckK), N, l, c);
+        if (full) kstore<N>(v, sl.phi(s));
+        else if (ckpt && s % a.ckK == 0) kstore<N>(v, sl.ckpt(s / a.ckK));
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = ov[r];
         if (s + 1 < a.S - 1) load_patch<N>(ov, Ocm + (size_t)(s + 1) * HW, a.W, pi.ty, pi.tx, l, c);
         fft2_from_col<N>(v, lds, tab.tw, l, c);
         apply_h<N, false>(v, tab, l, c);
-        if (full) wstore<N, ROW, MID>(v, sl.spec(s + 1), N, l, c);
+        if (full) kstore<N>(v, sl.spec(s + 1));
         ifft2_to_col<N>(v, lds, tab.tw, l, c);
     }
     const int s = a.S - 1;
-    if (full) wstore<N, COL, NAT>(v, sl.phi(s), N, l, c);
-    else if (ckpt && s % a.ckK == 0) wstore<N, COL, NAT>(v, sl.ckpt(s / a.ckK), N, l, c);
+    if (full) kstore<N>(v, sl.phi(s));
+    else if (ckpt && s % a.ckK == 0) kstore<N>(v, sl.ckpt(s / a.ckK));
     transmit<N>(v, Ocm + (size_t)s * HW, a.W, pi.ty, pi.tx, l, c);
     fft2_from_col<N>(v, lds, tab.tw, l, c);
-    if (full) wstore<N, ROW, MID>(v, sl.far(), N, l, c);
+    if (full) kstore<N>(v, sl.far());
     // far field |F chi|^2 / N^2 (zero frequency at (0, 0); the mode sum shifts it)
     const float s2 = 1.0f / ((float)N * N);
     float iv[16];
@@ -305,7 +308,7 @@ __device__ __forceinline__ void recompute_phi(float2 (&v)[16], int s, const Wave
     int s0 = 0;
     if (a.ckK <= a.S) {
         s0 = s > 0 ? ((s - 1) / a.ckK) * a.ckK : 0;
-        wload<N, COL, NAT>(v, sl.ckpt(s0 / a.ckK), N, l, c);
+        kload<N>(v, sl.ckpt(s0 / a.ckK));
     } else {
         shift_probe<N>(v, chain_probe(a, m, N * N), lds, t, l, c);
     }
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
     float2 g[16];
     // far field: kept, or recomputed from phi_{S-1}
     if (KEEP == KEEP_FULL) {
-        wload<N, ROW, MID>(g, sl.far(), N, l, c);
+        kload<N>(g, sl.far());
     } else {
         recompute_phi<N>(g, a.S - 1, a, sl, m, pi.ty, pi.tx, sl.sc_spec(), lds, tab, l, c);
         transmit<N>(g, chain_object(a, m) + (size_t)(a.S - 1) * HW, a.W, pi.ty, pi.tx, l, c);
@@ -364,7 +367,6 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
 
     using YC = Lay<N, COL, NAT>;
     using YR = Lay<N, ROW, MID>;
-    const unsigned oN = YC::toff(l, c, N);
     const unsigned oW = YC::toff(l, c, a.W);
     const unsigned oM = YR::toff(l, c, N);
 
@@ -377,10 +379,10 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
             Y_s = s > 0 ? sl.spec(s) : nullptr;
         } else {
             // park G, recompute phi_s and Y'_s into the scratch, take G back
-            wstore<N, COL, NAT>(g, sl.sc_g(), N, l, c);
+            kstore<N>(g, sl.sc_g());
             recompute_phi<N>(g, s, a, sl, m, pi.ty, pi.tx, sl.sc_spec(), lds, tab, l, c);
-            wstore<N, COL, NAT>(g, sl.sc_phi(), N, l, c);
-            wload<N, COL, NAT>(g, sl.sc_g(), N, l, c);
+            kstore<N>(g, sl.sc_phi());
+            kload<N>(g, sl.sc_g());
             phi_s = sl.sc_phi();
             Y_s = sl.sc_spec();
         }
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
             float2 ph[8], ov[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                ph[r] = (phi_s + YC::dy(r) * N)[oN];
+                ph[r] = (phi_s + r * T)[threadIdx.x];
                 ov[r] = (Os + YC::dy(r) * a.W)[oW];
             }
 #pragma unroll
@@ -415,14 +417,14 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
             float2 ph[8], ov[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                ph[r] = (phi_s + YC::dy(8 + r) * N)[oN];
+                ph[r] = (phi_s + (8 + r) * T)[threadIdx.x];
                 ov[r] = (Os + YC::dy(8 + r) * a.W)[oW];
             }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) go[r * T + threadIdx.x] = t0[r];
+            for (int r = 0; r < 8; ++r) (go + r * T)[threadIdx.x] = t0[r];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                go[(8 + r) * T + threadIdx.x] = cmulc(g[8 + r], ph[r]);
+                (go + (8 + r) * T)[threadIdx.x] = cmulc(g[8 + r], ph[r]);
                 g[8 + r] = cmulc(g[8 + r], ov[r]);
             }
         }
@@ -447,7 +449,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
         asm volatile("" : "+v"(cc));
         float2 yv[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) yv[r] = (Y_s + YR::dx(r))[oM];
+        for (int r = 0; r < 16; ++r) yv[r] = (Y_s + r * T)[threadIdx.x];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const float2 y = yv[r];

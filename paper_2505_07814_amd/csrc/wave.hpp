@@ -258,6 +258,21 @@ __device__ __forceinline__ void wstore(const T (&v)[16], T* base, int stride, in
     for (int r = 0; r < 16; ++r) (base + (Y::dy(r) * stride + Y::dx(r)))[o] = v[r];
 }
 
+// A wave kept in device memory for the same workgroup geometry to read back
+// (the kept waves, checkpoints and scratch of the fused kernels): register r
+// of thread t at r T + t, T = N^2 / 16 threads, so every access instruction
+// moves one contiguous 512-byte run per wave whatever the register layout.
+template <int N, typename T> __device__ __forceinline__ void kstore(const T (&v)[16], T* base) {
+    constexpr int TT = N * N / 16;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) (base + r * TT)[threadIdx.x] = v[r];
+}
+template <int N, typename T> __device__ __forceinline__ void kload(T (&v)[16], const T* base) {
+    constexpr int TT = N * N / 16;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = (base + r * TT)[threadIdx.x];
+}
+
 // LDS slot of exchange element (line l, b, lane c') for line geometry GEO
 // (GEO::L lanes per line, paddings GEO::SB, GEO::SL)
 template <class GEO> __device__ __forceinline__ int slot_x(int l, int b, int c) {
