@@ -117,6 +117,19 @@ __device__ __forceinline__ void cols_store(const float2 (&v)[16], float2* w, int
     for (int r = 0; r < 16; ++r) w[(c + 16 * r) * N256 + x] = v[r];
 }
 
+// Kept waves (phi_s, Y_s, far field) are written and read by passes of the
+// same geometry, register-major per line block: register r of thread t of
+// block blk at blk 4096 + r 256 + t, so each access instruction moves one
+// contiguous 512-byte run per wave.
+__device__ __forceinline__ void keep_store(const float2 (&v)[16], float2* w, int blk) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) (w + blk * (LINES256 * N256) + r * 256)[threadIdx.x] = v[r];
+}
+__device__ __forceinline__ void keep_load(float2 (&v)[16], const float2* w, int blk) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = (w + blk * (LINES256 * N256) + r * 256)[threadIdx.x];
+}
+
 struct Pass256 {
     WaveArgs a;
     float2* wave;          // B x M x 256 x 256 working waves
@@ -153,8 +166,8 @@ __global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
     }
     mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                      // phi_s (space)
     const Slots<N256> sl(a, ch);
-    if (sl.base && a.keep == KEEP_FULL) rows_store(v, sl.phi(P.s), y, c);
-    else if (sl.base && a.ckK <= a.S && P.s % a.ckK == 0) rows_store(v, sl.ckpt(P.s / a.ckK), y, c);
+    if (sl.base && a.keep == KEEP_FULL) keep_store(v, sl.phi(P.s), blk);
+    else if (sl.base && a.ckK <= a.S && P.s % a.ckK == 0) keep_store(v, sl.ckpt(P.s / a.ckK), blk);
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], ov[r]);
     nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
@@ -201,11 +214,11 @@ __global__ __launch_bounds__(256) void k256_fwd_col(Pass256 P) {
         const float sc = 1.0f / ((float)N256 * N256);
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = cscale(tmul<false>(tmul<false>(v[r], tab.h[c + 16 * r]), hx), sc);
-        if (full) cols_store(v, sl.spec(P.s + 1), x, c);
+        if (full) keep_store(v, sl.spec(P.s + 1), blk);
         mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
         cols_store(v, w, x, c);
     } else {
-        if (full) cols_store(v, sl.far(), x, c);
+        if (full) keep_store(v, sl.far(), blk);
         const float s2 = 1.0f / ((float)N256 * N256);
 #pragma unroll
         for (int r = 0; r < 16; ++r) Iout[(c + 16 * r) * N256 + x] = cabs2(v[r]) * s2;
@@ -240,7 +253,7 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
     const float inv_n = 1.0f / N256, inv_n2 = 1.0f / ((float)N256 * N256);
     float2 v[16];
     if (P.s == a.S) {
-        cols_load(v, sl.far(), x, c);
+        keep_load(v, sl.far(), blk);
         const float* wj = a.wgt + (size_t)j * N256 * N256;
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = cscale(v[r], wj[(c + 16 * r) * N256 + x] * inv_n2);
@@ -251,7 +264,7 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
     }
     cols_load(v, w, x, c);
     float2 yv_[16];                      // Y'_s, read now so that its latency overlaps the DFT
-    if (P.s > 0) cols_load(yv_, sl.spec(P.s), x, c);
+    if (P.s > 0) keep_load(yv_, sl.spec(P.s), blk);
     nat2mid<ColGeo256, -1>(v, lds, tab.tw, l, c);                       // G^ (raw), (k_y, k_x)
     // partial sums in double (see k_gradient)
     const double dk = 1.0 / (N256 * a.dx);
@@ -314,7 +327,7 @@ __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
     load256<1>(tab, P.tw, P.tab, j, blk * LINES256);
     float2 v[16], ph[16], ov[16], acc[16];
     rows_load(v, P.wave + (size_t)ch0 * N256 * N256, y, c);
-    rows_load(ph, Slots<N256>(a, ch0).phi(P.s), y, c);
+    keep_load(ph, Slots<N256>(a, ch0).phi(P.s), blk);
     // the object patch (the same for the group's chains) and the first
     // chain's G and phi_s are read now, so that their latency overlaps the
     // line DFT
@@ -332,7 +345,7 @@ __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
             acc[r] = cadd(acc[r], cmulc(v[r], ph[r]));                  // conj(phi) G_chi
             v[r] = cmulc(v[r], ov[r]);                                  // conj(O) G_chi
         }
-        if (p + 1 < mg) rows_load(ph, Slots<N256>(a, ch + 1).phi(P.s), y, c);
+        if (p + 1 < mg) keep_load(ph, Slots<N256>(a, ch + 1).phi(P.s), blk);
         nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
         rows_store(v, P.wave + (size_t)ch * N256 * N256, y, c);
         if (p + 1 < mg) rows_load(v, P.wave + (size_t)(ch + 1) * N256 * N256, y, c);
