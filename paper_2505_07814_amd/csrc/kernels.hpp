@@ -240,7 +240,6 @@ template <int N> constexpr int fwd_lds_slots() {
 // wait for the object-patch reads would also wait for the writes.
 template <int N, int KEEP>
 __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
-    constexpr int L = N / 16;
     __shared__ float2 lds[fwd_lds_slots<N>()];
     __shared__ Tables<N> tab;
     int l, c;
@@ -327,7 +326,7 @@ __device__ __forceinline__ void recompute_phi(float2 (&v)[16], int s, const Wave
 // tilt and dz gradients.
 template <int N, int KEEP>
 __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
-    constexpr int L = N / 16, T = N * N / 16;
+    constexpr int T = N * N / 16;
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ Tables<N> tab;
     int l, c;
@@ -494,7 +493,6 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
 // by 1/N (orthonormal); the result is written to dst, or added to it (ACC).
 template <int N, int SG, bool ACC>
 __device__ __forceinline__ void fft2_block(const float2* src, float2* dst) {
-    constexpr int L = N / 16;
     __shared__ float2 lds[WaveGeo<N>::LDS_SLOTS];
     __shared__ float4 tw[N];
     int l, c;
