@@ -1475,22 +1475,25 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
             hipStreamWaitEvent(c->side, c->ev_mid, 0) != hipSuccess)
             return PTYR_E_DEVICE;
         if (g1 > 0) gradient_chains(c, a, 0, g1, c->stream);
-        if (hipEventRecord(c->ev_a1, c->stream) != hipSuccess) return PTYR_E_DEVICE;
         loss_rows(c, I_meas, idx, nm, rA, B - rA, 1, c->side);
         if (hipEventRecord(c->ev_loss, c->side) != hipSuccess ||
             hipStreamWaitEvent(c->stream, c->ev_loss, 0) != hipSuccess)
             return PTYR_E_DEVICE;
-        // side: the first range's remaining gradient chains, then (the batch
-        // factor needing both loss ranges, and the first gradient launch being
-        // done) the scatter of the first range's complete rows, which runs in
-        // the compute units the main stream's last gradient launch leaves free
+        // main: the batch factor (both loss ranges are done) after its first
+        // gradient launch, off the side stream's path to the scatter
+        loss_final(c, 2, B, loss_dev, c->stream, true);
+        if (hipEventRecord(c->ev_a1, c->stream) != hipSuccess) return PTYR_E_DEVICE;
+        // side: the first range's remaining gradient chains, then (the first
+        // gradient launch and the batch factor being done) the scatter of the
+        // first range's complete rows, which runs in the compute units the
+        // main stream's last gradient launch leaves free
         if (nA > g1) gradient_chains(c, a, g1, nA - g1, c->side);
-        if (hipStreamWaitEvent(c->side, c->ev_a1, 0) != hipSuccess) return PTYR_E_DEVICE;
-        loss_final(c, 2, B, loss_dev, c->side, true);
-        if (hipEventRecord(c->ev_sgrad, c->side) != hipSuccess) return PTYR_E_DEVICE;
+        if (hipEventRecord(c->ev_sgrad, c->side) != hipSuccess ||
+            hipStreamWaitEvent(c->side, c->ev_a1, 0) != hipSuccess)
+            return PTYR_E_DEVICE;
         scatter(0, rA, c->side, false);
         // main: the second range's gradient chains, then (with the side
-        // stream's chains and the batch factor done) the probe / parameter
+        // stream's chains done) the probe / parameter
         // reductions, which need every chain; the side stream meanwhile
         // scatters the remaining rows.  (The reductions' probe transform
         // needs whole compute units: issued first, on the stream that is
