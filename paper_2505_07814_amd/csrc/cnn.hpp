@@ -343,33 +343,64 @@ __global__ __launch_bounds__(256) void k_wreduce(const float* part, int nchunk, 
 // Input gradient of layer L (L >= 1) through the ReLU of layer L-1:
 //   Gprev[q][c] = bf16([X[q][c] > 0] sum_{tap, o} WT[c][tap * Cout_p + o] G[p_out(q, tap)][o])
 // where output pixel p_out = ((y + 1 - u) / s, (x + 1 - v) / s) when that is an
-// integer inside the output.  One wave per 16 input pixels and all channels.
+// integer inside the output.  One wave per 16 input pixels and all channels
+// (stride 2: 16 pixels of one parity class, see below).
 template <int L>
 __global__ __launch_bounds__(256) void k_dgrad(const __bf16* G, const __bf16* WT, const __bf16* X, __bf16* Gprev,
                                                int B) {
     constexpr int cinp = CINP[L], coutp = COUTP[L], s = STRIDE[L], hin = HIN[L], hout = HOUT[L], KD = kd(L);
     constexpr int MT = cinp / 16;
     const int lane = threadIdx.x % 64, g = lane / 16, n = lane % 16;
-    const int p0 = (blockIdx.x * 4 + threadIdx.x / 64) * 16;
-    if (p0 >= B * hin * hin) return;
-    const int q = p0 + n;
-    const int b = q / (hin * hin), yi = (q / hin) % hin, xi = q % hin;
+    const int wv = blockIdx.x * 4 + threadIdx.x / 64;
+    if (wv * 16 >= B * hin * hin) return;
+    int b, yi, xi;
     floatx4 acc[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) acc[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
-    for (int k0 = 0; k0 < KD; k0 += 32) {
-        const int kk = k0 + 8 * g;
-        bf16x8 bv = zero8();
-        if (kk < 9 * coutp) {
-            const int tap = kk / coutp, o0 = kk % coutp;
-            const int ty = yi + 1 - tap / 3, tx = xi + 1 - tap % 3;
-            if (ty >= 0 && tx >= 0 && ty % s == 0 && tx % s == 0 && ty / s < hout && tx / s < hout)
-                bv = ld8(G + (((size_t)b * hout + ty / s) * hout + tx / s) * coutp + o0);
-        }
+    if constexpr (s == 2) {
+        // A wave takes 16 input pixels of one row and one column parity
+        // (every other pixel of half a row): only the taps (u, v) with
+        // y + 1 - u and x + 1 - v even meet an output pixel, the same for all
+        // 16 (u = 1 for even rows, u = 0, 2 for odd ones; v likewise), so the
+        // reduction runs over those 1, 2 or 4 taps in increasing order (the
+        // other taps' products are zero) instead of all 9.
+        static_assert(coutp == 32, "one 32-wide reduction step per tap");
+        const int rem = wv % (hin * 4), px = (rem / 2) % 2, half = rem % 2;
+        b = wv / (hin * 4);
+        yi = rem / 4;
+        xi = 2 * (16 * half + n) + px;
+        const int u0 = (yi % 2 == 0) ? 1 : 0, du = (yi % 2 == 0) ? 3 : 2;   // u = 1, or u = 0, 2
+        const int v0 = px == 0 ? 1 : 0, dv = px == 0 ? 3 : 2;
+        for (int u = u0; u < 3; u += du)
+            for (int v = v0; v < 3; v += dv) {
+                const int tap = 3 * u + v, kk = tap * coutp + 8 * g;
+                const int ty = yi + 1 - u, tx = xi + 1 - v;
+                bf16x8 bv = zero8();
+                if (ty >= 0 && tx >= 0 && ty / 2 < hout && tx / 2 < hout)
+                    bv = ld8(G + (((size_t)b * hout + ty / 2) * hout + tx / 2) * coutp + 8 * g);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma(ld8(WT + (mt * 16 + n) * KD + kk), bv, acc[mt]);
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma(ld8(WT + (mt * 16 + n) * KD + kk), bv, acc[mt]);
+            }
+    } else {
+        const int q = wv * 16 + n;
+        b = q / (hin * hin);
+        yi = (q / hin) % hin;
+        xi = q % hin;
+#pragma unroll 3
+        for (int k0 = 0; k0 < KD; k0 += 32) {
+            const int kk = k0 + 8 * g;
+            bf16x8 bv = zero8();
+            if (kk < 9 * coutp) {
+                const int tap = kk / coutp, o0 = kk % coutp;
+                const int ty = yi + 1 - tap / 3, tx = xi + 1 - tap % 3;
+                if (ty >= 0 && tx >= 0 && ty % s == 0 && tx % s == 0 && ty / s < hout && tx / s < hout)
+                    bv = ld8(G + (((size_t)b * hout + ty / s) * hout + tx / s) * coutp + o0);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma(ld8(WT + (mt * 16 + n) * KD + kk), bv, acc[mt]);
+        }
     }
+    const int q = (b * hin + yi) * hin + xi;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const size_t o = (size_t)q * cinp + mt * 16 + 4 * g;
