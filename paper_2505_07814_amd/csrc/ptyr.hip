@@ -384,8 +384,11 @@ struct ObjAdam {
     float *amp, *phase;                     // the parameters (read, then updated in place)
     float *m_amp, *v_amp, *m_phase, *v_phase;
     float lr_amp, lr_phase, b1, b2, eps, bc1, bc2s;
-    int gin;    // 1: g_amp / g_phase hold an earlier scatter's sums of this step
-                // (added, then cleared); 0: they are zero (neither read nor written)
+    int gin;    // fused launch: 1 = rows [0, j0) were scattered first by an
+                // assigning launch, whose sums are read on the tiles those rows
+                // touch (nothing else of g_amp / g_phase is read or written)
+    int assign; // unfused launch: 1 = write the sums to the tiles the rows touch
+                // (the first scatter of a fused step), 0 = add them
 };
 
 // Offset of patch pixel (py, px) in a stored patch gradient.  N = 256 (line
@@ -410,9 +413,11 @@ __device__ __forceinline__ size_t patch_offset(int py, int px, int N) {
 // consecutive (position, mode) items are issued together before they are
 // added (in item order), to keep enough bytes in flight per workgroup.  FUSE: the
 // launch also takes every pixel's complete gradient (this sum, plus the
-// buffer's when an earlier scatter filled it, which is then cleared) through
-// Adam (ObjAdam), untouched tiles included.  MB: 8 when the probe modes come
-// in eights, else 4 (fewer registers, more resident workgroups).
+// buffer's on the tiles an earlier assigning scatter of rows [0, j0) wrote)
+// through Adam (ObjAdam), untouched tiles included; the buffers are never
+// cleared, as each step's first scatter writes before the fused one reads.
+// MB: 8 when the probe modes come in eights, else 4 (fewer registers, more
+// resident workgroups).
 template <bool FUSE, int SCATTER_MB>
 __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const PosInfo* pinfo, int j0, int j1, int M,
                                                         int Mc, int S, int N, int H, int W, const float* amp,
@@ -458,6 +463,13 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
         }
     };
     advance();
+    // FUSE with gin: whether the assigning scatter of rows [0, j0) wrote this tile
+    bool pre = false;
+    if (FUSE && ad.gin)
+        for (int j = 0; j < j0 && !pre; ++j) {
+            const int ty = pinfo[j].ty, tx = pinfo[j].tx;
+            pre = ty >= 0 && ty < y0 + 32 && ty + N > y0 && tx < x0 + 32 && tx + N > x0;
+        }
     while (jc < j1) {
         float2 buf[SCATTER_MB][4];
 #pragma unroll
@@ -498,23 +510,15 @@ __global__ __launch_bounds__(256) void k_scatter_object(const float2* gO, const 
             if (sp != 0.f) gp += sp * (float)cnt[i] * (ph > 0.f ? 1.f : (ph < 0.f ? -1.f : 0.f));
         }
         if constexpr (!FUSE) {
-            if (g_amp) g_amp[o] += ga;
-            if (g_phase) g_phase[o] += gp;
+            if (g_amp) g_amp[o] = ad.assign ? ga : g_amp[o] + ga;
+            if (g_phase) g_phase[o] = ad.assign ? gp : g_phase[o] + gp;
         } else {
             if (g_amp) {
-                float gi = ga;
-                if (ad.gin) {
-                    gi += g_amp[o];
-                    g_amp[o] = 0.f;
-                }
+                const float gi = pre ? ga + g_amp[o] : ga;
                 adam_elem(ad.amp[o], ad.m_amp[o], ad.v_amp[o], gi, ad.lr_amp, ad.b1, ad.b2, ad.eps, ad.bc1, ad.bc2s);
             }
             if (g_phase) {
-                float gi = gp;
-                if (ad.gin) {
-                    gi += g_phase[o];
-                    g_phase[o] = 0.f;
-                }
+                const float gi = pre ? gp + g_phase[o] : gp;
                 adam_elem(ad.phase[o], ad.m_phase[o], ad.v_phase[o], gi, ad.lr_phase, ad.b1, ad.b2, ad.eps, ad.bc1,
                           ad.bc2s);
             }
@@ -1421,12 +1425,15 @@ ptyr_status run_adjoint(ptyr_ctx* c, const float* amp, const float* phase, const
                 hipLaunchKernelGGL((k_scatter_object<true, 4>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, Mg, Mcg,
                                    g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ad, sp);
         } else if (j1 > j0) {
+            // the first scatter of a fused step writes its sums, any other adds them
+            ObjAdam ad{};
+            ad.assign = fuse && j0 == 0 ? 1 : 0;
             if (mb8)
                 hipLaunchKernelGGL((k_scatter_object<false, 8>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, Mg, Mcg,
-                                   g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
+                                   g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ad, sp);
             else
                 hipLaunchKernelGGL((k_scatter_object<false, 4>), grid, dim3(256), 0, st, gO, pinfo, j0, j1, Mg, Mcg,
-                                   g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ObjAdam{}, sp);
+                                   g.S, g.N, g.H, g.W, amp, phase, scale, g_amp, g_phase, ad, sp);
         }
     };
     // probe-spectrum sum and inverse transform, position / tilt / dz partials
@@ -1741,8 +1748,9 @@ ptyr_status ptyr_step(ptyr_ctx* c, ptyr_params* p, const int* idx, int B, const 
     // The six gradient buffers are consecutive in the workspace; they are
     // cleared once here and afterwards by each step's Adam as it reads them
     // (an interrupted step leaves them to be cleared again).  The object's two
-    // are only written by the first scatter of a two-stream batch, and read
-    // and cleared by its fused Adam; otherwise they stay zero.
+    // need no clearing: only the first scatter of a two-stream batch writes
+    // them (its sums, on the tiles its rows touch), and the fused Adam reads
+    // exactly those tiles.
     if (!c->step_grads_clear)
         zero(c, gamp, (size_t)(reinterpret_cast<char*>(at<float>(c, c->L.gtilt) + std::max(g.n_scan, 1) * 2) -
                                reinterpret_cast<char*>(gamp)) / sizeof(float));

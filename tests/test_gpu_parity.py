@@ -317,8 +317,8 @@ def test_step_split_batch_matches_adjoint_then_adam(which):
     """ptyr_step on a batch of more chains than compute units (two-stream
     schedule, the object's Adam fused into the batch's last scatter) equals
     ptyr_adjoint's gradients of the same batch followed by Adam in float64,
-    over two steps (the second also shows that the first left its gradient
-    buffers cleared).  The gradients are the same kernels' in the same order,
+    over two steps (the second also shows that no gradient sums of the first
+    leak into it).  The gradients are the same kernels' in the same order,
     so the parameters differ only by the float32 Adam arithmetic and the
     rounding of the updated parameter."""
     from paper_2505_07814_amd.ptyr import AdamState, Engine
