@@ -99,8 +99,12 @@ __global__ void k_check_distinct(const int* idx, int B, PosInfo* pinfo, int* err
 // transform the probe modes (long, one compute unit each), the others form
 // the transmission of every slice, and the first of them the positions, so
 // the transform overlaps the streaming pass instead of following it.
+// The transmission is formed four pixels at a time from 16-byte loads, two
+// quads per thread issued before either is stored, where the parameters are
+// 16-byte aligned (pixel by pixel otherwise, and for the tail).
 template <int N>
-__global__ __launch_bounds__(N * N / 16) void k_prepare(const float* amp, const float* phase, float2* Oc,
+__global__ __launch_bounds__(N * N / 16) void k_prepare(const float* __restrict__ amp,
+                                                        const float* __restrict__ phase, float2* __restrict__ Oc,
                                                         size_t nobj, const float* pos, const int* idx, int n_rows,
                                                         int B, int H, int W, PosInfo* pinfo, int* err,
                                                         const float2* probe, float2* Phat, int M, int distinct) {
@@ -113,7 +117,32 @@ __global__ __launch_bounds__(N * N / 16) void k_prepare(const float* amp, const 
     if (b == M)
         for (int j = threadIdx.x; j < B; j += blockDim.x)
             position_info(j, pos, idx, n_rows, N, H, W, pinfo, err, distinct);
-    for (size_t i = (size_t)(b - M) * blockDim.x + threadIdx.x; i < nobj; i += (size_t)nb * blockDim.x) {
+    const size_t t0 = (size_t)(b - M) * blockDim.x + threadIdx.x, stride = (size_t)nb * blockDim.x;
+    size_t done = 0;
+    if (((reinterpret_cast<uintptr_t>(amp) | reinterpret_cast<uintptr_t>(phase)) & 15) == 0) {
+        const float4* a4 = reinterpret_cast<const float4*>(amp);
+        const float4* p4 = reinterpret_cast<const float4*>(phase);
+        float4* o4 = reinterpret_cast<float4*>(Oc);      // the workspace is 256-byte aligned
+        const size_t nq = nobj / 4;
+        auto quad = [&](size_t q, const float4& a, const float4& ph) {
+            float s0, c0, s1, c1, s2, c2, s3, c3;
+            sincosf(ph.x, &s0, &c0);
+            sincosf(ph.y, &s1, &c1);
+            sincosf(ph.z, &s2, &c2);
+            sincosf(ph.w, &s3, &c3);
+            o4[2 * q] = make_float4(a.x * c0, a.x * s0, a.y * c1, a.y * s1);
+            o4[2 * q + 1] = make_float4(a.z * c2, a.z * s2, a.w * c3, a.w * s3);
+        };
+        for (size_t q = t0; q < nq; q += 2 * stride) {
+            const bool two = q + stride < nq;
+            const float4 a = a4[q], ph = p4[q];
+            const float4 a1 = two ? a4[q + stride] : a, ph1 = two ? p4[q + stride] : ph;
+            quad(q, a, ph);
+            if (two) quad(q + stride, a1, ph1);
+        }
+        done = nq * 4;
+    }
+    for (size_t i = done + t0; i < nobj; i += stride) {
         float s, c;
         sincosf(phase[i], &s, &c);
         const float a = amp[i];

@@ -87,6 +87,30 @@ def test_forward_parity_small(N, S, M, B, seed):
     assert e < 1e-5
 
 
+def test_forward_unaligned_object_matches_aligned():
+    """The transmission pass takes 16-byte aligned parameters four pixels at a
+    time and others pixel by pixel: an object passed as views 4 bytes into
+    larger buffers (and a pixel count that is not a multiple of 4) gives
+    bitwise the patterns of the aligned call."""
+    print("forward unaligned object N=64 S=3", flush=True)
+    c = Case(small(64, 3, 2, 5, 2), perturb=False)
+    assert c.amp.size % 4 != 0
+    eng = c.engine()
+    args = c.gpu_args()
+    I0 = eng.forward(*args).clone()
+    views = []
+    for a in args[:2]:
+        buf = torch.zeros(a.numel() + 1, dtype=a.dtype, device=DEV)
+        v = buf[1:].view(a.shape)
+        v.copy_(a)
+        assert v.data_ptr() % 16 != 0
+        views.append(v)
+    I1 = eng.forward(*views, *args[2:])
+    eng.sync()
+    assert torch.equal(I0, I1)
+    assert rel(I1.cpu().numpy(), c.I_true) < 1e-5
+
+
 def test_forward_parity_single_slice_64():
     print("forward single_slice_64", flush=True)
     c = Case(synth.workload("single_slice_64"), perturb=False)
