@@ -50,11 +50,12 @@ def fft_flops(N):
 def line_pass_bytes(w, B, n_obj=1):
     """Algorithmic HBM bytes per step of the N=256 line passes (one wave =
     N*N complex64).  Forward, per chain: shifted probe (read the spectrum,
-    write the wave) 2 waves; per slice a row pass (read wave, keep phi, write
-    wave) and a column pass (read wave, keep Y, write wave) 6 waves, the last
-    column pass writing the far field and the mode intensity instead (2.5);
-    so 6S + 1.5 waves.  Gradient, per chain: 6S + 1.5 waves (the column pass
-    also reads Y, the row pass reads phi), plus the patch gradients, which the
+    write Z_0, the wave entering slice 0's row pass) 2 waves; per slice a row
+    pass (read Z_s, write the wave) and a column pass (read the wave, write
+    the kept Z_{s+1}) 4 waves, the last column pass writing the far field and
+    the mode intensity instead (2.5); so 4S + 2.5 waves.  Gradient, per chain:
+    6S + 1.5 waves (the column pass also reads Z_s to rebuild Y_s, the row
+    pass reads Z_s to rebuild phi_s), plus the patch gradients, which the
     row pass sums over groups of mg probe modes (mg = the largest divisor of
     the probe modes up to 8) and writes once per group: S / mg waves per
     chain.  Object patches are read once per batch row, slice and
@@ -64,7 +65,7 @@ def line_pass_bytes(w, B, n_obj=1):
     chains = B * w.M * n_obj
     patches = B * w.S * wave * n_obj
     mg = max(d for d in range(1, 9) if w.M % d == 0)
-    return {"forward": chains * (6 * w.S + 1.5) * wave + patches,
+    return {"forward": chains * (4 * w.S + 2.5) * wave + patches,
             "gradient": chains * (6 * w.S + w.S / mg + 1.5) * wave + patches}
 
 

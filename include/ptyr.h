@@ -157,7 +157,8 @@ size_t ptyr_workspace_bytes(const ptyr_geom* g);
 /* Pure host: how the forward keeps waves for the gradient under
  * g->wave_budget_bytes, counted in N x N complex64 waves per (row, mode)
  * chain of a B_max batch.  *stride = 1: all 2S waves of a chain are kept
- * (incident wave and its spectrum per slice, far field).  Otherwise three
+ * (incident wave and its spectrum per slice, far field; at N = 256 S + 1:
+ * the wave entering each slice's row pass, far field).  Otherwise three
  * waves per chain are scratch for recomputation and the incident wave is
  * kept every *stride >= 2 slices; *stride = S+1: none is kept and the
  * gradient recomputes from the probe (O(S^2) slice steps). */

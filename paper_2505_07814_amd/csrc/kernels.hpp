@@ -72,13 +72,14 @@ template <int N> struct Slots {
     float2* base;
     int S, nck;
     __device__ Slots(const WaveArgs& a, int chain) : S(a.S), nck(a.nck) {
-        const int per = a.keep == KEEP_FULL ? 2 * a.S : a.nck + 3;
+        const int per = a.keep == KEEP_FULL ? (N == 256 ? a.S + 1 : 2 * a.S) : a.nck + 3;
         base = a.store ? a.store + (size_t)chain * per * (N * N) : nullptr;
     }
-    // FULL: [phi_0 .. phi_{S-1}] [Y_1 .. Y_{S-1}] [far field]
+    // FULL: [phi_0 .. phi_{S-1}] [Y_1 .. Y_{S-1}] [far field]; N = 256:
+    // [Z_0 .. Z_{S-1}] [far field], Z_s the wave entering slice s's row pass
     __device__ float2* phi(int s) const { return base + (size_t)s * N * N; }
     __device__ float2* spec(int s) const { return base + (size_t)(S + s - 1) * N * N; }
-    __device__ float2* far() const { return base + (size_t)(2 * S - 1) * N * N; }
+    __device__ float2* far() const { return base + (size_t)(N == 256 ? S : 2 * S - 1) * N * N; }
     // CKPT: [checkpoints 0 .. nck-1] [scratch phi] [scratch Y] [scratch G]
     __device__ float2* ckpt(int k) const { return base + (size_t)k * N * N; }
     __device__ float2* sc_phi() const { return base + (size_t)nck * N * N; }

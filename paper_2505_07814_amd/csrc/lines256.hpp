@@ -4,9 +4,17 @@
 // stays in device memory (L2 / Infinity Cache resident for the batch) and
 // each slice is two line passes over all (row, mode) chains of the batch:
 //
-//   row pass    : inverse DFT along x, keep phi_s, transmit by O_s, DFT along x
-//   column pass : DFT along y (full 2-D spectrum), multiply by H, keep Y_s,
-//                 inverse DFT along y
+//   row pass    : inverse DFT along x (phi_s), transmit by O_s, DFT along x
+//   column pass : DFT along y (full 2-D spectrum), multiply by H, inverse DFT
+//                 along y
+//
+// The wave between a column pass and the next row pass, Z_s (y, k_x), is the
+// one wave kept per slice: the column pass writes it into slice s's slot of
+// the store and the row pass reads it from there.  The gradient rebuilds from
+// it both phi_s (the row pass's inverse along x, bitwise the forward's) and
+// the spectrum Y_s (a DFT along y), so the forward moves four waves per slice
+// instead of six (no separate phi_s and Y_s stores) at the price of one line
+// DFT more in each gradient pass.
 //
 // A workgroup transforms 16 lines of 256 points with the register / LDS line
 // machinery of wave.hpp (16 lanes per line, 16 values per lane).  Row passes
@@ -153,8 +161,10 @@ __global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
     const int l = threadIdx.x / 16, c = threadIdx.x % 16, y = blk * LINES256 + l;
     load256<1>(tab, P.tw, P.tab, j, blk * LINES256);
     float2* w = P.wave + (size_t)ch * N256 * N256;
+    const Slots<N256> sl(a, ch);
+    const bool full = sl.base && a.keep == KEEP_FULL;
     float2 v[16], ov[16];
-    rows_load(v, w, y, c);
+    rows_load(v, full ? sl.phi(P.s) : w, y, c);
     // the object patch is read now, so that its latency overlaps the line DFT
     // (three workgroups per CU by LDS leave room for the extra registers)
     const float2* Os = chain_object(a, ch % a.M) + (size_t)P.s * a.H * a.W + (size_t)(pi.ty + y) * a.W + pi.tx;
@@ -165,9 +175,6 @@ __global__ __launch_bounds__(256) void k256_fwd_row(Pass256 P) {
         for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], tab.r[c + 16 * r]);
     }
     mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                      // phi_s (space)
-    const Slots<N256> sl(a, ch);
-    if (sl.base && a.keep == KEEP_FULL) keep_store(v, sl.phi(P.s), blk);
-    else if (sl.base && a.ckK <= a.S && P.s % a.ckK == 0) keep_store(v, sl.ckpt(P.s / a.ckK), blk);
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], ov[r]);
     nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
@@ -195,6 +202,8 @@ __global__ __launch_bounds__(256) void k256_fwd_col(Pass256 P) {
     }
     load256<0>(tab, P.tw, P.tab, j, blk * LINES256);
     float2* w = P.wave + (size_t)ch * N256 * N256;
+    const Slots<N256> sl(a, ch);
+    const bool full = sl.base && a.keep == KEEP_FULL;
     float2 v[16];
     if (P.s < 0) {
         cols_load(v, chain_probe(a, m, N256 * N256), x, c);
@@ -202,21 +211,18 @@ __global__ __launch_bounds__(256) void k256_fwd_col(Pass256 P) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = cscale(cmul(v[r], tab.r[c + 16 * r]), sc);
         mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
-        cols_store(v, w, x, c);
+        cols_store(v, full ? sl.phi(0) : w, x, c);                      // Z_0
         return;
     }
     cols_load(v, w, x, c);
     nat2mid<ColGeo256, -1>(v, lds, tab.tw, l, c);                       // full 2-D spectrum (raw)
-    const Slots<N256> sl(a, ch);
-    const bool full = sl.base && a.keep == KEEP_FULL;
     if (P.s < a.S - 1) {
         const float4 hx = tab.hl[l];
         const float sc = 1.0f / ((float)N256 * N256);
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = cscale(tmul<false>(tmul<false>(v[r], tab.h[c + 16 * r]), hx), sc);
-        if (full) keep_store(v, sl.spec(P.s + 1), blk);
         mid2nat<ColGeo256, +1>(v, lds, tab.tw, l, c);
-        cols_store(v, w, x, c);
+        cols_store(v, full ? sl.phi(P.s + 1) : w, x, c);                 // Z_{s+1}
     } else {
         if (full) keep_store(v, sl.far(), blk);
         const float s2 = 1.0f / ((float)N256 * N256);
@@ -263,9 +269,15 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
         return;
     }
     cols_load(v, w, x, c);
-    float2 yv_[16];                      // Y'_s, read now so that its latency overlaps the DFT
-    if (P.s > 0) keep_load(yv_, sl.spec(P.s), blk);
+    float2 yv_[16];                      // Z_s, read now so that its latency overlaps the DFT
+    if (P.s > 0) cols_load(yv_, sl.phi(P.s), x, c);
     nat2mid<ColGeo256, -1>(v, lds, tab.tw, l, c);                       // G^ (raw), (k_y, k_x)
+    if (P.s > 0) {
+        // Y'_s = F_y[Z_s] / N: the forward's inverse along y undone (1/N is exact)
+        nat2mid<ColGeo256, -1>(yv_, lds, tab.tw, l, c);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) yv_[r] = cscale(yv_[r], inv_n);
+    }
     // partial sums in double (see k_gradient)
     const double dk = 1.0 / (N256 * a.dx);
     const double kx = sfreq<N256>(x) * dk, kx2 = kx * kx;
@@ -309,7 +321,8 @@ __global__ __launch_bounds__(256) void k256_grad_col(Pass256 P) {
 // Gradient row pass of slice s for P.mg consecutive chains of one position
 // and object mode (probe modes p0 .. p0 + mg - 1): per chain the wave holds
 // (y, k_x) of G after the inverse along y; the inverse along x gives
-// G_chi_s, the group's patch gradient sum_p conj(phi_s) G_chi (in probe-mode
+// G_chi_s, phi_s is rebuilt from the kept Z_s as the forward row pass formed
+// it, the group's patch gradient sum_p conj(phi_s) G_chi (in probe-mode
 // order) is summed in registers, and G_phi = conj(O_s) G_chi is transformed
 // along x.  The object patch is read once for the group and the summed patch
 // gradient written once, mg times less patch-gradient traffic (written here,
@@ -327,7 +340,7 @@ __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
     load256<1>(tab, P.tw, P.tab, j, blk * LINES256);
     float2 v[16], ph[16], ov[16], acc[16];
     rows_load(v, P.wave + (size_t)ch0 * N256 * N256, y, c);
-    keep_load(ph, Slots<N256>(a, ch0).phi(P.s), blk);
+    rows_load(ph, Slots<N256>(a, ch0).phi(P.s), y, c);
     // the object patch (the same for the group's chains) and the first
     // chain's G and phi_s are read now, so that their latency overlaps the
     // line DFT
@@ -339,13 +352,18 @@ __global__ __launch_bounds__(256) void k256_grad_row(Pass256 P) {
     }
     for (int p = 0; p < mg; ++p) {
         const int ch = ch0 + p;
+        if (P.s == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) ph[r] = cmul(ph[r], tab.r[c + 16 * r]);
+        }
+        mid2nat<RowGeo256, +1>(ph, lds, tab.tw, l, c);                 // phi_s (space)
         mid2nat<RowGeo256, +1>(v, lds, tab.tw, l, c);                  // G_chi_s (space)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             acc[r] = cadd(acc[r], cmulc(v[r], ph[r]));                  // conj(phi) G_chi
             v[r] = cmulc(v[r], ov[r]);                                  // conj(O) G_chi
         }
-        if (p + 1 < mg) keep_load(ph, Slots<N256>(a, ch + 1).phi(P.s), blk);
+        if (p + 1 < mg) rows_load(ph, Slots<N256>(a, ch + 1).phi(P.s), y, c);
         nat2mid<RowGeo256, -1>(v, lds, tab.tw, l, c);
         rows_store(v, P.wave + (size_t)ch * N256 * N256, y, c);
         if (p + 1 < mg) rows_load(v, P.wave + (size_t)(ch + 1) * N256 * N256, y, c);

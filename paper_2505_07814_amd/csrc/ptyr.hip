@@ -791,14 +791,19 @@ struct Layout {
     int keep, ckK, nck, waves_per_chain;
 };
 
+// Waves per chain that keep everything the gradient reads: 2S (phi_s, Y_s,
+// far field) for the fused kernels, S + 1 for the N = 256 line passes (the
+// wave entering each slice's row pass, far field).
+size_t full_waves(const ptyr_geom* g) { return g->N == 256 ? (size_t)g->S + 1 : 2 * (size_t)g->S; }
+
 // How the forward keeps waves under the budget (in waves of N x N complex
-// per chain, B_max * M chains): all 2S (phi_s, Y_s, far field) -> stride 1;
+// per chain, B_max * M chains): all of them (full_waves) -> stride 1;
 // else a 3-wave scratch plus checkpoints of phi every K >= 2 slices; with no
 // room for a checkpoint, K = S + 1 (recompute from the probe).
 void keep_plan(const ptyr_geom* g, int* keep, int* K, int* nck) {
     size_t per = (size_t)g->B_max * chain_modes(*g) * g->N * g->N * sizeof(float2);
     size_t fit = g->wave_budget_bytes / per;
-    if (fit >= (size_t)(2 * g->S)) { *keep = KEEP_FULL; *K = 1; *nck = 0; return; }
+    if (fit >= full_waves(g)) { *keep = KEEP_FULL; *K = 1; *nck = 0; return; }
     *keep = KEEP_CKPT;
     size_t avail = fit > 3 ? fit - 3 : 0;
     if (avail == 0) { *K = g->S + 1; *nck = 0; return; }
@@ -819,7 +824,7 @@ Layout make_layout(const ptyr_geom* g) {
     const size_t NN = (size_t)g->N * g->N, HW = (size_t)g->H * g->W, B = g->B_max, M = g->M, S = g->S;
     const size_t Mc = chain_modes(*g), OS = obj_modes(*g) * S;     // chain modes; object slices of all modes
     keep_plan(g, &L.keep, &L.ckK, &L.nck);
-    L.waves_per_chain = L.keep == KEEP_FULL ? 2 * g->S : L.nck + 3;
+    L.waves_per_chain = L.keep == KEEP_FULL ? (int)full_waves(g) : L.nck + 3;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     L.Oc = take(OS * HW * sizeof(float2));
