@@ -29,14 +29,48 @@ __global__ void k_zero(float* p, size_t n) {
         p[i] = 0.f;
 }
 
-// O = a exp(i phase) for the whole object (accurate sincos)
-__global__ void k_transmission(const float* amp, const float* phase, float2* Oc, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+// O = a exp(i phase) (accurate sincos) for the n pixels, thread t0 of
+// `stride` taking every stride-th one: four pixels at a time from 16-byte
+// loads, two quads per thread issued before either is stored, where the
+// parameters are 16-byte aligned (Oc is: the workspace is 256-byte aligned);
+// pixel by pixel otherwise, and for the tail.
+__device__ __forceinline__ void transmission(const float* __restrict__ amp, const float* __restrict__ phase,
+                                             float2* __restrict__ Oc, size_t n, size_t t0, size_t stride) {
+    size_t done = 0;
+    if (((reinterpret_cast<uintptr_t>(amp) | reinterpret_cast<uintptr_t>(phase)) & 15) == 0) {
+        const float4* a4 = reinterpret_cast<const float4*>(amp);
+        const float4* p4 = reinterpret_cast<const float4*>(phase);
+        float4* o4 = reinterpret_cast<float4*>(Oc);
+        const size_t nq = n / 4;
+        auto quad = [&](size_t q, const float4& a, const float4& ph) {
+            float s0, c0, s1, c1, s2, c2, s3, c3;
+            sincosf(ph.x, &s0, &c0);
+            sincosf(ph.y, &s1, &c1);
+            sincosf(ph.z, &s2, &c2);
+            sincosf(ph.w, &s3, &c3);
+            o4[2 * q] = make_float4(a.x * c0, a.x * s0, a.y * c1, a.y * s1);
+            o4[2 * q + 1] = make_float4(a.z * c2, a.z * s2, a.w * c3, a.w * s3);
+        };
+        for (size_t q = t0; q < nq; q += 2 * stride) {
+            const bool two = q + stride < nq;
+            const float4 a = a4[q], ph = p4[q];
+            const float4 a1 = two ? a4[q + stride] : a, ph1 = two ? p4[q + stride] : ph;
+            quad(q, a, ph);
+            if (two) quad(q + stride, a1, ph1);
+        }
+        done = nq * 4;
+    }
+    for (size_t i = done + t0; i < n; i += stride) {
         float s, c;
         sincosf(phase[i], &s, &c);
-        float a = amp[i];
+        const float a = amp[i];
         Oc[i] = make_float2(a * c, a * s);
     }
+}
+
+// O = a exp(i phase) for the whole object
+__global__ void k_transmission(const float* amp, const float* phase, float2* Oc, size_t n) {
+    transmission(amp, phase, Oc, n, blockIdx.x * (size_t)blockDim.x + threadIdx.x, (size_t)gridDim.x * blockDim.x);
 }
 
 // true when batch row j repeats the row of an earlier batch row (a gradient
@@ -99,13 +133,8 @@ __global__ void k_check_distinct(const int* idx, int B, PosInfo* pinfo, int* err
 // transform the probe modes (long, one compute unit each), the others form
 // the transmission of every slice, and the first of them the positions, so
 // the transform overlaps the streaming pass instead of following it.
-// The transmission is formed four pixels at a time from 16-byte loads, two
-// quads per thread issued before either is stored, where the parameters are
-// 16-byte aligned (pixel by pixel otherwise, and for the tail).
 template <int N>
-__global__ __launch_bounds__(N * N / 16) void k_prepare(const float* __restrict__ amp,
-                                                        const float* __restrict__ phase, float2* __restrict__ Oc,
-                                                        size_t nobj, const float* pos, const int* idx, int n_rows,
+__global__ __launch_bounds__(N * N / 16) void k_prepare(const float* amp, const float* phase, float2* Oc, size_t nobj, const float* pos, const int* idx, int n_rows,
                                                         int B, int H, int W, PosInfo* pinfo, int* err,
                                                         const float2* probe, float2* Phat, int M, int distinct) {
     const int b = blockIdx.x;
@@ -117,37 +146,7 @@ __global__ __launch_bounds__(N * N / 16) void k_prepare(const float* __restrict_
     if (b == M)
         for (int j = threadIdx.x; j < B; j += blockDim.x)
             position_info(j, pos, idx, n_rows, N, H, W, pinfo, err, distinct);
-    const size_t t0 = (size_t)(b - M) * blockDim.x + threadIdx.x, stride = (size_t)nb * blockDim.x;
-    size_t done = 0;
-    if (((reinterpret_cast<uintptr_t>(amp) | reinterpret_cast<uintptr_t>(phase)) & 15) == 0) {
-        const float4* a4 = reinterpret_cast<const float4*>(amp);
-        const float4* p4 = reinterpret_cast<const float4*>(phase);
-        float4* o4 = reinterpret_cast<float4*>(Oc);      // the workspace is 256-byte aligned
-        const size_t nq = nobj / 4;
-        auto quad = [&](size_t q, const float4& a, const float4& ph) {
-            float s0, c0, s1, c1, s2, c2, s3, c3;
-            sincosf(ph.x, &s0, &c0);
-            sincosf(ph.y, &s1, &c1);
-            sincosf(ph.z, &s2, &c2);
-            sincosf(ph.w, &s3, &c3);
-            o4[2 * q] = make_float4(a.x * c0, a.x * s0, a.y * c1, a.y * s1);
-            o4[2 * q + 1] = make_float4(a.z * c2, a.z * s2, a.w * c3, a.w * s3);
-        };
-        for (size_t q = t0; q < nq; q += 2 * stride) {
-            const bool two = q + stride < nq;
-            const float4 a = a4[q], ph = p4[q];
-            const float4 a1 = two ? a4[q + stride] : a, ph1 = two ? p4[q + stride] : ph;
-            quad(q, a, ph);
-            if (two) quad(q + stride, a1, ph1);
-        }
-        done = nq * 4;
-    }
-    for (size_t i = done + t0; i < nobj; i += stride) {
-        float s, c;
-        sincosf(phase[i], &s, &c);
-        const float a = amp[i];
-        Oc[i] = make_float2(a * c, a * s);
-    }
+    transmission(amp, phase, Oc, nobj, (size_t)(b - M) * blockDim.x + threadIdx.x, (size_t)nb * blockDim.x);
 }
 
 // fftshift index of an N x N array (its own inverse for even N)
@@ -1237,7 +1236,7 @@ void prepare_forward(ptyr_ctx* c, const float* amp, const float* phase, const fl
     if (g.N == 64) launch_prepare<64>(c, amp, phase, probe, pos, idx, n_rows, B, nobj, st, distinct);
     else if (g.N == 128) launch_prepare<128>(c, amp, phase, probe, pos, idx, n_rows, B, nobj, st, distinct);
     else {
-        hipLaunchKernelGGL(k_transmission, dim3(grid_for(nobj)), dim3(256), 0, st, amp, phase,
+        hipLaunchKernelGGL(k_transmission, dim3(grid_for((nobj + 7) / 8)), dim3(256), 0, st, amp, phase,
                            at<float2>(c, c->L.Oc), nobj);
         hipLaunchKernelGGL(k_positions, dim3((B + 63) / 64), dim3(64), 0, st, pos, idx, idx ? n_rows : B, B, g.N,
                            g.H, g.W, at<PosInfo>(c, c->L.pinfo), at<int>(c, c->L.err), distinct);
