@@ -269,19 +269,32 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     float2 ov[16];
     if (a.S > 1) load_patch<N>(ov, Ocm, a.W, pi.ty, pi.tx, l, c);
     for (int s = 0; s < a.S - 1; ++s) {
-        // chi_s is formed before phi_s is written: waiting for the patch then
-        // cannot wait for those (conditional) writes as well
+        // chi_s is formed in ov before phi_s is written: waiting for the patch
+        // then cannot wait for those (conditional) writes as well.  v keeps
+        // phi_s while ov is transformed, and each kept wave is written in two
+        // halves around a line pass, so that a wave's writes do not queue up
+        // all at once behind those of the other waves.
 #pragma unroll
         for (int r = 0; r < 16; ++r) ov[r] = cmul(v[r], ov[r]);
-        if (full) kstore<N>(v, sl.phi(s));
+        if (full) kstore_half<N, 0>(v, sl.phi(s));
         else if (ckpt && s % a.ckK == 0) kstore<N>(v, sl.ckpt(s / a.ckK));
+        __builtin_amdgcn_sched_barrier(0);
+        nat2mid<WaveGeo<N>, -1>(ov, lds, tab.tw, l, c);
+        __builtin_amdgcn_sched_barrier(0);
+        if (full) kstore_half<N, 1>(v, sl.phi(s));
+        relayout<N, COL, MID, ROW, NAT>(ov, lds, l, c);
+        nat2mid<WaveGeo<N>, -1>(ov, lds, tab.tw, l, c);
+        apply_h<N, false>(ov, tab, l, c);
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = ov[r];
+        if (full) kstore_half<N, 0>(ov, sl.spec(s + 1));
+        __builtin_amdgcn_sched_barrier(0);
+        mid2nat<WaveGeo<N>, +1>(v, lds, tab.tw, l, c);
+        __builtin_amdgcn_sched_barrier(0);
+        if (full) kstore_half<N, 1>(ov, sl.spec(s + 1));
+        relayout<N, ROW, NAT, COL, MID>(v, lds, l, c);
         if (s + 1 < a.S - 1) load_patch<N>(ov, Ocm + (size_t)(s + 1) * HW, a.W, pi.ty, pi.tx, l, c);
-        fft2_from_col<N>(v, lds, tab.tw, l, c);
-        apply_h<N, false>(v, tab, l, c);
-        if (full) kstore<N>(v, sl.spec(s + 1));
-        ifft2_to_col<N>(v, lds, tab.tw, l, c);
+        mid2nat<WaveGeo<N>, +1>(v, lds, tab.tw, l, c);
     }
     const int s = a.S - 1;
     if (full) kstore<N>(v, sl.phi(s));

@@ -267,6 +267,12 @@ template <int N, typename T> __device__ __forceinline__ void kstore(const T (&v)
 #pragma unroll
     for (int r = 0; r < 16; ++r) (base + r * TT)[threadIdx.x] = v[r];
 }
+// registers 8 H .. 8 H + 7 only
+template <int N, int H, typename T> __device__ __forceinline__ void kstore_half(const T (&v)[16], T* base) {
+    constexpr int TT = N * N / 16;
+#pragma unroll
+    for (int r = 8 * H; r < 8 * H + 8; ++r) (base + r * TT)[threadIdx.x] = v[r];
+}
 template <int N, typename T> __device__ __forceinline__ void kload(T (&v)[16], const T* base) {
     constexpr int TT = N * N / 16;
 #pragma unroll
