@@ -434,14 +434,20 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
                 ov[r] = (Os + YC::dy(8 + r) * a.W)[oW];
             }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) (go + r * T)[threadIdx.x] = t0[r];
-#pragma unroll
             for (int r = 0; r < 8; ++r) {
                 (go + (8 + r) * T)[threadIdx.x] = cmulc(g[8 + r], ph[r]);
                 g[8 + r] = cmulc(g[8 + r], ov[r]);
             }
         }
-        fft2_from_col<N>(g, lds, tab.tw, l, c);                               // G^ = F_raw G_phi
+        // G^ = F_raw G_phi; half 0's patch gradient is written after the first
+        // line pass, so that the chain's writes come in two spaced halves
+        __builtin_amdgcn_sched_barrier(0);
+        nat2mid<WaveGeo<N>, -1>(g, lds, tab.tw, l, c);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) (go + r * T)[threadIdx.x] = t0[r];
+        relayout<N, COL, MID, ROW, NAT>(g, lds, l, c);
+        nat2mid<WaveGeo<N>, -1>(g, lds, tab.tw, l, c);
         return Y_s;
     };
 
