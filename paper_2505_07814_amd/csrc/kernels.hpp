@@ -271,19 +271,26 @@ __global__ __launch_bounds__(N * N / 16) void k_forward(WaveArgs a) {
     for (int s = 0; s < a.S - 1; ++s) {
         // chi_s is formed in ov before phi_s is written: waiting for the patch
         // then cannot wait for those (conditional) writes as well.  v keeps
-        // phi_s while ov is transformed, and each kept wave is written in two
-        // halves around a line pass, so that a wave's writes do not queue up
-        // all at once behind those of the other waves.
+        // phi_s while ov is transformed, and the kept waves are written in
+        // groups spaced by the transforms' stages (phi_s in quarters, Y_s in
+        // halves), so that a wave's writes do not queue up all at once behind
+        // those of the other waves.
 #pragma unroll
         for (int r = 0; r < 16; ++r) ov[r] = cmul(v[r], ov[r]);
-        if (full) kstore_half<N, 0>(v, sl.phi(s));
+        if (full) kstore_q<N, 0>(v, sl.phi(s));
         else if (ckpt && s % a.ckK == 0) kstore<N>(v, sl.ckpt(s / a.ckK));
         __builtin_amdgcn_sched_barrier(0);
         nat2mid<WaveGeo<N>, -1>(ov, lds, tab.tw, l, c);
         __builtin_amdgcn_sched_barrier(0);
-        if (full) kstore_half<N, 1>(v, sl.phi(s));
+        if (full) kstore_q<N, 1>(v, sl.phi(s));
+        __builtin_amdgcn_sched_barrier(0);
         relayout<N, COL, MID, ROW, NAT>(ov, lds, l, c);
+        __builtin_amdgcn_sched_barrier(0);
+        if (full) kstore_q<N, 2>(v, sl.phi(s));
+        __builtin_amdgcn_sched_barrier(0);
         nat2mid<WaveGeo<N>, -1>(ov, lds, tab.tw, l, c);
+        __builtin_amdgcn_sched_barrier(0);
+        if (full) kstore_q<N, 3>(v, sl.phi(s));
         apply_h<N, false>(ov, tab, l, c);
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = ov[r];
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
         // write waits for that write too.  Half 0's patch gradient t0 is
         // therefore written only after half 1's reads are issued (measured:
         // gradient launch 0.432 -> 0.417 ms).
-        float2 t0[8];
+        float2 t0[8], t1[4];
         {
             float2 ph[8], ov[8];
 #pragma unroll
@@ -435,18 +442,27 @@ __global__ __launch_bounds__(N * N / 16) void k_gradient(WaveArgs a) {
             }
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                (go + (8 + r) * T)[threadIdx.x] = cmulc(g[8 + r], ph[r]);
+                if (r < 4) t1[r] = cmulc(g[8 + r], ph[r]);
+                else (go + (8 + r) * T)[threadIdx.x] = cmulc(g[8 + r], ph[r]);
                 g[8 + r] = cmulc(g[8 + r], ov[r]);
             }
         }
-        // G^ = F_raw G_phi; half 0's patch gradient is written after the first
-        // line pass, so that the chain's writes come in two spaced halves
+        // G^ = F_raw G_phi; the patch gradient's quarters 0 and 2 (t0[0..3],
+        // t1) are written after the first line pass and quarter 1 after the
+        // exchange (quarter 3 went out before the transform), so that the
+        // chain's writes come in spaced groups
         __builtin_amdgcn_sched_barrier(0);
         nat2mid<WaveGeo<N>, -1>(g, lds, tab.tw, l, c);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) (go + r * T)[threadIdx.x] = t0[r];
+        for (int r = 0; r < 4; ++r) (go + r * T)[threadIdx.x] = t0[r];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) (go + (8 + r) * T)[threadIdx.x] = t1[r];
+        __builtin_amdgcn_sched_barrier(0);
         relayout<N, COL, MID, ROW, NAT>(g, lds, l, c);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 4; r < 8; ++r) (go + r * T)[threadIdx.x] = t0[r];
         nat2mid<WaveGeo<N>, -1>(g, lds, tab.tw, l, c);
         return Y_s;
     };

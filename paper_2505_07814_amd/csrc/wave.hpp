@@ -273,6 +273,11 @@ template <int N, int H, typename T> __device__ __forceinline__ void kstore_half(
 #pragma unroll
     for (int r = 8 * H; r < 8 * H + 8; ++r) (base + r * TT)[threadIdx.x] = v[r];
 }
+template <int N, int Q, typename T> __device__ __forceinline__ void kstore_q(const T (&v)[16], T* base) {
+    constexpr int TT = N * N / 16;
+#pragma unroll
+    for (int r = 4 * Q; r < 4 * Q + 4; ++r) (base + r * TT)[threadIdx.x] = v[r];
+}
 template <int N, typename T> __device__ __forceinline__ void kload(T (&v)[16], const T* base) {
     constexpr int TT = N * N / 16;
 #pragma unroll
