@@ -135,6 +135,14 @@ def rms_phase_error(phase: np.ndarray, truth: np.ndarray, roi: np.ndarray) -> fl
     return float(np.sqrt(np.mean(d * d)))
 
 
+def rms_phase_error_dev(phase: torch.Tensor, truth: torch.Tensor, roi: torch.Tensor) -> float:
+    """rms_phase_error on device tensors (truth float64, roi bool): the same
+    float64 arithmetic, only the scalar is read back."""
+    d = (phase.double() - truth)[roi]
+    d = d - d.mean()
+    return float(torch.sqrt(torch.mean(d * d)))
+
+
 @dataclass
 class EvalCase:
     amp: np.ndarray
@@ -187,9 +195,9 @@ def reconstruct(case: EvalCase, phase0: torch.Tensor, iterations: int, target: f
     """Gradient reconstruction of object amplitude and phase (known probe and
     positions) with ptyr_step: Gaussian amplitude loss, Adam, `batch`
     positions per step in a seeded random order, one iteration = one pass over
-    the scan.  The error is measured after every iteration; the clock includes
-    setup_seconds (the cost of computing phase0) and the per-iteration error
-    read-back."""
+    the scan.  The error is measured after every iteration (on the device, one
+    scalar read back); the clock includes setup_seconds (the cost of computing
+    phase0), the upload of each iteration's order and the error read-back."""
     dev = phase0.device
     lam = synth.wavelength_A(synth.LI_KV)
     n = case.pos.shape[0]
@@ -202,17 +210,20 @@ def reconstruct(case: EvalCase, phase0: torch.Tensor, iterations: int, target: f
                    torch.tensor([synth.LI_DZ], dtype=torch.float32, device=dev))
     rates = dict(amp=lr, phase=lr, probe=0.0, pos=0.0, tilt=0.0, dz=0.0)
     rng = np.random.default_rng(seed)
-    truth = case.phase[0]
-    errors = [rms_phase_error(phase0.cpu().numpy(), truth, case.roi)]
+    truth = torch.from_numpy(np.ascontiguousarray(case.phase[0], np.float64)).to(dev)
+    roi = torch.from_numpy(np.ascontiguousarray(case.roi)).to(dev)
+    step = eng.bind_step(st, case.patterns, rates)
+    errors = [rms_phase_error_dev(st.phase[0], truth, roi)]
     seconds = [setup_seconds]
     hit_it, hit_s = (0, setup_seconds) if errors[0] <= target else (None, None)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter() - setup_seconds
     for it in range(iterations):
-        perm = rng.permutation(n)
+        # one upload of the iteration's order; the batches are views of it
+        perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).to(dev)
         for b in range(0, n - batch + 1, batch):
-            eng.step(st, torch.from_numpy(perm[b:b + batch].astype(np.int32)).to(dev), case.patterns, rates)
-        e = rms_phase_error(st.phase[0].cpu().numpy(), truth, case.roi)      # synchronises
+            step(perm[b:b + batch])
+        e = rms_phase_error_dev(st.phase[0], truth, roi)                       # synchronises
         errors.append(e)
         seconds.append(time.perf_counter() - t0)
         if hit_it is None and e <= target:

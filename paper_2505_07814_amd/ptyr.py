@@ -213,6 +213,36 @@ class Engine:
         return loss
 
 
+    def bind_step(self, state: "AdamState", I_meas_all, lr: dict, betas=(0.9, 0.999), eps=1e-8):
+        """`step` for a loop of updates of one state with fixed rates: the
+        parameters, moments, measured data and rates are checked and marshalled
+        once, and the returned function(idx) checks only idx before calling
+        ptyr_step (the host work per call of `step` is then left out; at small
+        batches it is comparable to the device work).  The function keeps the
+        tensors the state held when it was bound and writes each batch's loss
+        into one device buffer, which it returns."""
+        B_max = self.B_max
+        _need(I_meas_all, "I_meas_all", torch.float32, (state.pos.shape[0], self.N, self.N), self.device)
+        self._check_params(state.amp, state.phase, state.probe, state.pos, state.tilt, state.dz, None, 1)
+        rates = L.LR(*(float(lr.get(k, 0.0)) for k in ("amp", "phase", "probe", "pos", "tilt", "dz")),
+                     float(betas[0]), float(betas[1]), float(eps))
+        prm = state.as_struct()
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        fn, ctx, meas, lptr = self.lib.ptyr_step, self._ctx, _ptr(I_meas_all), _ptr(loss)
+        dev = self.device
+
+        def run(idx):
+            B = idx.numel()
+            if idx.dtype != torch.int32 or idx.device != dev or not idx.is_contiguous() or not 0 < B <= B_max:
+                _need(idx, "idx", torch.int32, (B,), dev)
+                raise ValueError(f"batch of {B} rows, engine B_max {B_max}")
+            prm.step = state.step
+            L.check(fn(ctx, C.byref(prm), C.c_void_p(idx.data_ptr()), B, meas, C.byref(rates), lptr), "ptyr_step")
+            state.step = prm.step
+            self.forward_epoch += 1
+            return loss
+        return run
+
     def constrain(self, amp=None, phase=None, probe=None, rz_sigma=0.0, phase_positive=False,
                   probe_orthogonal=False, kz_beta=0.0, kz_alpha=0.0, kz_dz=0.0):
         """Per-iteration constraints in place (include/ptyr.h, ptyr_constrain):

@@ -336,6 +336,38 @@ def test_adam_step_parity():
         assert err < 1e-3, (k, err)
 
 
+def test_bound_step_matches_step():
+    """Engine.bind_step (parameters and rates marshalled once) gives bitwise
+    the parameters, moments, step counter and losses of Engine.step over
+    three batches, the last given as a view into a larger index tensor, and
+    refuses a batch larger than the engine's."""
+    from paper_2505_07814_amd.ptyr import AdamState, Engine
+    print("bound step N=64 S=3 M=2 B=4", flush=True)
+    w = small(64, 3, 2, 8, 26)
+    c = Case(w)
+    lr = dict(amp=1e-3, phase=2e-3, probe=1e-2, pos=1e-2, tilt=1e-4, dz=1e-1)
+    meas = T(c.meas)
+    eng_a = Engine(64, 2, 3, w.H, w.W, 4, w.dx, c.lam, device=DEV, n_scan=8)
+    eng_b = Engine(64, 2, 3, w.H, w.W, 4, w.dx, c.lam, device=DEV, n_scan=8)
+    sa = AdamState(*[t.clone() for t in c.gpu_args()])
+    sb = AdamState(*[t.clone() for t in c.gpu_args()])
+    step_b = eng_b.bind_step(sb, meas, lr)
+    order = torch.tensor([0, 2, 4, 6, 7, 5, 3, 1, 6, 1, 4, 3], dtype=torch.int32, device=DEV)
+    for k in range(3):
+        idx = order[4 * k:4 * k + 4]
+        la = eng_a.step(sa, idx.clone(), meas, lr)
+        lb = step_b(idx)
+        eng_a.sync()
+        eng_b.sync()
+        assert torch.equal(la, lb), k
+    assert sa.step == sb.step == 3
+    for k in sa.NAMES:
+        assert torch.equal(getattr(sa, k), getattr(sb, k)), k
+        assert torch.equal(sa.m[k], sb.m[k]) and torch.equal(sa.v[k], sb.v[k]), k
+    with pytest.raises(ValueError):
+        step_b(order[:5])
+
+
 @pytest.mark.parametrize("which", ["all", "phase_only", "sparse", "pacbed", "terms"])
 def test_step_split_batch_matches_adjoint_then_adam(which):
     """ptyr_step on a batch of more chains than compute units (two-stream
