@@ -336,6 +336,42 @@ def test_adam_step_parity():
         assert err < 1e-3, (k, err)
 
 
+def test_launch_timing_counts_every_fused_launch():
+    """With timing on, every fused forward / gradient dispatch is timed by
+    start / stop events bound to the dispatch: two steps of a batch that
+    splits over two streams (more chains than compute units) give each
+    kernel's launches, all with positive durations, and results bitwise
+    those of the same steps untimed."""
+    import torch as _t
+    from paper_2505_07814_amd.ptyr import AdamState, Engine
+    print("launch timing N=64 S=3 M=3 B=90", flush=True)
+    w = synth.small_case(N=64, S=3, M=3, B=90, H=64 + 60, W=64 + 70, seed=31)
+    c = Case(w)
+    lr = dict(amp=1e-3, phase=2e-3, probe=1e-2, pos=1e-2, tilt=1e-4, dz=1e-1)
+    meas = T(c.meas)
+    states = []
+    for timed in (True, False):
+        eng = Engine(64, 3, 3, w.H, w.W, 90, w.dx, c.lam, device=DEV, n_scan=90)
+        st = AdamState(*[t.clone() for t in c.gpu_args()])
+        eng.timing(timed)
+        for order in (np.arange(90), np.arange(90)[::-1].copy()):
+            eng.step(st, _t.tensor(order, dtype=_t.int32, device=DEV), meas, lr)
+        eng.sync()
+        if timed:
+            kt = eng.timing_read()
+            eng.timing(False)
+            print(kt, flush=True)
+            split = 270 > _t.cuda.get_device_properties(DEV).multi_processor_count
+            for k in ("forward", "gradient"):
+                ms, n = kt[k]
+                assert n >= 2 and ms > 0.0, (k, kt[k])
+                if split:
+                    assert n >= 4, (k, kt[k])
+        states.append(st)
+    for k in states[0].NAMES:
+        assert _t.equal(getattr(states[0], k), getattr(states[1], k)), k
+
+
 def test_bound_step_matches_step():
     """Engine.bind_step (parameters and rates marshalled once) gives bitwise
     the parameters, moments, step counter and losses of Engine.step over
